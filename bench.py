@@ -1,0 +1,282 @@
+"""Benchmark: setup latency and invocations/s, shared+batched vs plain, on one
+MI355X.
+
+Workload (default): 4 functions, each an 8-layer BF16 MLP of width 4096
+(256 MiB of read-only weights), with 30 % of the 64 KiB block indices holding
+identical content in all four; 64 invocations per function with batch sizes
+uniform on 1..32 and BF16 N(0,1) inputs.  Sources and inputs are resident in
+HBM before the timed region.
+
+One step = the whole path over one batch of 256 requests:
+  shared+batched: fn_register x4 (fingerprint + dedup into the pool),
+                  fn_setup x256, one fn_invoke_batch (grouped GEMM per layer
+                  from a hipGraph), fn_release x256, fn_unregister x4;
+  plain:          fn_register x4 (code only), then per request a private
+                  copy of the weights (fn_setup), one launch sequence
+                  (fn_invoke), fn_release.
+Setup latency of a request = its fn_setup time, plus its function's
+fn_register time for the first request of each function (a cold start).
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "setup p50/p99 ms + invocations/sec, shared+batched vs plain, 1 MI355X"
+HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
+
+
+_T0 = time.time()
+
+
+def log(msg):
+    print(f"[bench {time.time() - _T0:7.1f}s] {msg}", file=sys.stderr, flush=True)
+
+
+def percentile(v, q):
+    """Nearest-rank percentile."""
+    s = sorted(v)
+    k = max(1, int(np.ceil(q / 100.0 * len(s))))
+    return s[k - 1]
+
+
+class Workload:
+    def __init__(self, torch, n_fns=4, layers=8, width=4096, per_fn=64, max_batch=32, seed=0):
+        from paper_2404_14691_amd import synth
+        self.layers, self.width, self.n_fns = layers, width, n_fns
+        w = synth.shared_mlp_bf16_functions(n_fns=n_fns, layers=layers, width=width, share_frac=0.3, seed=seed)
+        self.host_blobs = w.blobs
+        self.dev_blobs = [torch.from_numpy(b.view(np.uint8)).cuda() for b in w.blobs]
+        self.requests = []            # (fn index, batch, row offset)
+        rows = 0
+        for f in range(n_fns):
+            for b in synth.uniform_batches(per_fn, 1, max_batch, seed=seed, stream=f):
+                self.requests.append((f, int(b), rows))
+                rows += int(b)
+        # interleave functions the way concurrent arrivals would
+        order = np.random.default_rng(seed).permutation(len(self.requests))
+        self.requests = [self.requests[i] for i in order]
+        self.rows = rows
+        x = np.concatenate([synth.bf16_inputs(b, width, seed, 100 + i) for i, (_, b, _) in
+                            enumerate(sorted(self.requests, key=lambda r: r[2]))])
+        self.x_host = x
+        self.x = torch.from_numpy(x).cuda()
+        self.y = torch.zeros((rows, width), dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+
+    def io(self, req):
+        _, b, r = req
+        xb, yb = b * self.width * 2, b * self.width * 4
+        return ((self.x.data_ptr() + r * self.width * 2, xb), (self.y.data_ptr() + r * self.width * 4, yb))
+
+
+def register_all(S, ctx, wl):
+    fns, reg_ms = [], []
+    desc = S.mlp_desc(S.SAGE_MLP_BF16, wl.layers, wl.width)
+    for d in wl.dev_blobs:
+        t0 = time.perf_counter()
+        fns.append(S.fn_register(ctx, desc, [S.make_blob(d.data_ptr(), d.numel(), where=S.SAGE_SRC_DEVICE)]))
+        reg_ms.append((time.perf_counter() - t0) * 1e3)
+    return fns, reg_ms
+
+
+def shared_step(S, ctx, wl):
+    io = S.SAGE_IO_DEVICE_IN | S.SAGE_IO_DEVICE_OUT
+    fns, reg_ms = register_all(S, ctx, wl)
+    setup_ms, invs, ins, outs = [], [], [], []
+    seen = set()
+    for req in wl.requests:
+        f = req[0]
+        t0 = time.perf_counter()
+        invs.append(S.fn_setup(ctx, fns[f], req[1]))
+        dt = (time.perf_counter() - t0) * 1e3
+        if f not in seen:
+            dt += reg_ms[f]
+            seen.add(f)
+        setup_ms.append(dt)
+        i, o = wl.io(req)
+        ins.append(i)
+        outs.append(o)
+    S.fn_invoke_batch(ctx, invs, ins, outs, io)
+    for inv in invs:
+        S.fn_release(ctx, inv)
+    stats = S.sage_get_stats(ctx)
+    for f in fns:
+        S.fn_unregister(ctx, f)
+    return setup_ms, stats
+
+
+def plain_step(S, ctx, wl):
+    io = S.SAGE_IO_DEVICE_IN | S.SAGE_IO_DEVICE_OUT
+    fns, reg_ms = register_all(S, ctx, wl)
+    setup_ms = []
+    seen = set()
+    for req in wl.requests:
+        f = req[0]
+        t0 = time.perf_counter()
+        inv = S.fn_setup(ctx, fns[f], req[1])
+        dt = (time.perf_counter() - t0) * 1e3
+        if f not in seen:
+            dt += reg_ms[f]
+            seen.add(f)
+        setup_ms.append(dt)
+        i, o = wl.io(req)
+        S.fn_invoke(ctx, inv, i, o, io)
+        S.fn_release(ctx, inv)
+    for f in fns:
+        S.fn_unregister(ctx, f)
+    return setup_ms
+
+
+def timed(torch, fn, steps):
+    out = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out.append(fn())
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0), out
+
+
+def cpu_baseline(wl, n_inv=8, seed=0):
+    """The oracle on the host: one function's fingerprints + dedup map and
+    `n_inv` of its invocations in float64; extrapolated to one step."""
+    from oracle import dedup as OD
+    from oracle import fingerprint as OF
+    from oracle import mlp as OM
+    t0 = time.perf_counter()
+    OF.fp64k_blob(wl.host_blobs[0])
+    OD.partition_dict([wl.host_blobs[0]], 65536)
+    t_reg = time.perf_counter() - t0
+    W = OM.bf16_to_f64(wl.host_blobs[0]).reshape(wl.layers, wl.width, wl.width)
+    reqs = [r for r in wl.requests if r[0] == 0][:n_inv]
+    t0 = time.perf_counter()
+    for _, b, r in reqs:
+        OM.mlp_forward(OM.bf16_to_f64(wl.x_host[r:r + b]), W)
+    t_inv = (time.perf_counter() - t0) / len(reqs)
+    step_s = wl.n_fns * t_reg + len(wl.requests) * t_inv
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    return {"value": len(wl.requests) / step_s, "unit": "invocations/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"fingerprint + dedup map of 1 of {wl.n_fns} functions (256 MiB) and {len(reqs)} of its "
+                      f"invocations in float64 numpy; step time = {wl.n_fns} x registration + "
+                      f"{len(wl.requests)} x mean invocation ({step_s:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (this path has no "
+              f"multi-GPU form; see DESIGN.md for how it would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2404_14691_amd import sage as S
+
+    log("generating workload")
+    wl = Workload(torch)
+    log(f"workload ready: {len(wl.requests)} requests, {wl.rows} rows")
+    cfg = S.sage_config_default()
+    cfg.pool_budget_bytes = 8 << 30
+    ctx = S.sage_open(0, cfg)
+    pcfg = S.sage_config_default()
+    pcfg.share = 0
+    pcfg.pool_budget_bytes = 1 << 20
+    pctx = S.sage_open(0, pcfg)
+    try:
+        for i in range(args.warmup):
+            shared_step(S, ctx, wl)
+            log(f"warmup step {i} done")
+        plain_step(S, pctx, wl)
+        log("plain warmup done")
+        # ---- timed: shared + batched, with per-kernel device timing
+        S.sage_timing_reset(ctx)
+        S.sage_timing_enable(ctx, True)
+        elapsed, res = timed(torch, lambda: shared_step(S, ctx, wl), args.steps)
+        S.sage_timing_enable(ctx, False)
+        log(f"shared timed: {elapsed * 1e3 / args.steps:.2f} ms/step")
+        setup_shared = [x for r in res for x in r[0]]
+        stats = res[-1][1]
+        g_ms, g_n = S.sage_timing_get(ctx, "ggemm_bf16")
+        f_ms, f_n = S.sage_timing_get(ctx, "fp64k")
+        b_ms, b_n = S.sage_timing_get(ctx, "blkcopy")
+        # ---- plain
+        p_elapsed, p_res = timed(torch, lambda: plain_step(S, pctx, wl), args.plain_steps)
+        setup_plain = [x for r in p_res for x in r]
+        log(f"plain timed: {p_elapsed * 1e3 / args.plain_steps:.2f} ms/step")
+    finally:
+        S.sage_close(ctx)
+        S.sage_close(pctx)
+
+    n_req = len(wl.requests)
+    ms_step = elapsed / args.steps * 1e3
+    value = n_req * args.steps / elapsed
+    plain_value = n_req * args.plain_steps / p_elapsed
+    flops_launch = 2.0 * wl.rows * wl.width * wl.width
+    gemm_avg_ms = g_ms / max(g_n, 1)
+    achieved = flops_launch / (gemm_avg_ms * 1e-3) / 1e12
+    fp_bytes = (sum(b.numel() for b in wl.dev_blobs) + 8 * sum(b.numel() for b in wl.dev_blobs) // 65536)
+    line = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "invocations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {
+            "workload": "sharing: 4 functions x 8-layer BF16 MLP width 4096 (256 MiB read-only each, 30% of "
+                        "64 KiB blocks identical across functions), 64 invocations per function, batch U[1,32], "
+                        "sources and inputs resident in HBM",
+            "requests_per_step": n_req, "rows_per_step": wl.rows},
+        "setup_ms": {
+            "shared": {"p50": round(percentile(setup_shared, 50), 4), "p99": round(percentile(setup_shared, 99), 3)},
+            "plain": {"p50": round(percentile(setup_plain, 50), 4), "p99": round(percentile(setup_plain, 99), 3)}},
+        "plain": {"value": round(plain_value, 2), "ms_per_step": round(p_elapsed / args.plain_steps * 1e3, 3),
+                  "steps": args.plain_steps},
+        "speedup_vs_plain": round(value / plain_value, 2),
+        "pool": {"logical_bytes": stats["logical_bytes"], "unique_bytes": stats["unique_bytes"],
+                 "shared_bytes": stats["shared_bytes"], "private_bytes": stats["private_bytes"]},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / BF16_PEAK_TFLOPS, 4), "traffic": None,
+                     "kernel": "ggemm_bf16", "avg_launch_ms": round(gemm_avg_ms, 5),
+                     "flop_per_launch": flops_launch},
+        "kernels": {
+            "fp64k": {"avg_ms": round(f_ms / max(f_n, 1), 5), "launches": f_n,
+                      "GB/s": round(fp_bytes * args.steps / max(f_ms * 1e-3, 1e-12) / 1e9, 1)},
+            "blkcopy": {"avg_ms": round(b_ms / max(b_n, 1), 5), "launches": b_n},
+            "ggemm_bf16": {"avg_ms": round(gemm_avg_ms, 5), "launches": g_n}},
+    }
+    if not args.no_cpu:
+        log("cpu baseline (oracle) ...")
+        line["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

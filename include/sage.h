@@ -1,0 +1,258 @@
+/*
+ * sage.h -- C ABI of the function-setup library for one AMD MI355X (gfx950).
+ *
+ * The library runs many invocations of the same GPU functions with fast setup
+ * and shared read-only memory, after "Towards Fast Setup and High Throughput
+ * of GPU Serverless Computing" (arXiv 2404.14691):
+ *
+ *  - parallelized function setup (section "Parallelized Function Setup"):
+ *    a function's read-only data is known from its request before it runs,
+ *    so it is moved to the GPU while the function's code is loaded;
+ *  - sharing-based memory management (section "Sharing-based Memory
+ *    Management"): read-only data is loaded once and used by every
+ *    invocation.  Here sharing works on 64 KiB blocks: each block is
+ *    fingerprinted on the GPU and identical blocks, also across functions,
+ *    occupy one slot of a refcounted pool.
+ *
+ * Conventions
+ *  - Every call returns sage_status; no C++ exception crosses this boundary.
+ *    sage_last_error() returns a message for the calling thread's last
+ *    failure (valid until that thread's next call).
+ *  - Pointers are plain host or device addresses.  "Device" means memory of
+ *    the context's GPU (hipMalloc, or a torch tensor on it).  Every
+ *    device address passed in must be 16-byte aligned.
+ *  - Handles (sage_fn, sage_inv) are never reused; a released or
+ *    unregistered handle gives SAGE_ESTATE / SAGE_ENOTFOUND.
+ *  - One sage_ctx per GPU.  Its calls are serialised by an internal mutex
+ *    and may come from any thread.
+ */
+#ifndef SAGE_H
+#define SAGE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sage_ctx sage_ctx;
+typedef uint64_t sage_fn;
+typedef uint64_t sage_inv;
+
+typedef enum {
+  SAGE_OK = 0,
+  SAGE_EINVAL = 1,    /* bad argument, size or layout */
+  SAGE_ENOMEM = 2,    /* admission failed: not enough pool or device memory */
+  SAGE_EBUSY = 3,     /* object still in use (e.g. unregister with live setups) */
+  SAGE_ENOTFOUND = 4, /* unknown handle */
+  SAGE_ESTATE = 5,    /* handle in the wrong state (released twice, ...) */
+  SAGE_EHIP = 6,      /* a HIP runtime call failed */
+  SAGE_EIO = 7        /* code object missing or unreadable */
+} sage_status;
+
+/* Data access type a developer declares for each datum (section "Read-only
+ * Memory Sharing": Data.Type is ReadOnly or Writable).  Only read-only blobs
+ * are registered; writable data is passed to each invocation. */
+typedef enum { SAGE_RO = 0, SAGE_RW = 1 } sage_access;
+
+/* Where a blob's bytes live. */
+typedef enum { SAGE_SRC_HOST = 0, SAGE_SRC_DEVICE = 1 } sage_where;
+
+/* One datum of a request (section "Parallelizing data and context": the
+ * Request lists the data to load, each with a key naming its source).
+ * src/nbytes name the bytes; they must stay valid and unchanged until
+ * fn_unregister, because evicted blocks are reloaded from them.  Host
+ * sources may be pageable or from sage_host_alloc (then copied by DMA
+ * without staging). */
+typedef struct {
+  const void* src;
+  size_t nbytes;
+  uint32_t access; /* sage_access; must be SAGE_RO for fn_register */
+  uint32_t where;  /* sage_where */
+  uint64_t key;    /* caller's name for the datum, kept for diagnostics */
+} sage_blob;
+
+/* Function bodies the library can run. */
+typedef enum {
+  SAGE_MLP_F32 = 1,     /* ReLU MLP, FP32 weights/activations */
+  SAGE_MLP_BF16 = 2,    /* ReLU MLP, BF16 weights/activations, FP32 accumulate, FP32 output */
+  SAGE_STENCIL7_F32 = 3 /* 7-point Jacobi relaxation with a read-only coefficient grid */
+} sage_kind;
+
+/* MLP: one RO blob, weights [layers][width][width] ([out][in]) row-major,
+ * width a power of two >= 128 whose row (width * element size) fits in
+ * 64 KiB, so every weight row lies inside one block.
+ *   H_0 = X, H_l = relu(H_{l-1} W_l^T) for l < layers, Y = H_{layers-1} W_L^T.
+ *   Input X [batch][width] (FP32 or BF16 bits), output Y [batch][width] FP32.
+ * STENCIL7: one RO blob, c[nz][ny][nx] FP32, nx a power of two with
+ *   nx*4 <= 65536, all extents >= 3.  Input u0 [batch][nz][ny][nx] FP32,
+ *   output u after `sweeps` Jacobi sweeps:
+ *   u'_p = u_p + c_p * (avg of 6 face neighbours - u_p) on interior cells,
+ *   boundary cells unchanged. */
+typedef struct {
+  uint32_t kind; /* sage_kind */
+  uint32_t layers, width;
+  uint32_t nx, ny, nz, sweeps;
+} sage_fn_desc;
+
+typedef struct {
+  size_t ring_slots;         /* pinned staging slots for host->device (default 8; 1 = no pipelining) */
+  size_t chunk_bytes;        /* bytes per staging slot, multiple of 64 KiB (default 8 MiB) */
+  uint32_t streams;          /* copy/fingerprint streams (default 4) */
+  uint32_t fill_threads;     /* host threads copying pageable sources into staging (default 4) */
+  uint32_t inflight_groups;  /* grouped launches that may run concurrently (default 4) */
+  uint32_t share;            /* 1 (default): shared block pool; 0: private copy per invocation */
+  uint32_t batch;            /* 1 (default): grouped launches replayed from hipGraphs; 0: eager */
+  uint32_t serial_setup;     /* 1: load code and move data one after the other (A/B switch) */
+  size_t pool_budget_bytes;  /* pool capacity; 0 = half of free device memory at open */
+  const char* tune_cache;    /* autotuner cache file, or NULL for in-memory only */
+} sage_config;
+
+typedef struct {
+  uint64_t logical_bytes;   /* sum of registered RO blob sizes */
+  uint64_t unique_bytes;    /* sum of lengths of all live classes */
+  uint64_t shared_bytes;    /* bytes of blocks in classes with >= 2 member blocks */
+  uint64_t private_bytes;   /* bytes of blocks in singleton classes */
+  uint64_t resident_bytes;  /* sum of lengths of resident classes */
+  uint64_t resident_slots;
+  uint64_t budget_slots;
+  uint64_t classes;         /* live classes */
+  uint64_t h2d_bytes;       /* RO bytes moved from sources into the device (pool or private copies) */
+  uint64_t refcount_sum;    /* sum of class references */
+  uint64_t live_setups;
+  uint64_t evictions;
+  uint64_t reloads;         /* classes reloaded by fn_setup */
+  uint64_t registrations;
+  uint64_t invocations;
+  uint64_t verify_mismatches; /* fingerprint hits whose bytes differed */
+  uint64_t workspace_bytes; /* device bytes held for invocation workspaces */
+} sage_stats;
+
+/* ----------------------------------------------------------------- context */
+void sage_config_default(sage_config* cfg);
+
+/* Open the library on `device` (HIP ordinal).  Loads the runtime kernels and
+ * allocates the staging ring; roughly SageInit() of the paper's programming
+ * model (section "Programming Model").  cfg may be NULL for defaults. */
+sage_status sage_open(int device, const sage_config* cfg, sage_ctx** out);
+/* Wait for all work, free every resource.  Live handles become invalid. */
+sage_status sage_close(sage_ctx* ctx);
+const char* sage_last_error(void);
+
+/* Pinned host memory (hipHostMalloc) owned by the context; sources here are
+ * copied to the device by DMA without staging. NULL on failure. */
+void* sage_host_alloc(sage_ctx* ctx, size_t nbytes);
+void sage_host_free(sage_ctx* ctx, void* p);
+
+/* --------------------------------------------------------------- functions */
+/* Register a function and its read-only data (sections "Parallelizing data
+ * and context" and "Read-only Memory Sharing").  The code object of the
+ * kind is loaded on one thread while the data moves on another: chunks of
+ * `chunk_bytes` go through the pinned ring to the device on several streams,
+ * each 64 KiB block is fingerprinted there, and blocks whose bytes are
+ * already in the pool join that slot (verified byte for byte); the others are
+ * copied into new slots.  With share=0 only the function record is made and
+ * the data is copied privately at each fn_setup.
+ * Returns when the data is in place.  Blobs must be SAGE_RO and match the
+ * kind's layout (see sage_fn_desc); sources stay borrowed until
+ * fn_unregister.  Errors: EINVAL (layout), ENOMEM (pool full of referenced
+ * blocks; the function is not registered), EIO (code object), EHIP. */
+sage_status fn_register(sage_ctx* ctx, const sage_fn_desc* desc, const sage_blob* blobs,
+                        size_t n_blobs, sage_fn* out);
+
+/* Drop a function.  EBUSY while it has live setups.  Blocks no other
+ * registered function uses leave the pool. */
+sage_status fn_unregister(sage_ctx* ctx, sage_fn fn);
+
+/* Make one invocation of `fn` with `batch` rows (MLP) or fields (stencil)
+ * runnable; the analogue of SageLoadToGPU() (section "Programming of
+ * Function Handle").  Admission: the function's evicted blocks are reloaded
+ * (evicting unreferenced blocks of other functions, least recently released
+ * first) and each distinct block of the function gains one reference.  With
+ * share=0 the read-only data is copied into a private buffer instead.
+ * Errors: ENOMEM (cannot admit; nothing changed), ENOTFOUND, EINVAL. */
+sage_status fn_setup(sage_ctx* ctx, sage_fn fn, uint32_t batch, sage_inv* out);
+
+/* Flags for fn_invoke / fn_invoke_batch: which I/O buffers are device memory. */
+#define SAGE_IO_DEVICE_IN 1u
+#define SAGE_IO_DEVICE_OUT 2u
+
+/* Run one set-up invocation: in = X / u0 as described in sage_fn_desc,
+ * out = Y / u.  The body waits for the function's data (the kernel-executor
+ * readiness check, section "Ensuring Function Correctness").  Blocking.
+ * in_bytes/out_bytes must equal the sizes the kind implies (EINVAL). */
+sage_status fn_invoke(sage_ctx* ctx, sage_inv inv, const void* in, size_t in_bytes, void* out,
+                      size_t out_bytes, uint32_t io_flags);
+
+/* Run n set-up invocations as one group: MLP invocations of the same width
+ * and depth run as one grouped GEMM per layer over all their rows (replayed
+ * from a captured hipGraph when batch=1); stencil invocations of one
+ * function run one sweep launch for all fields.  Invocations of different
+ * kinds are split into several groups.  Blocking.  Each output equals the
+ * invocation's fn_invoke output. */
+sage_status fn_invoke_batch(sage_ctx* ctx, size_t n, const sage_inv* invs, const void* const* in,
+                            const size_t* in_bytes, void* const* out, const size_t* out_bytes,
+                            uint32_t io_flags);
+
+/* End an invocation: drop its block references (blocks reaching zero stay
+ * resident until evicted: first exit stage, section "Multi-stage Resource
+ * Exit") and free its private buffers.  ESTATE if already released. */
+sage_status fn_release(sage_ctx* ctx, sage_inv inv);
+
+/* ---------------------------------------------------------- introspection */
+sage_status sage_get_stats(sage_ctx* ctx, sage_stats* out);
+/* Fingerprint of each of the function's blocks, in block order (n = count). */
+sage_status sage_fn_fingerprints(sage_ctx* ctx, sage_fn fn, uint64_t* out, size_t n);
+/* Per block: class id, pool slot (UINT32_MAX when evicted) and references. */
+sage_status sage_fn_block_info(sage_ctx* ctx, sage_fn fn, uint32_t* cls, uint32_t* slot,
+                               uint32_t* refs, size_t n);
+/* Number of blocks of a function. */
+sage_status sage_fn_block_count(sage_ctx* ctx, sage_fn fn, size_t* out);
+/* Copy one 64 KiB pool slot to host memory. */
+sage_status sage_read_slot(sage_ctx* ctx, uint32_t slot, void* host64k);
+
+/* ------------------------------------------------------ kernel entry points
+ * The data-movement kernels of the path, callable directly on device
+ * buffers.  stream is a hipStream_t (NULL = the context's own stream); the
+ * calls are asynchronous on it. */
+
+/* FP64K-v1 fingerprints of the ceil(nbytes/65536) blocks at dev (the last
+ * block may be short) into dev_out[]. */
+sage_status sage_fingerprint(sage_ctx* ctx, const void* dev, size_t nbytes, uint64_t* dev_out,
+                             void* stream);
+
+/* Block operations, one per 64 KiB block: COPY src -> dst, or VERIFY that the
+ * len bytes at src and dst are equal (result[i] = 1 when they differ). */
+#define SAGE_OP_COPY 0u
+#define SAGE_OP_VERIFY 1u
+typedef struct {
+  uint64_t src;
+  uint64_t dst;
+  uint32_t len; /* 1..65536 */
+  uint32_t op;  /* SAGE_OP_* */
+} sage_blk_op;
+sage_status sage_blkcopy(sage_ctx* ctx, const sage_blk_op* dev_ops, size_t n_ops,
+                         uint32_t* dev_result, void* stream);
+
+/* --------------------------------------------------------------- timing
+ * Per-kernel device time measured with HIP events on the stream each launch
+ * is issued on, accumulated while timing is on.  Names: "fp64k", "blkcopy",
+ * "ggemm_bf16", "mlp_f32", "stencil7".  A graph replay of L layers counts as
+ * L launches of its kernel. */
+sage_status sage_timing_enable(sage_ctx* ctx, int on);
+sage_status sage_timing_get(sage_ctx* ctx, const char* kernel, double* total_ms, uint64_t* launches);
+sage_status sage_timing_reset(sage_ctx* ctx);
+
+/* --------------------------------------------------------------- self test
+ * Host-only check of the setup orchestrator: runs its two branches with
+ * stand-in stages that sleep (code load = load_ms; data = host_ms then
+ * copy_ms per the data branch) and reports the measured setup time.  With
+ * serial != 0 the branches run one after the other.  Needs no GPU. */
+sage_status sage_selftest_setup_overlap(double load_ms, double host_ms, double copy_ms, int serial,
+                                        double* measured_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SAGE_H */

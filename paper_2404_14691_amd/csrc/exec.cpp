@@ -1,0 +1,458 @@
+// Execution of function bodies: grouped MLP launches (one persistent kernel
+// per layer, replayed from a captured hipGraph), batched stencil sweeps, and
+// the tile-shape autotuner.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+
+#include "internal.h"
+
+namespace sage {
+
+size_t in_elem_size(const sage_fn_desc& d) { return d.kind == SAGE_MLP_BF16 ? 2 : 4; }
+
+uint64_t ro_bytes_for(const sage_fn_desc& d) {
+  if (d.kind == SAGE_STENCIL7_F32) return (uint64_t)d.nx * d.ny * d.nz * 4;
+  return (uint64_t)d.layers * d.width * d.width * in_elem_size(d);
+}
+
+size_t in_bytes_for(const sage_fn_desc& d, uint32_t batch) {
+  if (d.kind == SAGE_STENCIL7_F32) return (size_t)batch * d.nx * d.ny * d.nz * 4;
+  return (size_t)batch * d.width * in_elem_size(d);
+}
+
+size_t out_bytes_for(const sage_fn_desc& d, uint32_t batch) {
+  if (d.kind == SAGE_STENCIL7_F32) return (size_t)batch * d.nx * d.ny * d.nz * 4;
+  return (size_t)batch * d.width * 4;
+}
+
+// ------------------------------------------------------------- tile shapes
+struct TileShape {
+  const char* name;
+  uint32_t bm, bn, occupancy;
+};
+static const TileShape kShapes[] = {
+    {"ggemm_bf16_16x64", 16, 64, 2},    {"ggemm_bf16_32x64", 32, 64, 2},
+    {"ggemm_bf16_32x128", 32, 128, 2},  {"ggemm_bf16_64x128", 64, 128, 2},
+    {"ggemm_bf16_128x128", 128, 128, 2}, {"ggemm_bf16_256x128", 256, 128, 1},
+    {"ggemm_bf16_128x256", 128, 256, 1},
+};
+
+static const TileShape& shape_of(const std::string& name) {
+  for (const auto& s : kShapes)
+    if (name == s.name) return s;
+  fail(SAGE_EINVAL, "unknown tile shape %s", name.c_str());
+}
+
+// ------------------------------------------------------------------ flights
+constexpr uint32_t kMaxGroups = 256;
+constexpr size_t kMetaGroupsOff = 16;
+constexpr size_t kMetaTabOff = kMetaGroupsOff + kMaxGroups * sizeof(GemmGroup);
+
+void flights_init(Ctx& c) {
+  c.flights.resize(std::max<uint32_t>(1, c.cfg.inflight_groups));
+  for (Flight& F : c.flights) {
+    HIPX(hipStreamCreateWithFlags(&F.s, hipStreamNonBlocking));
+    HIPX(hipEventCreateWithFlags(&F.done, hipEventDisableTiming));
+  }
+}
+
+static void drop_graphs(Flight& F) {
+  for (auto& kv : F.graphs) (void)hipGraphExecDestroy(kv.second);
+  F.graphs.clear();
+}
+
+void flights_destroy(Ctx& c) {
+  for (Flight& F : c.flights) {
+    (void)hipStreamSynchronize(F.s);
+    drop_graphs(F);
+    (void)hipFree(F.d_meta);
+    (void)hipHostFree(F.h_meta);
+    (void)hipFree(F.ws);
+    (void)hipFree(F.d_in);
+    (void)hipHostFree(F.h_in);
+    (void)hipFree(F.d_out);
+    (void)hipHostFree(F.h_out);
+    (void)hipEventDestroy(F.done);
+    (void)hipStreamDestroy(F.s);
+  }
+  c.flights.clear();
+}
+
+static size_t grow(size_t need) {
+  size_t cap = 1u << 20;
+  while (cap < need) cap <<= 1;
+  return cap;
+}
+
+// Device/pinned buffer pair grown to at least `need` bytes; returns true
+// when it moved (graphs holding the old address must be re-captured).
+static bool ensure(uint8_t** d, uint8_t** h, size_t* cap, size_t need) {
+  if (*cap >= need) return false;
+  const size_t n = grow(need);
+  if (*d) HIPX(hipFree(*d));
+  if (h && *h) HIPX(hipHostFree(*h));
+  *d = nullptr;
+  HIPX(hipMalloc((void**)d, n));
+  if (h) HIPX(hipHostMalloc((void**)h, n, hipHostMallocDefault));
+  *cap = n;
+  return true;
+}
+
+static int take_flight(Ctx& c) {
+  const int f = (int)(c.next_flight++ % c.flights.size());
+  if (c.flights[f].busy) finish_flight(c, f);
+  return f;
+}
+
+void finish_flight(Ctx& c, int f) {
+  Flight& F = c.flights[f];
+  if (!F.busy) return;
+  HIPX(hipEventSynchronize(F.done));
+  for (auto& d : F.deliver) std::memcpy(d.first, F.h_out + d.second.first, d.second.second);
+  F.deliver.clear();
+  F.busy = false;
+  c.timer.collect();
+}
+
+static void launch_kernel(hipFunction_t k, uint32_t grid, hipStream_t s, const GemmHdr* hdr, const GemmGroup* groups,
+                          const LayerArgs& la) {
+  const GemmHdr* h = hdr;
+  const GemmGroup* g = groups;
+  LayerArgs a = la;
+  void* params[] = {&h, &g, &a};
+  HIPX(hipModuleLaunchKernel(k, grid, 1, 1, 256, 1, 1, 0, s, params, nullptr));
+}
+
+// ---------------------------------------------------------------- MLP group
+// All calls share kind, width and depth.  Rows of the calls of one weight
+// table (one function, or one private copy) are packed into one group; the
+// launch covers all groups with one tile list.  Layer 0 reads the inputs
+// through a row table, the last layer writes the outputs through another;
+// hidden layers ping-pong in the flight's workspace.
+int launch_mlp_group(Ctx& c, const std::vector<Call>& calls, uint32_t io) {
+  const sage_fn_desc& d = calls[0].inv->fn->d;
+  const uint32_t W = d.width, L = d.layers;
+  const bool bf16 = d.kind == SAGE_MLP_BF16;
+  const size_t es_in = bf16 ? 2 : 4, es_act = es_in;
+
+  // groups by weight table, first-appearance order
+  std::vector<const uint64_t*> tabs;
+  std::vector<std::vector<size_t>> members;
+  for (size_t i = 0; i < calls.size(); i++) {
+    const uint64_t* t = calls[i].inv->table();
+    size_t g = 0;
+    while (g < tabs.size() && tabs[g] != t) g++;
+    if (g == tabs.size()) {
+      tabs.push_back(t);
+      members.emplace_back();
+    }
+    members[g].push_back(i);
+  }
+  if (tabs.size() > kMaxGroups) fail(SAGE_EINVAL, "more than %u weight tables in one launch", kMaxGroups);
+  uint32_t M = 0;
+  for (const Call& cl : calls) M += cl.inv->batch;
+
+  std::string kname;
+  uint32_t bm = 8, bn = 8, occ = 4;
+  if (bf16) {
+    kname = tuned_kernel(c, W, M);
+    const TileShape& ts = shape_of(kname);
+    if (W % ts.bn) fail(SAGE_EINVAL, "tile %s does not divide width %u", kname.c_str(), W);
+    bm = ts.bm;
+    bn = ts.bn;
+    occ = ts.occupancy;
+  } else {
+    kname = "mlp_f32_layer";
+  }
+
+  const int fi = take_flight(c);
+  Flight& F = c.flights[fi];
+  bool moved = false;
+  moved |= ensure(&F.d_meta, &F.h_meta, &F.meta_cap, kMetaTabOff + (size_t)M * 16);
+  moved |= ensure(&F.ws, nullptr, &F.ws_cap, 2 * (size_t)M * W * es_act);
+  // graphs hold meta/workspace addresses and the row capacity
+  const size_t rows_cap = (F.meta_cap - kMetaTabOff) / 16;
+  if (moved) drop_graphs(F);
+  const bool host_in = !(io & SAGE_IO_DEVICE_IN), host_out = !(io & SAGE_IO_DEVICE_OUT);
+  if (host_in) ensure(&F.d_in, &F.h_in, &F.in_cap, (size_t)M * W * es_in);
+  if (host_out) ensure(&F.d_out, &F.h_out, &F.out_cap, (size_t)M * W * 4);
+
+  GemmHdr* hdr = reinterpret_cast<GemmHdr*>(F.h_meta);
+  GemmGroup* grp = reinterpret_cast<GemmGroup*>(F.h_meta + kMetaGroupsOff);
+  uint64_t* in_tab = reinterpret_cast<uint64_t*>(F.h_meta + kMetaTabOff);
+  uint64_t* out_tab = in_tab + rows_cap;
+  uint32_t row = 0, tiles = 0;
+  F.deliver.clear();
+  for (size_t g = 0; g < tabs.size(); g++) {
+    GemmGroup& G = grp[g];
+    G.wtab = (uint64_t)tabs[g];
+    G.row0 = row;
+    G.tile_start = tiles;
+    G.pad = 0;
+    for (size_t i : members[g]) {
+      const Call& cl = calls[i];
+      const uint32_t b = cl.inv->batch;
+      for (uint32_t r = 0; r < b; r++) {
+        const uint32_t R = row + r;
+        in_tab[R] = host_in ? (uint64_t)(F.d_in + (size_t)R * W * es_in)
+                            : (uint64_t)((const uint8_t*)cl.in + (size_t)r * W * es_in);
+        out_tab[R] = host_out ? (uint64_t)(F.d_out + (size_t)R * W * 4)
+                              : (uint64_t)((uint8_t*)cl.out + (size_t)r * W * 4);
+      }
+      if (host_in) std::memcpy(F.h_in + (size_t)row * W * es_in, cl.in, (size_t)b * W * es_in);
+      if (host_out) F.deliver.push_back({cl.out, {(size_t)row * W * 4, (size_t)b * W * 4}});
+      row += b;
+    }
+    G.m = row - G.row0;
+    tiles += bf16 ? ((G.m + bm - 1) / bm) * (W / bn) : W / 8;
+  }
+  hdr->n_groups = (uint32_t)tabs.size();
+  hdr->total_tiles = tiles;
+  hdr->total_rows = M;
+  hdr->pad = 0;
+
+  hipStream_t s = F.s;
+  // readiness gate: the body waits until every function's data is in place
+  for (const Call& cl : calls) HIPX(hipStreamWaitEvent(s, cl.inv->fn->ready, 0));
+  HIPX(hipMemcpyAsync(F.d_meta, F.h_meta, kMetaGroupsOff + tabs.size() * sizeof(GemmGroup), hipMemcpyHostToDevice, s));
+  HIPX(hipMemcpyAsync(F.d_meta + kMetaTabOff, in_tab, (size_t)M * 8, hipMemcpyHostToDevice, s));
+  HIPX(hipMemcpyAsync(F.d_meta + kMetaTabOff + rows_cap * 8, out_tab, (size_t)M * 8, hipMemcpyHostToDevice, s));
+  if (host_in) HIPX(hipMemcpyAsync(F.d_in, F.h_in, (size_t)M * W * es_in, hipMemcpyHostToDevice, s));
+
+  Module* mod = calls[0].inv->fn->mod;
+  hipFunction_t kfn = mod->get(kname.c_str());
+  const uint32_t grid = (uint32_t)c.cus * occ;
+  const GemmHdr* d_hdr = reinterpret_cast<const GemmHdr*>(F.d_meta);
+  const GemmGroup* d_grp = reinterpret_cast<const GemmGroup*>(F.d_meta + kMetaGroupsOff);
+  const uint64_t* d_in_tab = reinterpret_cast<const uint64_t*>(F.d_meta + kMetaTabOff);
+  const uint64_t* d_out_tab = d_in_tab + rows_cap;
+  const size_t half = F.ws_cap / 2;
+  auto layer_args = [&](uint32_t l) {
+    LayerArgs la{};
+    la.a_tab = l == 0 ? d_in_tab : nullptr;
+    la.a_base = F.ws + ((l + 1) % 2) * half;
+    la.c_tab = l == L - 1 ? d_out_tab : nullptr;
+    la.c_base = F.ws + (l % 2) * half;
+    la.w_off = (uint64_t)l * W * W * es_in;
+    la.N = W;
+    la.K = W;
+    la.flags = (l + 1 < L ? kRelu : 0u) | (l + 1 == L ? kOutF32 : 0u);
+    return la;
+  };
+  const char* tname = bf16 ? "ggemm_bf16" : "mlp_f32";
+  const int tok = c.timer.start(tname, s, L);
+  if (c.cfg.batch) {
+    const GraphKey key{kname, L, W};
+    auto it = F.graphs.find(key);
+    if (it == F.graphs.end()) {
+      hipStream_t cap = s;
+      HIPX(hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed));
+      for (uint32_t l = 0; l < L; l++) launch_kernel(kfn, grid, cap, d_hdr, d_grp, layer_args(l));
+      hipGraph_t g = nullptr;
+      HIPX(hipStreamEndCapture(cap, &g));
+      hipGraphExec_t ex = nullptr;
+      HIPX(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+      HIPX(hipGraphDestroy(g));
+      it = F.graphs.emplace(key, ex).first;
+    }
+    HIPX(hipGraphLaunch(it->second, s));
+  } else {
+    for (uint32_t l = 0; l < L; l++) launch_kernel(kfn, grid, s, d_hdr, d_grp, layer_args(l));
+  }
+  c.timer.stop(tok, s);
+  if (host_out) HIPX(hipMemcpyAsync(F.h_out, F.d_out, (size_t)M * W * 4, hipMemcpyDeviceToHost, s));
+  HIPX(hipEventRecord(F.done, s));
+  F.busy = true;
+  return fi;
+}
+
+// ------------------------------------------------------------ stencil group
+// All calls share one coefficient table.  Every field of every call is
+// swept together; the sweep's output goes to the call's output buffer on
+// the last sweep and alternates with a scratch field before it.
+int launch_stencil_group(Ctx& c, const std::vector<Call>& calls, uint32_t io) {
+  const sage_fn_desc& d = calls[0].inv->fn->d;
+  const uint64_t cells = (uint64_t)d.nx * d.ny * d.nz, fbytes = cells * 4;
+  const uint32_t S = d.sweeps;
+  uint32_t nf = 0;
+  for (const Call& cl : calls) nf += cl.inv->batch;
+  const bool host_in = !(io & SAGE_IO_DEVICE_IN), host_out = !(io & SAGE_IO_DEVICE_OUT);
+
+  const int fi = take_flight(c);
+  Flight& F = c.flights[fi];
+  hipStream_t s = F.s;
+  for (const Call& cl : calls) HIPX(hipStreamWaitEvent(s, cl.inv->fn->ready, 0));
+  ensure(&F.d_meta, &F.h_meta, &F.meta_cap, (size_t)std::max<uint32_t>(S, 1) * 2 * nf * 8);
+  uint64_t* tab = reinterpret_cast<uint64_t*>(F.h_meta);
+  F.deliver.clear();
+  std::vector<std::pair<const uint8_t*, uint8_t*>> io_fields;  // (input, final output) per field
+  uint32_t fidx = 0;
+  for (const Call& cl : calls) {
+    Inv& v = *cl.inv;
+    const size_t bytes = (size_t)v.batch * fbytes;
+    if (!v.ws) v.ws = c.cache.get(bytes);
+    const uint8_t* in = (const uint8_t*)cl.in;
+    uint8_t* out = (uint8_t*)cl.out;
+    if (host_in) {
+      if (!v.io_in) v.io_in = c.cache.get(bytes);
+      HIPX(hipMemcpyAsync(v.io_in, cl.in, bytes, hipMemcpyHostToDevice, s));
+      in = (const uint8_t*)v.io_in;
+    }
+    if (host_out) {
+      if (!v.io_out) v.io_out = c.cache.get(bytes);
+      out = (uint8_t*)v.io_out;
+    }
+    for (uint32_t b = 0; b < v.batch; b++) {
+      const uint8_t* fin = in + b * fbytes;
+      uint8_t* fout = out + b * fbytes;
+      uint8_t* scratch = (uint8_t*)v.ws + b * fbytes;
+      for (uint32_t sw = 1; sw <= S; sw++) {
+        const uint8_t* r = sw == 1 ? fin : (((S - (sw - 1)) % 2 == 0) ? fout : scratch);
+        uint8_t* w = ((S - sw) % 2 == 0) ? fout : scratch;
+        tab[(size_t)(sw - 1) * 2 * nf + fidx] = (uint64_t)r;
+        tab[(size_t)(sw - 1) * 2 * nf + nf + fidx] = (uint64_t)w;
+      }
+      io_fields.push_back({fin, fout});
+      fidx++;
+    }
+  }
+  const uint64_t* ctab = calls[0].inv->table();
+  if (S == 0) {
+    for (auto& p : io_fields) HIPX(hipMemcpyAsync(p.second, p.first, fbytes, hipMemcpyDeviceToDevice, s));
+  } else {
+    HIPX(hipMemcpyAsync(F.d_meta, F.h_meta, (size_t)S * 2 * nf * 8, hipMemcpyHostToDevice, s));
+    StencilArgs sa{};
+    sa.ctab = ctab;
+    sa.nx = d.nx;
+    sa.ny = d.ny;
+    sa.nz = d.nz;
+    sa.n_fields = nf;
+    sa.tiles_x = (d.nx + kStencilTX - 1) / kStencilTX;
+    sa.tiles_y = (d.ny + kStencilTY - 1) / kStencilTY;
+    sa.tiles_z = (d.nz + kStencilTZ - 1) / kStencilTZ;
+    sa.spatial_tiles = sa.tiles_x * sa.tiles_y * sa.tiles_z;
+    const uint64_t groups = (uint64_t)((sa.spatial_tiles + 7) / 8) * 8 * nf;
+    if (groups > 0x7FFFFFFFull) fail(SAGE_EINVAL, "stencil launch too large");
+    hipFunction_t k = calls[0].inv->fn->mod->get("stencil7_sweep");
+    const int tok = c.timer.start("stencil7", s, S);
+    for (uint32_t sw = 0; sw < S; sw++) {
+      sa.src = reinterpret_cast<const uint64_t*>(F.d_meta) + (size_t)sw * 2 * nf;
+      sa.dst = sa.src + nf;
+      void* params[] = {&sa};
+      HIPX(hipModuleLaunchKernel(k, (uint32_t)groups, 1, 1, 256, 1, 1, 0, s, params, nullptr));
+    }
+    c.timer.stop(tok, s);
+  }
+  if (host_out) {
+    for (const Call& cl : calls)
+      HIPX(hipMemcpyAsync(cl.out, cl.inv->io_out, (size_t)cl.inv->batch * fbytes, hipMemcpyDeviceToHost, s));
+  }
+  HIPX(hipEventRecord(F.done, s));
+  F.busy = true;
+  return fi;
+}
+
+// ---------------------------------------------------------------- autotuner
+// Tile shape per (width, row bucket): every shape is timed on a synthetic
+// layer of that size and the fastest kept.  All shapes give bit-identical
+// results (same MFMA, same K order), so tuning never changes outputs.
+static uint32_t bucket_of(uint32_t rows) {
+  uint32_t b = 16;
+  while (b < rows) b <<= 1;
+  return b;
+}
+
+static void tune_save(Ctx& c) {
+  if (!c.cfg.tune_cache) return;
+  std::ofstream o(c.cfg.tune_cache);
+  for (auto& kv : c.tune) o << kv.first << " " << kv.second.kernel << " " << kv.second.ms << "\n";
+}
+
+void tune_load(Ctx& c) {
+  if (!c.cfg.tune_cache) return;
+  std::ifstream in(c.cfg.tune_cache);
+  std::string key, k;
+  double ms;
+  while (in >> key >> k >> ms) {
+    bool ok = false;
+    for (const auto& s : kShapes) ok |= k == s.name;
+    if (ok) c.tune[key] = TuneEntry{k, ms};
+  }
+}
+
+std::string tuned_kernel(Ctx& c, uint32_t width, uint32_t rows) {
+  const uint32_t bucket = bucket_of(rows);
+  const std::string key = std::to_string(width) + ":" + std::to_string(bucket);
+  auto it = c.tune.find(key);
+  if (it != c.tune.end()) return it->second.kernel;
+  Module* mod = load_module(c, SAGE_MLP_BF16);
+  // synthetic layer: weights contiguous, block table pointing into them
+  const size_t wbytes = (size_t)width * width * 2, nblk = (wbytes + kBlock - 1) / kBlock;
+  uint8_t* w = (uint8_t*)c.cache.get(wbytes);
+  uint8_t* a = (uint8_t*)c.cache.get((size_t)bucket * width * 2);
+  uint8_t* o = (uint8_t*)c.cache.get((size_t)bucket * width * 2);
+  uint8_t* meta = (uint8_t*)c.cache.get(4096 + nblk * 8);
+  std::vector<uint64_t> tab(nblk);
+  for (size_t b = 0; b < nblk; b++) tab[b] = (uint64_t)(w + b * kBlock);
+  hipStream_t s = c.ctl;
+  HIPX(hipMemsetAsync(w, 0, wbytes, s));
+  HIPX(hipMemsetAsync(a, 0, (size_t)bucket * width * 2, s));
+  HIPX(hipMemcpyAsync(meta + 4096, tab.data(), nblk * 8, hipMemcpyHostToDevice, s));
+  HIPX(hipStreamSynchronize(s));
+  hipEvent_t e0, e1;
+  HIPX(hipEventCreate(&e0));
+  HIPX(hipEventCreate(&e1));
+  std::string best;
+  double best_ms = 1e30;
+  for (const auto& ts : kShapes) {
+    if (width % ts.bn) continue;
+    struct {
+      GemmHdr h;
+      GemmGroup g;
+    } m{};
+    m.h.n_groups = 1;
+    m.h.total_tiles = ((bucket + ts.bm - 1) / ts.bm) * (width / ts.bn);
+    m.h.total_rows = bucket;
+    m.g.wtab = (uint64_t)(meta + 4096);
+    m.g.m = bucket;
+    HIPX(hipMemcpyAsync(meta, &m.h, sizeof(GemmHdr), hipMemcpyHostToDevice, s));
+    HIPX(hipMemcpyAsync(meta + 16, &m.g, sizeof(GemmGroup), hipMemcpyHostToDevice, s));
+    HIPX(hipStreamSynchronize(s));
+    LayerArgs la{};
+    la.a_base = a;
+    la.c_base = o;
+    la.N = la.K = width;
+    la.flags = kRelu;
+    hipFunction_t k = mod->get(ts.name);
+    const uint32_t grid = (uint32_t)c.cus * ts.occupancy;
+    auto run = [&] {
+      launch_kernel(k, grid, s, (const GemmHdr*)meta, (const GemmGroup*)(meta + 16), la);
+    };
+    run();
+    const int reps = 5;
+    HIPX(hipEventRecord(e0, s));
+    for (int r = 0; r < reps; r++) run();
+    HIPX(hipEventRecord(e1, s));
+    HIPX(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPX(hipEventElapsedTime(&ms, e0, e1));
+    if (ms / reps < best_ms) {
+      best_ms = ms / reps;
+      best = ts.name;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c.cache.put(w);
+  c.cache.put(a);
+  c.cache.put(o);
+  c.cache.put(meta);
+  c.tune[key] = TuneEntry{best, best_ms};
+  tune_save(c);
+  return best;
+}
+
+}  // namespace sage

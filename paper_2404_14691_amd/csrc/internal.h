@@ -1,0 +1,297 @@
+// Host-side runtime of libsage: context, block pool, function and
+// invocation records, staging ring, grouped launcher.  Internal only; the
+// public interface is include/sage.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <cstdint>
+#include <cstdio>
+#include <deque>
+#include <functional>
+#include <list>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <set>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/sage.h"
+#include "layout.h"
+
+namespace sage {
+
+// ------------------------------------------------------------------ errors
+struct Error {
+  sage_status status;
+  std::string msg;
+};
+[[noreturn]] void fail(sage_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+void set_last_error(const std::string& msg);
+const std::string& last_error();
+void hip_check(hipError_t e, const char* what, const char* file, int line);
+#define HIPX(call) ::sage::hip_check((call), #call, __FILE__, __LINE__)
+
+// Run `body` and translate an Error / std::exception into a status.
+sage_status guard(const std::function<void()>& body);
+
+// ------------------------------------------------------------ kernels (rt)
+hipError_t launch_fp64k(const void* data, uint64_t nbytes, uint64_t* out, int max_groups, hipStream_t s);
+hipError_t launch_blkcopy(const BlkOp* ops, uint32_t n, uint32_t* result, int max_groups, hipStream_t s);
+
+// --------------------------------------------------- device memory caching
+// Size-binned cache of hipMalloc blocks for workspaces and private copies;
+// memory returns to the bin on put() and to HIP only at close.
+class DevCache {
+ public:
+  void* get(size_t n);
+  void put(void* p);
+  void release_all();
+  size_t held() const { return held_; }
+  size_t in_use() const { return in_use_; }
+  static size_t round(size_t n);
+
+ private:
+  std::map<size_t, std::vector<void*>> free_;
+  std::unordered_map<void*, size_t> live_;
+  size_t held_ = 0, in_use_ = 0;
+};
+
+// ------------------------------------------------------------------ timing
+class KernelTimer {
+ public:
+  bool on = false;
+  // Record a start event on s; returns a token for stop().
+  int start(const char* name, hipStream_t s, uint32_t launches);
+  void stop(int token, hipStream_t s);
+  void collect();  // resolve finished pairs (events must be complete)
+  void reset();
+  bool get(const std::string& name, double* ms, uint64_t* n);
+  void destroy();
+
+ private:
+  struct Pair {
+    hipEvent_t a, b;
+    std::string name;
+    uint32_t launches;
+    bool busy;
+  };
+  std::vector<Pair> pairs_;
+  std::map<std::string, std::pair<double, uint64_t>> acc_;
+};
+
+// ------------------------------------------------------------------- pool
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+struct Class {
+  uint64_t fp = 0;
+  uint32_t len = 0;
+  uint32_t slot = kNone;
+  uint32_t rc = 0;
+  uint32_t members = 0;       // registered (fn, block) references
+  bool alive = false;
+  bool in_lru = false;
+  bool indexed = false;
+  std::list<uint32_t>::iterator lru_it;
+  const uint8_t* pending = nullptr;  // device bytes of its first block while its chunk is in flight
+};
+
+class Pool {
+ public:
+  void init(uint64_t budget_slots, size_t seg_slots);
+  void destroy();
+  uint8_t* addr(uint32_t slot) const {
+    return segs_[slot / seg_slots_] + (uint64_t)(slot % seg_slots_) * kBlock;
+  }
+  // Take a free slot, growing the arena up to the budget, else evicting the
+  // front unreferenced class that `protect` does not hold.  kNone if none.
+  uint32_t alloc_slot(const std::function<bool(uint32_t)>& protect);
+  void free_slot(uint32_t s) { free_.push_back(s); used_--; }
+  uint32_t new_class(uint64_t fp, uint32_t len);
+  void drop_class(uint32_t c);          // dead class: slot freed, index entry removed
+  void evict(uint32_t c);
+  void index_add(uint32_t c);
+  void index_remove(uint32_t c);
+  void lru_back(uint32_t c);
+  void lru_remove(uint32_t c);
+  const std::vector<uint32_t>* chain(uint64_t fp) const;
+
+  std::vector<Class> cls;
+  std::list<uint32_t> lru;
+  uint64_t budget = 0, used_ = 0, evictions = 0, epoch = 0;
+
+ private:
+  std::vector<uint8_t*> segs_;
+  size_t seg_slots_ = 16384;
+  std::vector<uint32_t> free_;
+  std::unordered_map<uint64_t, std::vector<uint32_t>> index_;
+};
+
+// --------------------------------------------------------------- modules
+struct Module {
+  hipModule_t mod = nullptr;
+  std::map<std::string, hipFunction_t> fn;
+  hipFunction_t get(const char* name);
+};
+
+// ------------------------------------------------------------- functions
+struct Src {
+  const uint8_t* p;
+  size_t n;
+  bool dev;
+  bool pinned;
+};
+
+struct Fn {
+  uint64_t id = 0;
+  sage_fn_desc d{};
+  std::vector<Src> srcs;
+  std::vector<uint32_t> blob_first;   // first block index of each blob
+  uint32_t n_blocks = 0;
+  uint64_t ro_bytes = 0;
+  std::vector<uint32_t> cls;          // class of each block (shared mode)
+  std::vector<uint32_t> distinct;     // sorted distinct classes
+  std::vector<uint64_t> fps;          // fingerprint of each block
+  uint64_t* d_table = nullptr;        // device: block -> address
+  std::vector<uint64_t> h_table;      // host copy of d_table
+  uint64_t table_epoch = ~0ull;
+  int live = 0;
+  Module* mod = nullptr;
+  hipEvent_t ready = nullptr;         // data of the function is in place
+  uint32_t block_len(uint32_t b) const;
+  const uint8_t* block_src(uint32_t b, bool* dev) const;
+};
+
+struct Inv {
+  uint64_t id = 0;
+  Fn* fn = nullptr;
+  uint32_t batch = 0;
+  bool live = false;
+  void* priv = nullptr;               // private RO copy (share=0)
+  uint64_t* priv_table = nullptr;
+  void* ws = nullptr;                 // stencil: field-sized scratch
+  void* io_in = nullptr;              // staging for host inputs
+  void* io_out = nullptr;             // staging for host outputs
+  const uint64_t* table() const { return priv_table ? priv_table : fn->d_table; }
+};
+
+// ------------------------------------------------------------ in-flight
+struct GraphKey {
+  std::string kernel;
+  uint32_t layers, width;
+  bool operator<(const GraphKey& o) const {
+    return std::tie(kernel, layers, width) < std::tie(o.kernel, o.layers, o.width);
+  }
+};
+
+struct Flight {
+  hipStream_t s = nullptr;
+  hipEvent_t done = nullptr;
+  bool busy = false;
+  // device + pinned mirrors of: header, groups, input row table, output row table
+  uint8_t* d_meta = nullptr;
+  uint8_t* h_meta = nullptr;
+  size_t meta_cap = 0;
+  uint8_t* ws = nullptr;             // activations ping-pong
+  size_t ws_cap = 0;
+  uint8_t* d_in = nullptr;           // packed host inputs
+  uint8_t* h_in = nullptr;
+  size_t in_cap = 0;
+  uint8_t* d_out = nullptr;          // packed outputs for host delivery
+  uint8_t* h_out = nullptr;
+  size_t out_cap = 0;
+  std::map<GraphKey, hipGraphExec_t> graphs;
+  // host delivery after completion
+  std::vector<std::pair<void*, std::pair<size_t, size_t>>> deliver;  // host dst, (offset, bytes)
+  std::vector<int> timer_tokens;
+};
+
+// ------------------------------------------------------------ staging ring
+struct Ring {
+  size_t slots = 0, chunk = 0;
+  std::vector<uint8_t*> host, dev;
+  std::vector<uint64_t*> dfp, hfp;
+  std::vector<BlkOp*> dops, hops;
+  std::vector<uint32_t*> dres, hres;
+  std::vector<hipEvent_t> ev;
+  std::vector<size_t> cap;  // blocks the fp/op/result buffers of each slot hold
+  size_t ops_cap = 0;
+};
+
+// -------------------------------------------------------------- autotuner
+struct TuneEntry {
+  std::string kernel;
+  double ms;
+};
+
+// ------------------------------------------------------------------ context
+struct Ctx {
+  int device = 0;
+  int cus = 256;
+  sage_config cfg{};
+  std::recursive_mutex mu;
+  hipStream_t ctl = nullptr;                 // control stream
+  std::vector<hipStream_t> streams;          // copy / fingerprint streams
+  Ring ring;
+  Pool pool;
+  DevCache cache;
+  KernelTimer timer;
+  std::map<int, std::unique_ptr<Module>> modules;  // per kind
+  std::mutex module_mu;
+  std::map<uint64_t, std::unique_ptr<Fn>> fns;
+  std::map<uint64_t, std::unique_ptr<Inv>> invs;
+  std::vector<Flight> flights;
+  size_t next_flight = 0;
+  uint64_t next_id = 1;
+  std::map<void*, size_t> pinned;            // sage_host_alloc ranges
+  std::map<std::string, TuneEntry> tune;     // "width:bucket" -> best kernel
+  // counters
+  uint64_t logical = 0, h2d = 0, reloads = 0, registrations = 0, invocations = 0, mismatches = 0;
+  bool test_fp_const = false;                // force every fingerprint equal (collision test)
+  uint64_t test_fp_value = 0;
+
+  bool is_pinned(const void* p, size_t n) const;
+  int max_groups_stream() const { return cus * 8; }
+};
+
+// ------------------------------------------------------------- components
+void ring_init(Ctx& c);
+void ring_destroy(Ctx& c);
+void fill_parallel(Ctx& c, uint8_t* dst, const uint8_t* src, size_t n);
+
+// Two setup branches: code load on a helper thread, data on the caller.
+void run_two_branches(const std::function<void()>& code, const std::function<void()>& data, bool serial);
+
+Module* load_module(Ctx& c, int kind);
+void register_shared(Ctx& c, Fn& f);
+void copy_private(Ctx& c, Fn& f, uint8_t* dst, hipStream_t s);
+void reload_classes(Ctx& c, Fn& f, const std::vector<uint32_t>& missing);
+void refresh_table(Ctx& c, Fn& f);
+
+// grouped execution
+struct Call {
+  Inv* inv;
+  const void* in;
+  size_t in_bytes;
+  void* out;
+  size_t out_bytes;
+};
+int launch_mlp_group(Ctx& c, const std::vector<Call>& calls, uint32_t io);
+int launch_stencil_group(Ctx& c, const std::vector<Call>& calls, uint32_t io);
+void finish_flight(Ctx& c, int flight);
+void flights_init(Ctx& c);
+void flights_destroy(Ctx& c);
+std::string tuned_kernel(Ctx& c, uint32_t width, uint32_t rows);
+void tune_load(Ctx& c);
+
+size_t in_elem_size(const sage_fn_desc& d);
+size_t in_bytes_for(const sage_fn_desc& d, uint32_t batch);
+size_t out_bytes_for(const sage_fn_desc& d, uint32_t batch);
+uint64_t ro_bytes_for(const sage_fn_desc& d);
+
+}  // namespace sage

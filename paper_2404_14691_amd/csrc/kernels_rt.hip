@@ -1,0 +1,156 @@
+// Runtime kernels of the data-preparation path, built into libsage.so:
+//   fp64k   - FP64K-v1 fingerprint of every 64 KiB block of a device buffer
+//   blkcopy - per-block COPY into pool slots, or byte-for-byte VERIFY
+// Both are HBM-streaming kernels: 16-byte coalesced loads, all of a block's
+// loads issued before any use, one workgroup per block (grid-stride).
+#include <hip/hip_runtime.h>
+
+#include "layout.h"
+
+namespace sage {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Keyed product of one 64-bit word j: ((lo + a_j) mod 2^32) * ((hi + c_j) mod 2^32).
+__device__ __forceinline__ uint64_t nh_term(uint32_t lo, uint32_t hi, uint32_t a, uint32_t c) {
+  return (uint64_t)(lo + a) * (uint64_t)(hi + c);
+}
+
+// 256 threads per block.  Thread t reads the 16-byte pieces i*4096 + 16t
+// (i < 16), i.e. words j = 512i + 2t and 512i + 2t + 1, so its keys advance
+// by 512*K1 / 512*K3 per piece.  The sum is commutative mod 2^64, so the
+// wave shuffle + LDS reduction order does not change the result.
+__global__ __launch_bounds__(256) void fp64k_kernel(const uint8_t* __restrict__ data, uint64_t nbytes,
+                                                    uint64_t* __restrict__ out, uint32_t nblocks) {
+  __shared__ uint64_t red[4];
+  const uint32_t t = threadIdx.x;
+  const uint64_t nfull = nbytes >> kBlockShift;
+  const uint32_t a0 = kFpK0 + (2u * t) * kFpK1;
+  const uint32_t c0 = kFpK2 + (2u * t) * kFpK3;
+  const uint32_t a_step = 512u * kFpK1, c_step = 512u * kFpK3;
+  for (uint32_t b = blockIdx.x; b < nblocks; b += gridDim.x) {
+    uint64_t acc = 0;
+    const uint8_t* base = data + ((uint64_t)b << kBlockShift);
+    uint64_t L;
+    if (b < nfull) {
+      L = kBlock;
+      const u32x4* p = reinterpret_cast<const u32x4*>(base) + t;
+      u32x4 v[16];
+#pragma unroll
+      for (int i = 0; i < 16; i++) v[i] = __builtin_nontemporal_load(p + i * 256);
+      uint32_t a = a0, c = c0;
+#pragma unroll
+      for (int i = 0; i < 16; i++) {
+        acc += nh_term(v[i].x, v[i].y, a, c);
+        acc += nh_term(v[i].z, v[i].w, a + kFpK1, c + kFpK3);
+        a += a_step;
+        c += c_step;
+      }
+    } else {
+      // short last block: word by word, zero-padded to 8 bytes
+      L = nbytes - ((uint64_t)b << kBlockShift);
+      const uint32_t nw = (uint32_t)((L + 7) >> 3);
+      for (uint32_t j = t; j < nw; j += 256) {
+        uint64_t w = 0;
+        if (8ull * (j + 1) <= L) {
+          w = *reinterpret_cast<const uint64_t*>(base + 8ull * j);
+        } else {
+          for (uint32_t q = 0; 8ull * j + q < L; q++) w |= (uint64_t)base[8ull * j + q] << (8 * q);
+        }
+        acc += nh_term((uint32_t)w, (uint32_t)(w >> 32), kFpK0 + j * kFpK1, kFpK2 + j * kFpK3);
+      }
+    }
+    acc = wave_sum_u64(acc);
+    if ((t & 63) == 0) red[t >> 6] = acc;
+    __syncthreads();
+    if (t == 0) {
+      const uint64_t s = red[0] + red[1] + red[2] + red[3];
+      out[b] = mix64(s ^ (L * kFpK4));
+    }
+    __syncthreads();
+  }
+}
+
+// One workgroup per operation.  Full blocks move as 16 x 16 B per thread,
+// all loads first; short blocks fall back to a strided loop plus bytes.
+__global__ __launch_bounds__(256) void blkcopy_kernel(const BlkOp* __restrict__ ops, uint32_t n,
+                                                      uint32_t* __restrict__ result) {
+  const uint32_t t = threadIdx.x;
+  for (uint32_t o = blockIdx.x; o < n; o += gridDim.x) {
+    const BlkOp op = ops[o];
+    const u32x4* s = reinterpret_cast<const u32x4*>(op.src);
+    const uint32_t nvec = op.len >> 4;
+    if (op.op == 0) {
+      u32x4* d = reinterpret_cast<u32x4*>(op.dst);
+      if (nvec == kBlock / 16) {
+        u32x4 v[16];
+#pragma unroll
+        for (int i = 0; i < 16; i++) v[i] = __builtin_nontemporal_load(s + t + i * 256);
+#pragma unroll
+        for (int i = 0; i < 16; i++) d[t + i * 256] = v[i];
+      } else {
+        for (uint32_t i = t; i < nvec; i += 256) d[i] = s[i];
+        const uint32_t q = nvec * 16 + t;
+        if (q < op.len)
+          reinterpret_cast<uint8_t*>(op.dst)[q] = reinterpret_cast<const uint8_t*>(op.src)[q];
+      }
+    } else {
+      const u32x4* d = reinterpret_cast<const u32x4*>(op.dst);
+      int diff = 0;
+      if (nvec == kBlock / 16) {
+        u32x4 v[8], w[8];
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+#pragma unroll
+          for (int i = 0; i < 8; i++) {
+            v[i] = __builtin_nontemporal_load(s + t + (h * 8 + i) * 256);
+            w[i] = __builtin_nontemporal_load(d + t + (h * 8 + i) * 256);
+          }
+#pragma unroll
+          for (int i = 0; i < 8; i++)
+            diff |= (v[i].x != w[i].x) | (v[i].y != w[i].y) | (v[i].z != w[i].z) | (v[i].w != w[i].w);
+        }
+      } else {
+        for (uint32_t i = t; i < nvec; i += 256) {
+          const u32x4 a = s[i], b = d[i];
+          diff |= (a.x != b.x) | (a.y != b.y) | (a.z != b.z) | (a.w != b.w);
+        }
+        const uint32_t q = nvec * 16 + t;
+        if (q < op.len)
+          diff |= reinterpret_cast<const uint8_t*>(op.src)[q] != reinterpret_cast<const uint8_t*>(op.dst)[q];
+      }
+      diff = __syncthreads_or(diff);
+      if (t == 0) result[o] = diff ? 1u : 0u;
+    }
+  }
+}
+
+hipError_t launch_fp64k(const void* data, uint64_t nbytes, uint64_t* out, int max_groups, hipStream_t s) {
+  if (nbytes == 0) return hipSuccess;
+  const uint32_t nblocks = (uint32_t)((nbytes + kBlock - 1) >> kBlockShift);
+  const uint32_t grid = nblocks < (uint32_t)max_groups ? nblocks : (uint32_t)max_groups;
+  hipLaunchKernelGGL(fp64k_kernel, dim3(grid), dim3(256), 0, s, static_cast<const uint8_t*>(data), nbytes, out,
+                     nblocks);
+  return hipGetLastError();
+}
+
+hipError_t launch_blkcopy(const BlkOp* ops, uint32_t n, uint32_t* result, int max_groups, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const uint32_t grid = n < (uint32_t)max_groups ? n : (uint32_t)max_groups;
+  hipLaunchKernelGGL(blkcopy_kernel, dim3(grid), dim3(256), 0, s, ops, n, result);
+  return hipGetLastError();
+}
+
+}  // namespace sage

@@ -1,0 +1,450 @@
+// Data preparation: the staging ring, the chunked fingerprint + dedup commit
+// of fn_register, private copies (share=0), reloads of evicted classes and
+// the per-function block tables.
+#include <dlfcn.h>
+
+#include <algorithm>
+#include <cstring>
+#include <unordered_set>
+
+#include "internal.h"
+
+namespace sage {
+
+// ----------------------------------------------------------------- ring
+void ring_init(Ctx& c) {
+  Ring& R = c.ring;
+  R.slots = c.cfg.ring_slots;
+  R.chunk = c.cfg.chunk_bytes;
+  const size_t nblk = R.chunk / kBlock;
+  R.ops_cap = nblk;
+  R.cap.assign(R.slots, nblk);
+  for (size_t i = 0; i < R.slots; i++) {
+    uint8_t *h = nullptr, *d = nullptr;
+    uint64_t *dfp = nullptr, *hfp = nullptr;
+    BlkOp *dops = nullptr, *hops = nullptr;
+    uint32_t *dres = nullptr, *hres = nullptr;
+    hipEvent_t ev;
+    HIPX(hipHostMalloc((void**)&h, R.chunk, hipHostMallocDefault));
+    HIPX(hipMalloc((void**)&d, R.chunk));
+    HIPX(hipMalloc((void**)&dfp, nblk * 8));
+    HIPX(hipHostMalloc((void**)&hfp, nblk * 8, hipHostMallocDefault));
+    HIPX(hipMalloc((void**)&dops, nblk * sizeof(BlkOp)));
+    HIPX(hipHostMalloc((void**)&hops, nblk * sizeof(BlkOp), hipHostMallocDefault));
+    HIPX(hipMalloc((void**)&dres, nblk * 4));
+    HIPX(hipHostMalloc((void**)&hres, nblk * 4, hipHostMallocDefault));
+    HIPX(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    R.host.push_back(h);
+    R.dev.push_back(d);
+    R.dfp.push_back(dfp);
+    R.hfp.push_back(hfp);
+    R.dops.push_back(dops);
+    R.hops.push_back(hops);
+    R.dres.push_back(dres);
+    R.hres.push_back(hres);
+    R.ev.push_back(ev);
+  }
+}
+
+void ring_destroy(Ctx& c) {
+  Ring& R = c.ring;
+  for (size_t i = 0; i < R.host.size(); i++) {
+    (void)hipHostFree(R.host[i]);
+    (void)hipFree(R.dev[i]);
+    (void)hipFree(R.dfp[i]);
+    (void)hipHostFree(R.hfp[i]);
+    (void)hipFree(R.dops[i]);
+    (void)hipHostFree(R.hops[i]);
+    (void)hipFree(R.dres[i]);
+    (void)hipHostFree(R.hres[i]);
+    (void)hipEventDestroy(R.ev[i]);
+  }
+  R = Ring{};
+}
+
+// Grow the per-slot fingerprint / operation / result buffers of `slot` to
+// hold `nblk` blocks (device-resident sources are fingerprinted whole).
+static void ring_reserve(Ctx& c, int slot, size_t nblk) {
+  Ring& R = c.ring;
+  if (R.cap[slot] >= nblk) return;
+  (void)hipFree(R.dfp[slot]);
+  (void)hipHostFree(R.hfp[slot]);
+  (void)hipFree(R.dops[slot]);
+  (void)hipHostFree(R.hops[slot]);
+  (void)hipFree(R.dres[slot]);
+  (void)hipHostFree(R.hres[slot]);
+  R.dfp[slot] = R.hfp[slot] = nullptr;
+  R.dops[slot] = R.hops[slot] = nullptr;
+  R.dres[slot] = R.hres[slot] = nullptr;
+  R.cap[slot] = 0;
+  HIPX(hipMalloc((void**)&R.dfp[slot], nblk * 8));
+  HIPX(hipHostMalloc((void**)&R.hfp[slot], nblk * 8, hipHostMallocDefault));
+  HIPX(hipMalloc((void**)&R.dops[slot], nblk * sizeof(BlkOp)));
+  HIPX(hipHostMalloc((void**)&R.hops[slot], nblk * sizeof(BlkOp), hipHostMallocDefault));
+  HIPX(hipMalloc((void**)&R.dres[slot], nblk * 4));
+  HIPX(hipHostMalloc((void**)&R.hres[slot], nblk * 4, hipHostMallocDefault));
+  R.cap[slot] = nblk;
+}
+
+// Host copy of a pageable source into pinned staging, split over threads.
+void fill_parallel(Ctx& c, uint8_t* dst, const uint8_t* src, size_t n) {
+  const size_t nt = std::max<uint32_t>(1, c.cfg.fill_threads);
+  if (nt == 1 || n < (1u << 20)) {
+    std::memcpy(dst, src, n);
+    return;
+  }
+  const size_t part = (n / nt + 4095) & ~size_t(4095);
+  std::vector<std::thread> th;
+  for (size_t i = 1; i < nt; i++) {
+    const size_t o = i * part;
+    if (o >= n) break;
+    th.emplace_back([=] { std::memcpy(dst + o, src + o, std::min(part, n - o)); });
+  }
+  std::memcpy(dst, src, std::min(part, n));
+  for (auto& t : th) t.join();
+}
+
+// --------------------------------------------------------------- modules
+static std::string lib_dir() {
+  Dl_info info;
+  if (dladdr((void*)&lib_dir, &info) && info.dli_fname) {
+    std::string p = info.dli_fname;
+    const size_t k = p.rfind('/');
+    if (k != std::string::npos) return p.substr(0, k);
+  }
+  return ".";
+}
+
+hipFunction_t Module::get(const char* name) {
+  auto it = fn.find(name);
+  if (it != fn.end()) return it->second;
+  hipFunction_t f = nullptr;
+  const hipError_t e = hipModuleGetFunction(&f, mod, name);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    fail(SAGE_EIO, "kernel %s not found in code object", name);
+  }
+  fn[name] = f;
+  return f;
+}
+
+// The code of a kind is loaded once per context and shared by all its
+// functions and invocations (section "Context Memory Sharing").
+Module* load_module(Ctx& c, int kind) {
+  std::lock_guard<std::mutex> lk(c.module_mu);
+  const int key = kind == SAGE_STENCIL7_F32 ? SAGE_STENCIL7_F32 : SAGE_MLP_BF16;
+  auto it = c.modules.find(key);
+  if (it != c.modules.end()) return it->second.get();
+  HIPX(hipSetDevice(c.device));
+  const std::string path = lib_dir() + (key == SAGE_STENCIL7_F32 ? "/sage_stencil.hsaco" : "/sage_mlp.hsaco");
+  auto m = std::make_unique<Module>();
+  const hipError_t e = hipModuleLoad(&m->mod, path.c_str());
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    fail(SAGE_EIO, "hipModuleLoad(%s): %s", path.c_str(), hipGetErrorString(e));
+  }
+  if (key == SAGE_STENCIL7_F32) {
+    m->get("stencil7_sweep");
+  } else {
+    m->get("mlp_f32_layer");
+    m->get("ggemm_bf16_128x128");
+  }
+  Module* raw = m.get();
+  c.modules[key] = std::move(m);
+  return raw;
+}
+
+// --------------------------------------------------------------- blocks
+uint32_t Fn::block_len(uint32_t b) const {
+  size_t i = std::upper_bound(blob_first.begin(), blob_first.end(), b) - blob_first.begin() - 1;
+  const uint64_t off = (uint64_t)(b - blob_first[i]) * kBlock;
+  return (uint32_t)std::min<uint64_t>(kBlock, srcs[i].n - off);
+}
+
+const uint8_t* Fn::block_src(uint32_t b, bool* dev) const {
+  size_t i = std::upper_bound(blob_first.begin(), blob_first.end(), b) - blob_first.begin() - 1;
+  *dev = srcs[i].dev;
+  return srcs[i].p + (uint64_t)(b - blob_first[i]) * kBlock;
+}
+
+// ------------------------------------------------------- register (shared)
+namespace {
+struct Chunk {
+  uint32_t blob;
+  uint64_t off, bytes;
+  uint32_t first, nblk;
+  int slot;
+  const uint8_t* data;  // device address of the chunk's bytes
+};
+}  // namespace
+
+// The data branch of fn_register with sharing on.  Chunks stream through
+// the ring: H2D (or the device source in place) -> fingerprints -> D2H, up
+// to `ring_slots` chunks ahead, while the host commits earlier chunks in
+// order: each block either joins the first indexed class with the same
+// fingerprint whose bytes verify equal, or becomes a new class copied into
+// a fresh slot.  Fingerprints are only an index; equality is decided by
+// the VERIFY kernel, so a collision costs a slot, never a wrong byte.
+void register_shared(Ctx& c, Fn& f) {
+  Pool& P = c.pool;
+  Ring& R = c.ring;
+  std::vector<Chunk> chunks;
+  for (uint32_t b = 0; b < f.srcs.size(); b++) {
+    // device sources need no staging: fingerprint and commit them whole
+    const uint64_t step = f.srcs[b].dev ? std::max<uint64_t>(f.srcs[b].n, 1) : R.chunk;
+    for (uint64_t off = 0; off < f.srcs[b].n; off += step) {
+      Chunk ch{};
+      ch.blob = b;
+      ch.off = off;
+      ch.bytes = std::min<uint64_t>(step, f.srcs[b].n - off);
+      ch.first = f.blob_first[b] + (uint32_t)(off / kBlock);
+      ch.nblk = (uint32_t)((ch.bytes + kBlock - 1) / kBlock);
+      ch.slot = -1;
+      chunks.push_back(ch);
+    }
+  }
+  f.cls.assign(f.n_blocks, kNone);
+  f.fps.assign(f.n_blocks, 0);
+  std::vector<uint32_t> created;
+  std::unordered_set<uint32_t> protect_set;
+  auto protect = [&](uint32_t cl) { return protect_set.count(cl) > 0; };
+  std::vector<int> free_slots;
+  for (int s = (int)R.slots; s-- > 0;) free_slots.push_back(s);
+
+  auto stream_of = [&](int slot) { return c.streams[slot % c.streams.size()]; };
+
+  auto issue = [&](Chunk& ch) {
+    ch.slot = free_slots.back();
+    free_slots.pop_back();
+    ring_reserve(c, ch.slot, ch.nblk);
+    hipStream_t s = stream_of(ch.slot);
+    const Src& src = f.srcs[ch.blob];
+    if (src.dev) {
+      ch.data = src.p + ch.off;
+    } else {
+      const uint8_t* hsrc = src.p + ch.off;
+      if (!src.pinned) {
+        fill_parallel(c, R.host[ch.slot], hsrc, ch.bytes);
+        hsrc = R.host[ch.slot];
+      }
+      HIPX(hipMemcpyAsync(R.dev[ch.slot], hsrc, ch.bytes, hipMemcpyHostToDevice, s));
+      ch.data = R.dev[ch.slot];
+    }
+    const int tok = c.timer.start("fp64k", s, 1);
+    HIPX(launch_fp64k(ch.data, ch.bytes, R.dfp[ch.slot], c.max_groups_stream(), s));
+    c.timer.stop(tok, s);
+    HIPX(hipMemcpyAsync(R.hfp[ch.slot], R.dfp[ch.slot], ch.nblk * 8, hipMemcpyDeviceToHost, s));
+    HIPX(hipEventRecord(R.ev[ch.slot], s));
+  };
+
+  auto process = [&](Chunk& ch) {
+    const int slot = ch.slot;
+    hipStream_t s = stream_of(slot);
+    HIPX(hipEventSynchronize(R.ev[slot]));
+    BlkOp* ops = R.hops[slot];
+    uint32_t nops = 0;
+    struct Pend {
+      uint32_t i, cand, op;
+    };
+    std::vector<Pend> pend;
+    std::vector<uint32_t> chunk_new;
+    auto ref_addr = [&](uint32_t cl) -> uint64_t {
+      const Class& k = P.cls[cl];
+      return (uint64_t)(k.pending ? k.pending : P.addr(k.slot));
+    };
+    auto make_new = [&](uint32_t i) {
+      const uint32_t gb = ch.first + i, len = f.block_len(gb);
+      const uint32_t slotid = P.alloc_slot(protect);
+      if (slotid == kNone)
+        fail(SAGE_ENOMEM, "pool full: no unreferenced block to evict (budget %llu slots)",
+             (unsigned long long)P.budget);
+      const uint32_t cl = P.new_class(f.fps[gb], len);
+      P.cls[cl].slot = slotid;
+      P.cls[cl].pending = ch.data + (uint64_t)i * kBlock;
+      P.index_add(cl);
+      created.push_back(cl);
+      chunk_new.push_back(cl);
+      protect_set.insert(cl);
+      f.cls[gb] = cl;
+      ops[nops++] = BlkOp{(uint64_t)(ch.data + (uint64_t)i * kBlock), (uint64_t)P.addr(slotid), len, 0};
+    };
+    // first candidate after `after` (or the first one) with the block's length
+    auto next_cand = [&](uint64_t fp, uint32_t len, uint32_t after) -> uint32_t {
+      const auto* chn = P.chain(fp);
+      if (!chn) return kNone;
+      size_t k = 0;
+      if (after != kNone) {
+        while (k < chn->size() && (*chn)[k] != after) k++;
+        k++;
+      }
+      for (; k < chn->size(); k++) {
+        protect_set.insert((*chn)[k]);
+        if (P.cls[(*chn)[k]].len == len) return (*chn)[k];
+      }
+      return kNone;
+    };
+    for (uint32_t i = 0; i < ch.nblk; i++) {
+      const uint32_t gb = ch.first + i;
+      const uint64_t fp = c.test_fp_const ? c.test_fp_value : R.hfp[slot][i];
+      f.fps[gb] = fp;
+      const uint32_t len = f.block_len(gb);
+      const uint32_t cand = next_cand(fp, len, kNone);
+      if (cand != kNone) {
+        pend.push_back({i, cand, nops});
+        ops[nops++] = BlkOp{(uint64_t)(ch.data + (uint64_t)i * kBlock), ref_addr(cand), len, 1};
+      } else {
+        make_new(i);
+      }
+    }
+    while (nops > 0) {
+      HIPX(hipMemcpyAsync(R.dops[slot], ops, nops * sizeof(BlkOp), hipMemcpyHostToDevice, s));
+      const int tok = c.timer.start("blkcopy", s, 1);
+      HIPX(launch_blkcopy(R.dops[slot], nops, R.dres[slot], c.max_groups_stream(), s));
+      c.timer.stop(tok, s);
+      HIPX(hipMemcpyAsync(R.hres[slot], R.dres[slot], nops * 4, hipMemcpyDeviceToHost, s));
+      HIPX(hipStreamSynchronize(s));
+      std::vector<uint32_t> res(R.hres[slot], R.hres[slot] + nops);
+      nops = 0;
+      std::vector<Pend> again;
+      for (const Pend& p : pend) {
+        const uint32_t gb = ch.first + p.i;
+        if (res[p.op] == 0) {
+          f.cls[gb] = p.cand;
+          continue;
+        }
+        c.mismatches++;
+        const uint32_t nxt = next_cand(f.fps[gb], f.block_len(gb), p.cand);
+        if (nxt != kNone) {
+          again.push_back({p.i, nxt, nops});
+          ops[nops++] = BlkOp{(uint64_t)(ch.data + (uint64_t)p.i * kBlock), ref_addr(nxt), f.block_len(gb), 1};
+        } else {
+          make_new(p.i);
+        }
+      }
+      pend.swap(again);
+    }
+    for (uint32_t cl : chunk_new) P.cls[cl].pending = nullptr;
+  };
+
+  try {
+    std::deque<size_t> inflight;
+    size_t next = 0;
+    while (next < chunks.size() || !inflight.empty()) {
+      while (next < chunks.size() && !free_slots.empty()) {
+        issue(chunks[next]);
+        inflight.push_back(next++);
+      }
+      Chunk& ch = chunks[inflight.front()];
+      inflight.pop_front();
+      process(ch);
+      free_slots.push_back(ch.slot);
+    }
+  } catch (...) {
+    for (hipStream_t s : c.streams) (void)hipStreamSynchronize(s);
+    for (uint32_t cl : created) P.drop_class(cl);
+    throw;
+  }
+  for (uint32_t cl : f.cls) P.cls[cl].members++;
+  f.distinct = f.cls;
+  std::sort(f.distinct.begin(), f.distinct.end());
+  f.distinct.erase(std::unique(f.distinct.begin(), f.distinct.end()), f.distinct.end());
+  for (uint32_t cl : f.distinct)
+    if (P.cls[cl].rc == 0) P.lru_back(cl);
+  c.h2d += f.ro_bytes;
+}
+
+// ------------------------------------------------------ private copies
+// share=0: the whole read-only data goes to `dst` (blob i at its first
+// block), through the same staging ring for pageable host sources.
+void copy_private(Ctx& c, Fn& f, uint8_t* dst, hipStream_t s) {
+  Ring& R = c.ring;
+  size_t k = 0;
+  for (size_t b = 0; b < f.srcs.size(); b++) {
+    const Src& src = f.srcs[b];
+    uint8_t* d = dst + (uint64_t)f.blob_first[b] * kBlock;
+    if (src.dev) {
+      HIPX(hipMemcpyAsync(d, src.p, src.n, hipMemcpyDeviceToDevice, s));
+    } else if (src.pinned) {
+      for (uint64_t off = 0; off < src.n; off += R.chunk, k++) {
+        hipStream_t cs = c.streams[k % c.streams.size()];
+        HIPX(hipMemcpyAsync(d + off, src.p + off, std::min<uint64_t>(R.chunk, src.n - off),
+                            hipMemcpyHostToDevice, cs));
+      }
+    } else {
+      for (uint64_t off = 0; off < src.n; off += R.chunk, k++) {
+        const int slot = (int)(k % R.slots);
+        hipStream_t cs = c.streams[slot % c.streams.size()];
+        if (k >= R.slots) HIPX(hipEventSynchronize(R.ev[slot]));  // slot's previous copy done
+        const uint64_t n = std::min<uint64_t>(R.chunk, src.n - off);
+        fill_parallel(c, R.host[slot], src.p + off, n);
+        HIPX(hipMemcpyAsync(d + off, R.host[slot], n, hipMemcpyHostToDevice, cs));
+        HIPX(hipEventRecord(R.ev[slot], cs));
+      }
+    }
+  }
+  for (hipStream_t cs : c.streams) HIPX(hipStreamSynchronize(cs));
+  c.h2d += f.ro_bytes;
+}
+
+// ------------------------------------------------------------ reloads
+// Bring evicted classes of `f` back: each class is copied from the source
+// block of `f` that first referenced it (the source is read-only and was
+// verified equal at registration).  Slots must already be available.
+void reload_classes(Ctx& c, Fn& f, const std::vector<uint32_t>& missing) {
+  if (missing.empty()) return;
+  Pool& P = c.pool;
+  Ring& R = c.ring;
+  std::unordered_map<uint32_t, uint32_t> first;
+  for (uint32_t b = 0; b < f.n_blocks; b++) first.emplace(f.cls[b], b);
+  std::unordered_set<uint32_t> mine(f.distinct.begin(), f.distinct.end());
+  auto protect = [&](uint32_t cl) { return mine.count(cl) > 0; };
+  const size_t per_slot = R.chunk / kBlock;
+  hipStream_t s = c.streams[0];
+  size_t i = 0;
+  while (i < missing.size()) {
+    BlkOp* ops = R.hops[0];
+    uint32_t nops = 0;
+    size_t staged = 0;
+    while (i < missing.size() && nops < per_slot) {
+      const uint32_t cl = missing[i++];
+      const uint32_t b = first.at(cl);
+      bool dev = false;
+      const uint8_t* src = f.block_src(b, &dev);
+      const uint32_t len = P.cls[cl].len;
+      const uint32_t slotid = P.alloc_slot(protect);
+      if (slotid == kNone) fail(SAGE_ENOMEM, "pool full during reload");
+      P.cls[cl].slot = slotid;
+      P.index_add(cl);
+      if (dev) {
+        ops[nops++] = BlkOp{(uint64_t)src, (uint64_t)P.addr(slotid), len, 0};
+      } else {
+        std::memcpy(R.host[0] + staged * kBlock, src, len);
+        ops[nops++] = BlkOp{(uint64_t)(R.dev[0] + staged * kBlock), (uint64_t)P.addr(slotid), len, 0};
+        staged++;
+      }
+      c.h2d += len;
+      c.reloads++;
+    }
+    if (staged) HIPX(hipMemcpyAsync(R.dev[0], R.host[0], staged * kBlock, hipMemcpyHostToDevice, s));
+    HIPX(hipMemcpyAsync(R.dops[0], ops, nops * sizeof(BlkOp), hipMemcpyHostToDevice, s));
+    const int tok = c.timer.start("blkcopy", s, 1);
+    HIPX(launch_blkcopy(R.dops[0], nops, R.dres[0], c.max_groups_stream(), s));
+    c.timer.stop(tok, s);
+    HIPX(hipStreamSynchronize(s));
+  }
+}
+
+// Rebuild the device block table of `f` when any of its classes moved.
+void refresh_table(Ctx& c, Fn& f) {
+  if (f.table_epoch == c.pool.epoch && !f.h_table.empty()) return;
+  std::vector<uint64_t> t(f.n_blocks);
+  for (uint32_t b = 0; b < f.n_blocks; b++) t[b] = (uint64_t)c.pool.addr(c.pool.cls[f.cls[b]].slot);
+  if (t != f.h_table) {
+    HIPX(hipMemcpyAsync(f.d_table, t.data(), t.size() * 8, hipMemcpyHostToDevice, c.ctl));
+    HIPX(hipStreamSynchronize(c.ctl));
+    f.h_table.swap(t);
+  }
+  f.table_epoch = c.pool.epoch;
+}
+
+}  // namespace sage

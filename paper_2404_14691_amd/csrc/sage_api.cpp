@@ -1,0 +1,544 @@
+// The C ABI (include/sage.h): context, functions, invocations, statistics,
+// kernel entry points and timing.
+#include <algorithm>
+#include <tuple>
+#include <cstdlib>
+#include <cstring>
+#include <unordered_set>
+
+#include "internal.h"
+
+using namespace sage;
+
+struct sage_ctx {
+  Ctx c;
+};
+
+namespace {
+
+Ctx& ctx_of(sage_ctx* p) {
+  if (!p) fail(SAGE_EINVAL, "null context");
+  return p->c;
+}
+
+Fn& fn_of(Ctx& c, sage_fn id) {
+  auto it = c.fns.find(id);
+  if (it == c.fns.end()) fail(SAGE_ENOTFOUND, "unknown function handle %llu", (unsigned long long)id);
+  return *it->second;
+}
+
+Inv& inv_of(Ctx& c, sage_inv id) {
+  auto it = c.invs.find(id);
+  if (it == c.invs.end()) fail(SAGE_ENOTFOUND, "unknown invocation handle %llu", (unsigned long long)id);
+  if (!it->second->live) fail(SAGE_ESTATE, "invocation %llu already released", (unsigned long long)id);
+  return *it->second;
+}
+
+bool pow2(uint64_t v) { return v && !(v & (v - 1)); }
+
+void check_aligned(const void* p, const char* what) {
+  if ((uintptr_t)p & 15) fail(SAGE_EINVAL, "%s must be 16-byte aligned", what);
+}
+
+// Validate a function description against its read-only blobs.
+void validate(const sage_fn_desc& d, const sage_blob* blobs, size_t n) {
+  if (d.kind == SAGE_MLP_F32 || d.kind == SAGE_MLP_BF16) {
+    const uint64_t es = d.kind == SAGE_MLP_BF16 ? 2 : 4;
+    if (d.layers < 1 || !pow2(d.width) || d.width < 128 || (uint64_t)d.width * es > kBlock)
+      fail(SAGE_EINVAL, "MLP needs layers >= 1 and a power-of-two width >= 128 with rows <= 64 KiB");
+  } else if (d.kind == SAGE_STENCIL7_F32) {
+    if (!pow2(d.nx) || (uint64_t)d.nx * 4 > kBlock || d.nx < 4 || d.ny < 3 || d.nz < 3)
+      fail(SAGE_EINVAL, "stencil needs a power-of-two nx with nx*4 <= 65536 and extents >= 3");
+  } else {
+    fail(SAGE_EINVAL, "unknown function kind %u", d.kind);
+  }
+  if (n != 1 || !blobs) fail(SAGE_EINVAL, "this kind takes exactly one read-only blob");
+  for (size_t i = 0; i < n; i++) {
+    const sage_blob& b = blobs[i];
+    if (b.access != SAGE_RO) fail(SAGE_EINVAL, "only read-only blobs are registered; writable data goes to fn_invoke");
+    if (!b.src && b.nbytes) fail(SAGE_EINVAL, "blob %zu has no source", i);
+    if (b.where == SAGE_SRC_DEVICE) check_aligned(b.src, "device blob source");
+    else if (b.where != SAGE_SRC_HOST) fail(SAGE_EINVAL, "blob %zu: unknown location", i);
+  }
+  if (blobs[0].nbytes != ro_bytes_for(d))
+    fail(SAGE_EINVAL, "blob holds %zu bytes, the kind needs %llu", blobs[0].nbytes,
+         (unsigned long long)ro_bytes_for(d));
+}
+
+void free_inv_buffers(Ctx& c, Inv& v) {
+  c.cache.put(v.priv);
+  c.cache.put(v.priv_table);
+  c.cache.put(v.ws);
+  c.cache.put(v.io_in);
+  c.cache.put(v.io_out);
+  v.priv = v.ws = v.io_in = v.io_out = nullptr;
+  v.priv_table = nullptr;
+}
+
+}  // namespace
+
+bool Ctx::is_pinned(const void* p, size_t n) const {
+  auto it = pinned.upper_bound(const_cast<void*>(p));
+  if (it == pinned.begin()) return false;
+  --it;
+  const uint8_t* base = (const uint8_t*)it->first;
+  return (const uint8_t*)p >= base && (const uint8_t*)p + n <= base + it->second;
+}
+
+extern "C" {
+
+void sage_config_default(sage_config* cfg) {
+  if (!cfg) return;
+  std::memset(cfg, 0, sizeof *cfg);
+  cfg->ring_slots = 8;
+  cfg->chunk_bytes = 8u << 20;
+  cfg->streams = 4;
+  cfg->fill_threads = 4;
+  cfg->inflight_groups = 4;
+  cfg->share = 1;
+  cfg->batch = 1;
+  cfg->serial_setup = 0;
+  cfg->pool_budget_bytes = 0;
+  cfg->tune_cache = nullptr;
+}
+
+const char* sage_last_error(void) { return last_error().c_str(); }
+
+sage_status sage_open(int device, const sage_config* cfg, sage_ctx** out) {
+  return guard([&] {
+    if (!out) fail(SAGE_EINVAL, "null output");
+    *out = nullptr;
+    auto h = std::make_unique<sage_ctx>();
+    Ctx& c = h->c;
+    c.device = device;
+    if (cfg) c.cfg = *cfg;
+    else sage_config_default(&c.cfg);
+    if (c.cfg.ring_slots < 1 || c.cfg.chunk_bytes < kBlock || c.cfg.chunk_bytes % kBlock || c.cfg.streams < 1)
+      fail(SAGE_EINVAL, "ring_slots >= 1, streams >= 1, chunk_bytes a multiple of 64 KiB");
+    int ndev = 0;
+    HIPX(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) fail(SAGE_EINVAL, "device %d not present (%d devices)", device, ndev);
+    HIPX(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    HIPX(hipGetDeviceProperties(&prop, device));
+    c.cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    HIPX(hipStreamCreateWithFlags(&c.ctl, hipStreamNonBlocking));
+    for (uint32_t i = 0; i < c.cfg.streams; i++) {
+      hipStream_t s;
+      HIPX(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+      c.streams.push_back(s);
+    }
+    size_t free_b = 0, total_b = 0;
+    HIPX(hipMemGetInfo(&free_b, &total_b));
+    uint64_t budget = c.cfg.pool_budget_bytes ? c.cfg.pool_budget_bytes : free_b / 2;
+    budget /= kBlock;
+    if (budget < 1) fail(SAGE_EINVAL, "pool budget below one block");
+    c.pool.init(budget, (size_t)std::min<uint64_t>(16384, budget));
+    ring_init(c);
+    flights_init(c);
+    tune_load(c);
+    if (const char* e = std::getenv("SAGE_TEST_FP_CONST")) {
+      c.test_fp_const = true;
+      c.test_fp_value = std::strtoull(e, nullptr, 0);
+    }
+    *out = h.release();
+  });
+}
+
+sage_status sage_close(sage_ctx* p) {
+  return guard([&] {
+    Ctx& c = ctx_of(p);
+    {
+      std::lock_guard<std::recursive_mutex> lk(c.mu);
+      (void)hipSetDevice(c.device);
+      (void)hipDeviceSynchronize();
+      flights_destroy(c);
+      for (auto& kv : c.fns) {
+        (void)hipFree(kv.second->d_table);
+        if (kv.second->ready) (void)hipEventDestroy(kv.second->ready);
+      }
+      c.fns.clear();
+      c.invs.clear();
+      c.cache.release_all();
+      c.pool.destroy();
+      ring_destroy(c);
+      for (auto& kv : c.modules) (void)hipModuleUnload(kv.second->mod);
+      c.modules.clear();
+      for (auto& kv : c.pinned) (void)hipHostFree(kv.first);
+      c.pinned.clear();
+      c.timer.destroy();
+      for (hipStream_t s : c.streams) (void)hipStreamDestroy(s);
+      (void)hipStreamDestroy(c.ctl);
+    }
+    delete p;
+  });
+}
+
+void* sage_host_alloc(sage_ctx* p, size_t n) {
+  void* out = nullptr;
+  const sage_status st = guard([&] {
+    Ctx& c = ctx_of(p);
+    std::lock_guard<std::recursive_mutex> lk(c.mu);
+    HIPX(hipHostMalloc(&out, n ? n : 1, hipHostMallocDefault));
+    c.pinned[out] = n;
+  });
+  return st == SAGE_OK ? out : nullptr;
+}
+
+void sage_host_free(sage_ctx* p, void* q) {
+  (void)guard([&] {
+    Ctx& c = ctx_of(p);
+    std::lock_guard<std::recursive_mutex> lk(c.mu);
+    auto it = c.pinned.find(q);
+    if (it == c.pinned.end()) return;
+    c.pinned.erase(it);
+    HIPX(hipHostFree(q));
+  });
+}
+
+// ------------------------------------------------------------- functions
+sage_status fn_register(sage_ctx* p, const sage_fn_desc* desc, const sage_blob* blobs, size_t n_blobs,
+                        sage_fn* out) {
+  return guard([&] {
+    Ctx& c = ctx_of(p);
+    if (!desc || !out) fail(SAGE_EINVAL, "null argument");
+    std::lock_guard<std::recursive_mutex> lk(c.mu);
+    HIPX(hipSetDevice(c.device));
+    validate(*desc, blobs, n_blobs);
+    auto f = std::make_unique<Fn>();
+    f->id = c.next_id++;
+    f->d = *desc;
+    uint32_t first = 0;
+    for (size_t i = 0; i < n_blobs; i++) {
+      const sage_blob& b = blobs[i];
+      const bool dev = b.where == SAGE_SRC_DEVICE;
+      f->srcs.push_back(Src{(const uint8_t*)b.src, b.nbytes, dev, !dev && c.is_pinned(b.src, b.nbytes)});
+      f->blob_first.push_back(first);
+      first += (uint32_t)((b.nbytes + kBlock - 1) / kBlock);
+      f->ro_bytes += b.nbytes;
+    }
+    f->n_blocks = first;
+    HIPX(hipEventCreateWithFlags(&f->ready, hipEventDisableTiming));
+    Fn& F = *f;
+    // code branch: module + block table; data branch: the blobs
+    auto code = [&] {
+      F.mod = load_module(c, F.d.kind);
+      if (c.cfg.share) {
+        HIPX(hipSetDevice(c.device));
+        HIPX(hipMalloc((void**)&F.d_table, std::max<size_t>(8, (size_t)F.n_blocks * 8)));
+      }
+    };
+    auto data = [&] {
+      if (c.cfg.share) register_shared(c, F);
+    };
+    try {
+      run_two_branches(code, data, c.cfg.serial_setup != 0);
+      if (c.cfg.share) refresh_table(c, F);
+      HIPX(hipEventRecord(F.ready, c.ctl));
+    } catch (...) {
+      if (F.d_table) (void)hipFree(F.d_table);
+      (void)hipEventDestroy(F.ready);
+      throw;
+    }
+    c.logical += F.ro_bytes;
+    c.registrations++;
+    *out = F.id;
+    c.fns[F.id] = std::move(f);
+  });
+}
+
+sage_status fn_unregister(sage_ctx* p, sage_fn id) {
+  return guard([&] {
+    Ctx& c = ctx_of(p);
+    std::lock_guard<std::recursive_mutex> lk(c.mu);
+    Fn& f = fn_of(c, id);
+    if (f.live > 0) fail(SAGE_EBUSY, "function has %d live setups", f.live);
+    for (size_t i = 0; i < c.flights.size(); i++) finish_flight(c, (int)i);
+    Pool& P = c.pool;
+    for (uint32_t cl : f.cls) P.cls[cl].members--;
+    for (uint32_t cl : f.distinct)
+      if (P.cls[cl].members == 0) P.drop_class(cl);
+    c.logical -= f.ro_bytes;
+    (void)hipFree(f.d_table);
+    (void)hipEventDestroy(f.ready);
+    c.fns.erase(id);
+  });
+}
+
+sage_status fn_setup(sage_ctx* p, sage_fn id, uint32_t batch, sage_inv* out) {
+  return guard([&] {
+    Ctx& c = ctx_of(p);
+    if (!out) fail(SAGE_EINVAL, "null output");
+    if (batch < 1) fail(SAGE_EINVAL, "batch must be >= 1");
+    std::lock_guard<std::recursive_mutex> lk(c.mu);
+    HIPX(hipSetDevice(c.device));
+    Fn& f = fn_of(c, id);
+    auto v = std::make_unique<Inv>();
+    v->id = c.next_id++;
+    v->fn = &f;
+    v->batch = batch;
+    if (c.cfg.share) {
+      Pool& P = c.pool;
+      std::vector<uint32_t> missing;
+      for (uint32_t cl : f.distinct)
+        if (P.cls[cl].slot == kNone) missing.push_back(cl);
+      if (!missing.empty()) {
+        // admission: all missing classes need slots; evict only if enough can be freed
+        const uint64_t free_slots = P.budget > P.used_ ? P.budget - P.used_ : 0;
+        if (missing.size() > free_slots) {
+          std::unordered_set<uint32_t> mine(f.distinct.begin(), f.distinct.end());
+          std::vector<uint32_t> victims;
+          const uint64_t short_by = missing.size() - free_slots;
+          for (uint32_t cl : P.lru) {
+            if (victims.size() >= short_by) break;
+            if (!mine.count(cl)) victims.push_back(cl);
+          }
+          if (victims.size() < short_by)
+            fail(SAGE_ENOMEM, "cannot admit: %zu blocks missing, %llu evictable", missing.size(),
+                 (unsigned long long)(free_slots + victims.size()));
+          for (uint32_t cl : victims) P.evict(cl);
+        }
+        reload_classes(c, f, missing);
+      }
+      refresh_table(c, f);
+      for (uint32_t cl : f.distinct) {
+        Class& k = P.cls[cl];
+        if (k.rc == 0) P.lru_remove(cl);
+        k.rc++;
+      }
+    } else {
+      // private copy of the read-only data for this invocation
+      const size_t bytes = (size_t)f.n_blocks * kBlock;
+      v->priv = c.cache.get(bytes);
+      v->priv_table = (uint64_t*)c.cache.get((size_t)f.n_blocks * 8);
+      try {
+        copy_private(c, f, (uint8_t*)v->priv, c.ctl);
+        std::vector<uint64_t> t(f.n_blocks);
+        for (uint32_t b = 0; b < f.n_blocks; b++) t[b] = (uint64_t)((uint8_t*)v->priv + (uint64_t)b * kBlock);
+        HIPX(hipMemcpyAsync(v->priv_table, t.data(), t.size() * 8, hipMemcpyHostToDevice, c.ctl));
+        HIPX(hipStreamSynchronize(c.ctl));
+      } catch (...) {
+        free_inv_buffers(c, *v);
+        throw;
+      }
+    }
+    v->live = true;
+    f.live++;
+    *out = v->id;
+    c.invs[v->id] = std::move(v);
+  });
+}
+
+sage_status fn_release(sage_ctx* p, sage_inv id) {
+  return guard([&] {
+    Ctx& c = ctx_of(p);
+    std::lock_guard<std::recursive_mutex> lk(c.mu);
+    Inv& v = inv_of(c, id);
+    Fn& f = *v.fn;
+    if (c.cfg.share) {
+      Pool& P = c.pool;
+      for (uint32_t cl : f.distinct) {
+        Class& k = P.cls[cl];
+        if (k.rc == 0) fail(SAGE_ESTATE, "reference count underflow");
+        if (--k.rc == 0) P.lru_back(cl);
+      }
+    }
+    free_inv_buffers(c, v);
+    v.live = false;
+    f.live--;
+  });
+}
+
+static void run_calls(Ctx& c, const std::vector<Call>& calls, uint32_t io) {
+  // partition: MLPs by (kind, width, layers); stencils by coefficient table
+  using Key = std::tuple<uint32_t, uint32_t, uint32_t, const void*>;
+  std::vector<std::vector<Call>> parts;
+  std::vector<Key> keys;
+  for (const Call& cl : calls) {
+    const sage_fn_desc& d = cl.inv->fn->d;
+    const Key k = d.kind == SAGE_STENCIL7_F32 ? Key{d.kind, 0u, 0u, (const void*)cl.inv->table()}
+                                              : Key{d.kind, d.width, d.layers, nullptr};
+    size_t i = 0;
+    while (i < keys.size() && keys[i] != k) i++;
+    if (i == keys.size()) {
+      keys.push_back(k);
+      parts.emplace_back();
+    }
+    parts[i].push_back(cl);
+  }
+  std::vector<int> used;
+  for (auto& part : parts) {
+    const int fl = part[0].inv->fn->d.kind == SAGE_STENCIL7_F32 ? launch_stencil_group(c, part, io)
+                                                                  : launch_mlp_group(c, part, io);
+    used.push_back(fl);
+  }
+  for (int fl : used) finish_flight(c, fl);
+  c.invocations += calls.size();
+}
+
+sage_status fn_invoke(sage_ctx* p, sage_inv id, const void* in, size_t in_bytes, void* out, size_t out_bytes,
+                      uint32_t io) {
+  return fn_invoke_batch(p, 1, &id, &in, &in_bytes, &out, &out_bytes, io);
+}
+
+sage_status fn_invoke_batch(sage_ctx* p, size_t n, const sage_inv* ids, const void* const* in,
+                            const size_t* in_bytes, void* const* out, const size_t* out_bytes, uint32_t io) {
+  return guard([&] {
+    Ctx& c = ctx_of(p);
+    if (n == 0) return;
+    if (!ids || !in || !in_bytes || !out || !out_bytes) fail(SAGE_EINVAL, "null argument");
+    std::lock_guard<std::recursive_mutex> lk(c.mu);
+    HIPX(hipSetDevice(c.device));
+    std::vector<Call> calls;
+    std::unordered_set<uint64_t> seen;
+    for (size_t i = 0; i < n; i++) {
+      Inv& v = inv_of(c, ids[i]);
+      if (!seen.insert(ids[i]).second) fail(SAGE_EINVAL, "invocation %llu listed twice", (unsigned long long)ids[i]);
+      const sage_fn_desc& d = v.fn->d;
+      if (in_bytes[i] != in_bytes_for(d, v.batch) || out_bytes[i] != out_bytes_for(d, v.batch))
+        fail(SAGE_EINVAL, "call %zu: in/out bytes %zu/%zu, expected %zu/%zu", i, in_bytes[i], out_bytes[i],
+             in_bytes_for(d, v.batch), out_bytes_for(d, v.batch));
+      if (!in[i] || !out[i]) fail(SAGE_EINVAL, "call %zu: null buffer", i);
+      if (io & SAGE_IO_DEVICE_IN) check_aligned(in[i], "device input");
+      if (io & SAGE_IO_DEVICE_OUT) check_aligned(out[i], "device output");
+      calls.push_back(Call{&v, in[i], in_bytes[i], out[i], out_bytes[i]});
+    }
+    run_calls(c, calls, io);
+  });
+}
+
+// ---------------------------------------------------------- introspection
+sage_status sage_get_stats(sage_ctx* p, sage_stats* out) {
+  return guard([&] {
+    Ctx& c = ctx_of(p);
+    if (!out) fail(SAGE_EINVAL, "null output");
+    std::lock_guard<std::recursive_mutex> lk(c.mu);
+    std::memset(out, 0, sizeof *out);
+    const Pool& P = c.pool;
+    for (const Class& k : P.cls) {
+      if (!k.alive) continue;
+      out->classes++;
+      out->unique_bytes += k.len;
+      if (k.members >= 2) out->shared_bytes += (uint64_t)k.len * k.members;
+      else out->private_bytes += (uint64_t)k.len * k.members;
+      if (k.slot != kNone) {
+        out->resident_bytes += k.len;
+        out->resident_slots++;
+      }
+      out->refcount_sum += k.rc;
+    }
+    out->logical_bytes = c.logical;
+    out->budget_slots = P.budget;
+    out->h2d_bytes = c.h2d;
+    for (auto& kv : c.invs) out->live_setups += kv.second->live ? 1 : 0;
+    out->evictions = P.evictions;
+    out->reloads = c.reloads;
+    out->registrations = c.registrations;
+    out->invocations = c.invocations;
+    out->verify_mismatches = c.mismatches;
+    out->workspace_bytes = c.cache.in_use();
+  });
+}
+
+sage_status sage_fn_fingerprints(sage_ctx* p, sage_fn id, uint64_t* out, size_t n) {
+  return guard([&] {
+    Ctx& c = ctx_of(p);
+    std::lock_guard<std::recursive_mutex> lk(c.mu);
+    Fn& f = fn_of(c, id);
+    if (!c.cfg.share) fail(SAGE_ESTATE, "fingerprints exist only with sharing on");
+    if (n != f.n_blocks || (!out && n)) fail(SAGE_EINVAL, "need %u entries", f.n_blocks);
+    std::copy(f.fps.begin(), f.fps.end(), out);
+  });
+}
+
+sage_status sage_fn_block_count(sage_ctx* p, sage_fn id, size_t* out) {
+  return guard([&] {
+    Ctx& c = ctx_of(p);
+    std::lock_guard<std::recursive_mutex> lk(c.mu);
+    if (!out) fail(SAGE_EINVAL, "null output");
+    *out = fn_of(c, id).n_blocks;
+  });
+}
+
+sage_status sage_fn_block_info(sage_ctx* p, sage_fn id, uint32_t* cls, uint32_t* slot, uint32_t* refs, size_t n) {
+  return guard([&] {
+    Ctx& c = ctx_of(p);
+    std::lock_guard<std::recursive_mutex> lk(c.mu);
+    Fn& f = fn_of(c, id);
+    if (!c.cfg.share) fail(SAGE_ESTATE, "block classes exist only with sharing on");
+    if (n != f.n_blocks) fail(SAGE_EINVAL, "need %u entries", f.n_blocks);
+    for (uint32_t b = 0; b < f.n_blocks; b++) {
+      const Class& k = c.pool.cls[f.cls[b]];
+      if (cls) cls[b] = f.cls[b];
+      if (slot) slot[b] = k.slot;
+      if (refs) refs[b] = k.rc;
+    }
+  });
+}
+
+sage_status sage_read_slot(sage_ctx* p, uint32_t slot, void* host) {
+  return guard([&] {
+    Ctx& c = ctx_of(p);
+    std::lock_guard<std::recursive_mutex> lk(c.mu);
+    if (!host) fail(SAGE_EINVAL, "null output");
+    bool found = false;
+    for (const Class& k : c.pool.cls) found |= k.alive && k.slot == slot;
+    if (!found) fail(SAGE_ENOTFOUND, "slot %u holds no class", slot);
+    HIPX(hipMemcpy(host, c.pool.addr(slot), kBlock, hipMemcpyDeviceToHost));
+  });
+}
+
+// ---------------------------------------------------- kernel entry points
+sage_status sage_fingerprint(sage_ctx* p, const void* dev, size_t nbytes, uint64_t* dev_out, void* stream) {
+  return guard([&] {
+    Ctx& c = ctx_of(p);
+    if (nbytes && (!dev || !dev_out)) fail(SAGE_EINVAL, "null buffer");
+    check_aligned(dev, "data");
+    check_aligned(dev_out, "output");
+    if ((nbytes + kBlock - 1) / kBlock > 0xFFFFFFFFull) fail(SAGE_EINVAL, "too many blocks");
+    hipStream_t s = stream ? (hipStream_t)stream : c.ctl;
+    const int tok = c.timer.start("fp64k", s, 1);
+    HIPX(launch_fp64k(dev, nbytes, dev_out, c.max_groups_stream(), s));
+    c.timer.stop(tok, s);
+  });
+}
+
+sage_status sage_blkcopy(sage_ctx* p, const sage_blk_op* ops, size_t n, uint32_t* result, void* stream) {
+  return guard([&] {
+    Ctx& c = ctx_of(p);
+    if (n && (!ops || !result)) fail(SAGE_EINVAL, "null buffer");
+    if (n > 0xFFFFFFFFull) fail(SAGE_EINVAL, "too many operations");
+    hipStream_t s = stream ? (hipStream_t)stream : c.ctl;
+    const int tok = c.timer.start("blkcopy", s, 1);
+    HIPX(launch_blkcopy(reinterpret_cast<const BlkOp*>(ops), (uint32_t)n, result, c.max_groups_stream(), s));
+    c.timer.stop(tok, s);
+  });
+}
+
+// ------------------------------------------------------------------ timing
+sage_status sage_timing_enable(sage_ctx* p, int on) {
+  return guard([&] {
+    Ctx& c = ctx_of(p);
+    std::lock_guard<std::recursive_mutex> lk(c.mu);
+    c.timer.on = on != 0;
+  });
+}
+
+sage_status sage_timing_get(sage_ctx* p, const char* kernel, double* total_ms, uint64_t* launches) {
+  return guard([&] {
+    Ctx& c = ctx_of(p);
+    if (!kernel || !total_ms || !launches) fail(SAGE_EINVAL, "null argument");
+    std::lock_guard<std::recursive_mutex> lk(c.mu);
+    c.timer.get(kernel, total_ms, launches);
+  });
+}
+
+sage_status sage_timing_reset(sage_ctx* p) {
+  return guard([&] {
+    Ctx& c = ctx_of(p);
+    std::lock_guard<std::recursive_mutex> lk(c.mu);
+    c.timer.reset();
+  });
+}
+
+}  // extern "C"

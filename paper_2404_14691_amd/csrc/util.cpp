@@ -1,0 +1,227 @@
+// Errors, device-memory cache, event timing and the two-branch setup
+// orchestrator.
+#include <chrono>
+#include <cstdarg>
+#include <cstring>
+
+#include "internal.h"
+
+namespace sage {
+
+static thread_local std::string t_last_error;
+
+void set_last_error(const std::string& msg) { t_last_error = msg; }
+const std::string& last_error() { return t_last_error; }
+
+void fail(sage_status st, const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  throw Error{st, buf};
+}
+
+void hip_check(hipError_t e, const char* what, const char* file, int line) {
+  if (e != hipSuccess) fail(SAGE_EHIP, "%s: %s (%s:%d)", what, hipGetErrorString(e), file, line);
+}
+
+sage_status guard(const std::function<void()>& body) {
+  try {
+    body();
+    return SAGE_OK;
+  } catch (const Error& e) {
+    set_last_error(e.msg);
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    set_last_error("host allocation failed");
+    return SAGE_ENOMEM;
+  } catch (const std::exception& e) {
+    set_last_error(e.what());
+    return SAGE_EINVAL;
+  }
+}
+
+// ------------------------------------------------------------ DevCache
+size_t DevCache::round(size_t n) {
+  if (n <= (1u << 20)) {
+    size_t r = 4096;
+    while (r < n) r <<= 1;
+    return r;
+  }
+  const size_t mb = 1u << 20;
+  return (n + mb - 1) / mb * mb;
+}
+
+void* DevCache::get(size_t n) {
+  const size_t r = round(n ? n : 1);
+  auto it = free_.find(r);
+  void* p = nullptr;
+  if (it != free_.end() && !it->second.empty()) {
+    p = it->second.back();
+    it->second.pop_back();
+  } else {
+    hipError_t e = hipMalloc(&p, r);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      // give cached blocks back to HIP and retry once
+      for (auto& kv : free_)
+        for (void* q : kv.second) {
+          (void)hipFree(q);
+          held_ -= kv.first;
+        }
+      free_.clear();
+      e = hipMalloc(&p, r);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(SAGE_ENOMEM, "device allocation of %zu bytes failed", r);
+      }
+    }
+    held_ += r;
+  }
+  live_[p] = r;
+  in_use_ += r;
+  return p;
+}
+
+void DevCache::put(void* p) {
+  if (!p) return;
+  auto it = live_.find(p);
+  if (it == live_.end()) return;
+  free_[it->second].push_back(p);
+  in_use_ -= it->second;
+  live_.erase(it);
+}
+
+void DevCache::release_all() {
+  for (auto& kv : free_)
+    for (void* q : kv.second) (void)hipFree(q);
+  for (auto& kv : live_) (void)hipFree(kv.first);
+  free_.clear();
+  live_.clear();
+  held_ = in_use_ = 0;
+}
+
+// ---------------------------------------------------------- KernelTimer
+int KernelTimer::start(const char* name, hipStream_t s, uint32_t launches) {
+  if (!on) return -1;
+  int tok = -1;
+  for (size_t i = 0; i < pairs_.size(); i++)
+    if (!pairs_[i].busy) {
+      tok = (int)i;
+      break;
+    }
+  if (tok < 0) {
+    Pair p{};
+    HIPX(hipEventCreate(&p.a));
+    HIPX(hipEventCreate(&p.b));
+    pairs_.push_back(p);
+    tok = (int)pairs_.size() - 1;
+  }
+  Pair& p = pairs_[tok];
+  p.busy = true;
+  p.name = name;
+  p.launches = launches;
+  HIPX(hipEventRecord(p.a, s));
+  return tok;
+}
+
+void KernelTimer::stop(int tok, hipStream_t s) {
+  if (tok < 0) return;
+  HIPX(hipEventRecord(pairs_[tok].b, s));
+}
+
+void KernelTimer::collect() {
+  for (auto& p : pairs_) {
+    if (!p.busy) continue;
+    if (hipEventQuery(p.b) != hipSuccess) {
+      (void)hipGetLastError();
+      continue;
+    }
+    float ms = 0.f;
+    HIPX(hipEventElapsedTime(&ms, p.a, p.b));
+    auto& a = acc_[p.name];
+    a.first += ms;
+    a.second += p.launches;
+    p.busy = false;
+  }
+}
+
+void KernelTimer::reset() {
+  collect();
+  acc_.clear();
+}
+
+bool KernelTimer::get(const std::string& name, double* ms, uint64_t* n) {
+  collect();
+  auto it = acc_.find(name);
+  if (it == acc_.end()) {
+    *ms = 0;
+    *n = 0;
+    return false;
+  }
+  *ms = it->second.first;
+  *n = it->second.second;
+  return true;
+}
+
+void KernelTimer::destroy() {
+  for (auto& p : pairs_) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  pairs_.clear();
+}
+
+// ------------------------------------------------------ setup branches
+// Parallelized function setup: the code branch (module load, allocation)
+// and the data branch run at the same time; compute starts when both are
+// done.  With `serial`, code first, then data (the one-after-the-other
+// baseline).  An error in either branch is rethrown after both finished.
+void run_two_branches(const std::function<void()>& code, const std::function<void()>& data, bool serial) {
+  if (serial) {
+    code();
+    data();
+    return;
+  }
+  std::exception_ptr code_err;
+  std::thread th([&] {
+    try {
+      code();
+    } catch (...) {
+      code_err = std::current_exception();
+    }
+  });
+  std::exception_ptr data_err;
+  try {
+    data();
+  } catch (...) {
+    data_err = std::current_exception();
+  }
+  th.join();
+  if (data_err) std::rethrow_exception(data_err);
+  if (code_err) std::rethrow_exception(code_err);
+}
+
+}  // namespace sage
+
+using namespace sage;
+
+extern "C" sage_status sage_selftest_setup_overlap(double load_ms, double host_ms, double copy_ms, int serial,
+                                                   double* measured_ms) {
+  return guard([&] {
+    if (!measured_ms || load_ms < 0 || host_ms < 0 || copy_ms < 0) fail(SAGE_EINVAL, "bad arguments");
+    auto sleep_ms = [](double ms) {
+      std::this_thread::sleep_for(std::chrono::microseconds((long long)(ms * 1000.0)));
+    };
+    const auto t0 = std::chrono::steady_clock::now();
+    run_two_branches([&] { sleep_ms(load_ms); },
+                     [&] {
+                       sleep_ms(host_ms);
+                       sleep_ms(copy_ms);
+                     },
+                     serial != 0);
+    const auto t1 = std::chrono::steady_clock::now();
+    *measured_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  });
+}

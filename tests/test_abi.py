@@ -1,0 +1,63 @@
+"""CPU checks of the C ABI library: it loads, it exports every function the
+header declares, and its setup orchestrator overlaps the two setup branches
+the way the Table 4 model says (no GPU needed)."""
+import json
+import os
+import re
+
+import pytest
+
+from oracle import setup_model as SM
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sage.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = set(re.findall(r"\b((?:sage|fn)_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    import ctypes
+    from paper_2404_14691_amd import sage as S
+    lib = ctypes.CDLL(S.LIB_PATH)
+    declared = _declared()
+    assert len(declared) >= 20
+    missing = [n for n in declared if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(declared) == set(S.EXPORTED)
+
+
+def test_code_objects_built():
+    from paper_2404_14691_amd import sage as S
+    for name in ("sage_mlp.hsaco", "sage_stencil.hsaco"):
+        assert os.path.getsize(os.path.join(S.LIB_DIR, name)) > 1000
+
+
+TABLE = json.load(open(os.path.join(ROOT, "tests", "golden", "table4_resnet50.json")))
+
+
+@pytest.mark.parametrize("col", ["stage3", "stage4", "cold"])
+def test_setup_overlap_matches_table4_model(col):
+    """The orchestrator's code branch (GPU context / code load) and data branch
+    (CPU data then GPU data) overlap: measured setup ~ max, not sum.  Stage
+    times are Table 4's, scaled to 1/4 ms per printed ms."""
+    from paper_2404_14691_amd import sage as S
+    s = TABLE["columns"][col]
+    k = 0.25
+    got = S.sage_selftest_setup_overlap(s["gpu_ctx"] * k, s["cpu_data"] * k, s["gpu_data"] * k, False)
+    want = (SM.parallel_setup(s) - s["cpu_ctx"]) * k
+    assert want - 1 <= got <= want + 25
+    serial = S.sage_selftest_setup_overlap(s["gpu_ctx"] * k, s["cpu_data"] * k, s["gpu_data"] * k, True)
+    want_serial = (SM.serial_setup(s) - s["cpu_ctx"]) * k
+    assert want_serial - 1 <= serial <= want_serial + 25
+
+
+def test_selftest_rejects_bad_arguments():
+    from paper_2404_14691_amd import sage as S
+    with pytest.raises(S.SageError) as e:
+        S.sage_selftest_setup_overlap(-1, 0, 0, False)
+    assert e.value.status == S.SAGE_EINVAL

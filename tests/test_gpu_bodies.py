@@ -1,0 +1,174 @@
+"""Parity of the function bodies run through fn_invoke / fn_invoke_batch:
+BF16 and FP32 MLPs and the 7-point stencil against the float64 oracle, exact
+special cases, and the invariants shared == private and grouped == solo."""
+import torch  # noqa: F401  (imported at collection: the first import on a fresh box is slow)
+import numpy as np
+import pytest
+
+from oracle import mlp as OM
+from oracle import stencil as OS
+from paper_2404_14691_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+BF16_TOL = 2e-2
+F32_TOL = 1e-5
+
+
+def _bf16_fn(S, ctx, layers, width, seed=0):
+    w = synth.shared_mlp_bf16_functions(n_fns=1, layers=layers, width=width, share_frac=0.0, seed=seed)
+    blob = w.blobs[0]
+    fn = S.fn_register(ctx, S.mlp_desc(S.SAGE_MLP_BF16, layers, width), [S.make_blob(blob)])
+    return fn, blob
+
+
+def _run(S, ctx, fn, xs, width, batch_call=True, io=0, torch=None):
+    invs = [S.fn_setup(ctx, fn, x.shape[0]) for x in xs]
+    ys = [np.zeros((x.shape[0], width), dtype=np.float32) for x in xs]
+    if io:
+        dx = [torch.from_numpy(x).cuda() for x in xs]
+        dy = [torch.zeros((x.shape[0], width), dtype=torch.float32, device="cuda") for x in xs]
+        torch.cuda.synchronize()
+        S.fn_invoke_batch(ctx, invs, [(t.data_ptr(), t.numel() * t.element_size()) for t in dx],
+                          [(t.data_ptr(), t.numel() * 4) for t in dy], io)
+        ys = [t.cpu().numpy() for t in dy]
+    elif batch_call:
+        S.fn_invoke_batch(ctx, invs, xs, ys)
+    else:
+        for inv, x, y in zip(invs, xs, ys):
+            S.fn_invoke(ctx, inv, x, y)
+    for inv in invs:
+        S.fn_release(ctx, inv)
+    return ys
+
+
+BATCHES = [1, 7, 16, 33, 100]
+
+
+def test_bf16_mlp_ragged_group_vs_oracle(sage_ctx_factory, torch_cuda):
+    from paper_2404_14691_amd import sage as S
+    ctx = sage_ctx_factory()
+    layers, width = 3, 256
+    fn, blob = _bf16_fn(S, ctx, layers, width)
+    xs = [synth.bf16_inputs(b, width, 0, i) for i, b in enumerate(BATCHES)]
+    ys = _run(S, ctx, fn, xs, width)
+    W = OM.bf16_to_f64(blob).reshape(layers, width, width)
+    for x, y in zip(xs, ys):
+        ref = OM.mlp_forward(OM.bf16_to_f64(x), W)
+        assert OM.normwise_error(y, ref) <= BF16_TOL
+        # the GPU rounds hidden layers to BF16: it must sit much closer to the mirror
+        assert OM.normwise_error(y, OM.mlp_forward_mirror(OM.bf16_to_f64(x), W)) <= 2e-3
+
+
+def test_bf16_grouped_equals_solo_and_device_io(sage_ctx_factory, torch_cuda):
+    from paper_2404_14691_amd import sage as S
+    ctx = sage_ctx_factory()
+    layers, width = 2, 512
+    fn, _ = _bf16_fn(S, ctx, layers, width, seed=1)
+    xs = [synth.bf16_inputs(b, width, 1, i) for i, b in enumerate(BATCHES)]
+    grouped = _run(S, ctx, fn, xs, width, batch_call=True)
+    solo = _run(S, ctx, fn, xs, width, batch_call=False)
+    dev = _run(S, ctx, fn, xs, width, io=S.SAGE_IO_DEVICE_IN | S.SAGE_IO_DEVICE_OUT, torch=torch_cuda)
+    for g, s, d in zip(grouped, solo, dev):
+        assert np.array_equal(g, s)
+        assert np.array_equal(g, d)
+
+
+def test_bf16_shared_equals_private_and_eager(sage_ctx_factory, torch_cuda):
+    from paper_2404_14691_amd import sage as S
+    layers, width = 3, 256
+    xs = [synth.bf16_inputs(b, width, 2, i) for i, b in enumerate(BATCHES)]
+    outs = []
+    for over in ({}, {"share": 0}, {"batch": 0}):
+        ctx = sage_ctx_factory(**over)
+        fn, _ = _bf16_fn(S, ctx, layers, width, seed=2)
+        outs.append(_run(S, ctx, fn, xs, width))
+    for a, b, c in zip(*outs):
+        assert np.array_equal(a, b)
+        assert np.array_equal(a, c)
+
+
+def test_bf16_permutation_weights_exact(sage_ctx_factory, torch_cuda):
+    """Permutation-matrix weights: every output is one input value, passed
+    through ReLU: the block-table indexing and the MFMA fragment layout must
+    put every element in its place, bit for bit."""
+    from paper_2404_14691_amd import sage as S
+    ctx = sage_ctx_factory()
+    layers, width = 3, 256
+    rng = np.random.default_rng(0)
+    perms = [rng.permutation(width) for _ in range(layers)]
+    W = np.zeros((layers, width, width), dtype=np.uint16)
+    for l, p in enumerate(perms):
+        W[l, np.arange(width), p] = 0x3F80                       # bf16 1.0
+    fn = S.fn_register(ctx, S.mlp_desc(S.SAGE_MLP_BF16, layers, width), [S.make_blob(W.reshape(-1))])
+    xs = [synth.bf16_inputs(b, width, 3, i) for i, b in enumerate([3, 40])]
+    ys = _run(S, ctx, fn, xs, width)
+    for x, y in zip(xs, ys):
+        ref = OM.mlp_forward(OM.bf16_to_f64(x), OM.bf16_to_f64(W))
+        assert np.array_equal(y.astype(np.float64), ref)
+
+
+def test_f32_mlp_vs_oracle(sage_ctx_factory, torch_cuda):
+    from paper_2404_14691_amd import sage as S
+    ctx = sage_ctx_factory()
+    wl = synth.mlp_f32_workload(width=256, layers=2, batch=8, invocations=3, seed=4)
+    fn = S.fn_register(ctx, S.mlp_desc(S.SAGE_MLP_F32, 2, 256), [S.make_blob(wl.weights.reshape(-1))])
+    xs = wl.inputs + [np.random.default_rng(1).standard_normal((13, 256)).astype(np.float32)]
+    ys = _run(S, ctx, fn, xs, 256)
+    for x, y in zip(xs, ys):
+        assert OM.normwise_error(y, OM.mlp_forward(x, wl.weights)) <= F32_TOL
+    solo = _run(S, ctx, fn, xs, 256, batch_call=False)
+    for a, b in zip(ys, solo):
+        assert np.array_equal(a, b)
+
+
+def test_f32_mlp_full_size_sixteen_invocations(sage_ctx_factory, torch_cuda):
+    """2-layer FP32 MLP of width 2048, 16 sequential invocations of 8 rows,
+    each with its own input: every output element vs the float64 oracle."""
+    from paper_2404_14691_amd import sage as S
+    ctx = sage_ctx_factory(share=0)
+    wl = synth.mlp_f32_workload()
+    fn = S.fn_register(ctx, S.mlp_desc(S.SAGE_MLP_F32, 2, 2048), [S.make_blob(wl.weights.reshape(-1))])
+    for x in wl.inputs:
+        inv = S.fn_setup(ctx, fn, 8)
+        y = np.zeros((8, 2048), dtype=np.float32)
+        S.fn_invoke(ctx, inv, x, y)
+        S.fn_release(ctx, inv)
+        assert OM.normwise_error(y, OM.mlp_forward(x, wl.weights)) <= F32_TOL
+    assert S.sage_get_stats(ctx)["h2d_bytes"] == 16 * wl.weights.nbytes
+
+
+@pytest.mark.parametrize("shape,sweeps", [((18, 20, 32), 5), ((9, 7, 64), 4), ((5, 3, 128), 1), ((6, 6, 16), 0)])
+def test_stencil_vs_oracle(sage_ctx_factory, torch_cuda, shape, sweeps):
+    from paper_2404_14691_amd import sage as S
+    ctx = sage_ctx_factory()
+    nz, ny, nx = shape
+    c = synth.stencil_coefficients(0, seed=1, shape=shape)
+    fn = S.fn_register(ctx, S.stencil_desc(nx, ny, nz, sweeps), [S.make_blob(c)])
+    fields = [np.stack([synth.stencil_field(0, 10 * i + j, seed=1, shape=shape) for j in range(b)])
+              for i, b in enumerate([3, 1])]
+    invs = [S.fn_setup(ctx, fn, f.shape[0]) for f in fields]
+    outs = [np.zeros_like(f) for f in fields]
+    S.fn_invoke_batch(ctx, invs, fields, outs)
+    for inv in invs:
+        S.fn_release(ctx, inv)
+    for f, o in zip(fields, outs):
+        for j in range(f.shape[0]):
+            ref = OS.jacobi7(f[j], c, sweeps)
+            assert OS.normwise_error(o[j], ref) <= F32_TOL
+            if sweeps == 0:
+                assert np.array_equal(o[j], f[j])
+
+
+def test_stencil_zero_coefficient_identity(sage_ctx_factory, torch_cuda):
+    from paper_2404_14691_amd import sage as S
+    ctx = sage_ctx_factory()
+    shape = (10, 12, 64)
+    c = np.zeros(shape, dtype=np.float32)
+    fn = S.fn_register(ctx, S.stencil_desc(64, 12, 10, 3), [S.make_blob(c)])
+    u = synth.stencil_field(0, 0, seed=2, shape=shape)
+    inv = S.fn_setup(ctx, fn, 1)
+    out = np.zeros_like(u)
+    S.fn_invoke(ctx, inv, u, out)
+    S.fn_release(ctx, inv)
+    assert np.array_equal(out, u)

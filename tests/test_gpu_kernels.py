@@ -1,0 +1,85 @@
+"""Parity of the data-movement kernels called through the C ABI: FP64K-v1
+fingerprints (bit-exact vs the oracle) and block COPY / VERIFY."""
+import torch  # noqa: F401  (imported at collection: the first import on a fresh box is slow)
+import numpy as np
+import pytest
+
+from oracle import fingerprint as OF
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(torch, arr):
+    return torch.from_numpy(np.ascontiguousarray(arr)).cuda()
+
+
+@pytest.mark.parametrize("nbytes", [1, 7, 8, 9, 4095, 65535, 65536, 65537, 3 * 65536 + 1000, 300 * 65536])
+def test_fingerprint_parity(sage_ctx_factory, torch_cuda, nbytes):
+    from paper_2404_14691_amd import sage as S
+    torch = torch_cuda
+    ctx = sage_ctx_factory()
+    rng = np.random.default_rng(nbytes)
+    data = rng.integers(0, 256, nbytes, dtype=np.uint8)
+    if nbytes >= 3 * 65536:
+        data[65536:2 * 65536] = 0                  # a zero block
+        data[2 * 65536:3 * 65536] = np.arange(65536) & 0xFF
+    nblk = -(-nbytes // 65536)
+    d = _dev(torch, data)
+    out = torch.zeros(nblk, dtype=torch.int64, device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    S.sage_fingerprint(ctx, d.data_ptr(), nbytes, out.data_ptr(), s)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(np.uint64)
+    assert np.array_equal(got, OF.fp64k_blob(data))
+
+
+def test_fingerprint_equal_blocks_equal_values(sage_ctx_factory, torch_cuda):
+    from paper_2404_14691_amd import sage as S
+    torch = torch_cuda
+    ctx = sage_ctx_factory()
+    rng = np.random.default_rng(9)
+    blk = rng.integers(0, 256, 65536, dtype=np.uint8)
+    data = np.concatenate([blk, blk, blk ^ np.uint8(1), blk])
+    d = _dev(torch, data)
+    out = torch.zeros(4, dtype=torch.int64, device="cuda")
+    S.sage_fingerprint(ctx, d.data_ptr(), data.size, out.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    fp = out.cpu().numpy().view(np.uint64)
+    assert fp[0] == fp[1] == fp[3] and fp[2] != fp[0]
+
+
+def test_blkcopy_copy_and_verify(sage_ctx_factory, torch_cuda):
+    from paper_2404_14691_amd import sage as S
+    torch = torch_cuda
+    ctx = sage_ctx_factory()
+    rng = np.random.default_rng(3)
+    nsrc = 6
+    src = rng.integers(0, 256, nsrc * 65536, dtype=np.uint8)
+    src[65536 + 1000] = 0x5A                       # differs from the 0xA5 fill below
+    dsrc = _dev(torch, src)
+    dst = torch.full((nsrc * 65536,), 0xA5, dtype=torch.uint8, device="cuda")
+    lens = [65536, 1000, 17, 65535, 65536, 16]
+    ops = np.zeros(nsrc, dtype=[("src", "<u8"), ("dst", "<u8"), ("len", "<u4"), ("op", "<u4")])
+    for i, L in enumerate(lens):
+        ops[i] = (dsrc.data_ptr() + i * 65536, dst.data_ptr() + ((i + 2) % nsrc) * 65536, L, S.SAGE_OP_COPY)
+    dops = _dev(torch, ops.view(np.uint8))
+    res = torch.zeros(nsrc, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    S.sage_blkcopy(ctx, dops.data_ptr(), nsrc, res.data_ptr(), stream)
+    torch.cuda.synchronize()
+    out = dst.cpu().numpy()
+    for i, L in enumerate(lens):
+        o = ((i + 2) % nsrc) * 65536
+        assert np.array_equal(out[o:o + L], src[i * 65536:i * 65536 + L])
+        assert np.all(out[o + L:o + 65536] == 0xA5)
+    # VERIFY: equal spans -> 0, a one-byte difference -> 1 (also in a short tail)
+    vops = np.zeros(4, dtype=ops.dtype)
+    vops[0] = (dsrc.data_ptr(), dst.data_ptr() + 2 * 65536, 65536, S.SAGE_OP_VERIFY)
+    vops[1] = (dsrc.data_ptr() + 65536, dst.data_ptr() + 3 * 65536, 1000, S.SAGE_OP_VERIFY)
+    vops[2] = (dsrc.data_ptr() + 65536, dst.data_ptr() + 3 * 65536, 1001, S.SAGE_OP_VERIFY)
+    vops[3] = (dsrc.data_ptr(), dst.data_ptr() + 3 * 65536, 65536, S.SAGE_OP_VERIFY)
+    dv = _dev(torch, vops.view(np.uint8))
+    res = torch.full((4,), 7, dtype=torch.int32, device="cuda")
+    S.sage_blkcopy(ctx, dv.data_ptr(), 4, res.data_ptr(), stream)
+    torch.cuda.synchronize()
+    assert res.cpu().tolist() == [0, 0, 1, 1]

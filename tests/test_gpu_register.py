@@ -1,0 +1,146 @@
+"""Parity of fn_register's data path: fingerprints, the dedup partition and
+the bytes in the pool are bit-exact against the oracle; the byte accounting
+matches its closed forms; host (pageable, pinned) and device sources agree;
+forced fingerprint collisions still give the byte-exact partition."""
+import torch  # noqa: F401  (imported at collection: the first import on a fresh box is slow)
+import os
+
+import numpy as np
+import pytest
+
+from oracle import dedup as OD
+from oracle import fingerprint as OF
+from paper_2404_14691_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+WIDTH, LAYERS = 512, 4          # 2 MiB blobs = 32 blocks
+
+
+def _blobs():
+    w = synth.shared_mlp_bf16_functions(n_fns=3, layers=LAYERS, width=WIDTH, share_frac=0.3, seed=5)
+    blobs = [b.copy() for b in w.blobs]
+    per = 65536 // 2
+    blobs[1][5 * per:6 * per] = blobs[1][2 * per:3 * per]     # duplicate inside one chunk pair
+    blobs[1][3 * per:4 * per] = blobs[1][2 * per:3 * per]     # same chunk as block 2 (chunk = 4 blocks)
+    blobs[2][7 * per:8 * per] = 0
+    blobs[0][30 * per:31 * per] = 0                           # zero block in two functions
+    blobs[2][31 * per:32 * per] = blobs[0][1 * per:2 * per]   # cross-function duplicate
+    return blobs
+
+
+def _register(S, ctx, blobs, where, torch=None, keep=None):
+    fns = []
+    for b in blobs:
+        if where == "host":
+            blob = S.make_blob(b)
+        elif where == "pinned":
+            arr = S.pinned_array(ctx, b.shape, b.dtype)
+            arr[:] = b
+            keep.append(arr)
+            blob = S.make_blob(arr)
+        else:
+            d = torch.from_numpy(b.view(np.uint8)).cuda()
+            torch.cuda.synchronize()
+            keep.append(d)
+            blob = S.make_blob(d.data_ptr(), b.nbytes, where=S.SAGE_SRC_DEVICE)
+        fns.append(S.fn_register(ctx, S.mlp_desc(S.SAGE_MLP_BF16, LAYERS, WIDTH), [blob]))
+    return fns
+
+
+def _check_against_oracle(S, ctx, fns, blobs, read_bytes=True):
+    for f, b in zip(fns, blobs):
+        assert np.array_equal(S.sage_fn_fingerprints(ctx, f), OF.fp64k_blob(b))
+    canon = OD.partition_dict(blobs, 65536)
+    lib_canon = []
+    for f in fns:
+        cls, slot, refs = S.sage_fn_block_info(ctx, f)
+        lib_canon.append([(int(c),) for c in cls])
+        assert np.all(slot != 0xFFFFFFFF) and np.all(refs == 0)
+    assert OD.same_partition(canon, lib_canon)
+    if read_bytes:
+        for f, b in zip(fns, blobs):
+            raw = b.view(np.uint8)
+            _, slot, _ = S.sage_fn_block_info(ctx, f)
+            for k, s in enumerate(slot):
+                assert np.array_equal(S.sage_read_slot(ctx, int(s)), raw[k * 65536:(k + 1) * 65536]), (f, k)
+    acc = OD.accounting(blobs, 65536, canon)
+    st = S.sage_get_stats(ctx)
+    assert st["logical_bytes"] == acc["logical"]
+    assert st["unique_bytes"] == acc["unique"]
+    assert st["shared_bytes"] == acc["shared"]
+    assert st["private_bytes"] == acc["private"]
+    assert st["shared_bytes"] + st["private_bytes"] == st["logical_bytes"]
+    assert st["classes"] == acc["n_classes"]
+    assert st["resident_bytes"] == acc["unique"]
+    assert st["h2d_bytes"] == acc["logical"]
+
+
+@pytest.mark.parametrize("where", ["host", "pinned", "device"])
+def test_register_partition_and_bytes(sage_ctx_factory, torch_cuda, where):
+    from paper_2404_14691_amd import sage as S
+    ctx = sage_ctx_factory(chunk_bytes=256 << 10, ring_slots=3, streams=2)
+    blobs = _blobs()
+    keep = []
+    fns = _register(S, ctx, blobs, where, torch_cuda, keep)
+    _check_against_oracle(S, ctx, fns, blobs)
+    for f in fns:
+        S.fn_unregister(ctx, f)
+    st = S.sage_get_stats(ctx)
+    assert st["classes"] == 0 and st["resident_slots"] == 0 and st["logical_bytes"] == 0
+    for a in keep:
+        if isinstance(a, np.ndarray):
+            S.sage_host_free(ctx, a.ctypes.data)
+
+
+def test_register_serial_and_unpipelined_agree(sage_ctx_factory, torch_cuda):
+    from paper_2404_14691_amd import sage as S
+    blobs = _blobs()
+    results = []
+    for over in ({"serial_setup": 1}, {"ring_slots": 1, "streams": 1, "chunk_bytes": 65536}):
+        ctx = sage_ctx_factory(**over)
+        fns = _register(S, ctx, blobs, "host")
+        _check_against_oracle(S, ctx, fns, blobs, read_bytes=False)
+        results.append([S.sage_fn_fingerprints(ctx, f) for f in fns])
+    for a, b in zip(*results):
+        assert np.array_equal(a, b)
+
+
+def test_forced_fingerprint_collisions(sage_ctx_factory, torch_cuda, monkeypatch):
+    """Every fingerprint forced to one value: only byte verification keeps
+    blocks apart, and the partition is still the byte-exact one."""
+    from paper_2404_14691_amd import sage as S
+    monkeypatch.setenv("SAGE_TEST_FP_CONST", "12345")
+    ctx = sage_ctx_factory(chunk_bytes=256 << 10, ring_slots=2)
+    monkeypatch.delenv("SAGE_TEST_FP_CONST")
+    # BF16 MLP of width 256 and 8 layers: 1 MiB = the first 16 blocks of each blob
+    blobs = [np.ascontiguousarray(b[: 8 * 256 * 256]) for b in _blobs()]
+    fns = [S.fn_register(ctx, S.mlp_desc(S.SAGE_MLP_BF16, 8, 256), [S.make_blob(b)]) for b in blobs]
+    canon = OD.partition_dict(blobs, 65536)
+    lib = [[(int(c),) for c in S.sage_fn_block_info(ctx, f)[0]] for f in fns]
+    assert OD.same_partition(canon, lib)
+    st = S.sage_get_stats(ctx)
+    assert st["verify_mismatches"] > 0
+    for f, b in zip(fns, blobs):
+        raw = b.view(np.uint8)
+        _, slot, _ = S.sage_fn_block_info(ctx, f)
+        for k, s in enumerate(slot):
+            assert np.array_equal(S.sage_read_slot(ctx, int(s)), raw[k * 65536:(k + 1) * 65536])
+
+
+def test_register_rejects_bad_layouts(sage_ctx_factory, torch_cuda):
+    from paper_2404_14691_amd import sage as S
+    ctx = sage_ctx_factory()
+    b = np.zeros(256 * 256, dtype=np.uint16)
+    with pytest.raises(S.SageError) as e:
+        S.fn_register(ctx, S.mlp_desc(S.SAGE_MLP_BF16, 2, 256), [S.make_blob(b)])
+    assert e.value.status == S.SAGE_EINVAL
+    with pytest.raises(S.SageError) as e:
+        S.fn_register(ctx, S.mlp_desc(S.SAGE_MLP_BF16, 1, 384), [S.make_blob(np.zeros(384 * 384, np.uint16))])
+    assert e.value.status == S.SAGE_EINVAL
+    with pytest.raises(S.SageError) as e:
+        S.fn_register(ctx, S.mlp_desc(S.SAGE_MLP_BF16, 1, 256), [S.make_blob(b, access=S.SAGE_RW)])
+    assert e.value.status == S.SAGE_EINVAL
+    with pytest.raises(S.SageError) as e:
+        S.fn_setup(ctx, 999999, 1)
+    assert e.value.status == S.SAGE_ENOTFOUND
