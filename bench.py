@@ -149,6 +149,46 @@ def timed(torch, fn, steps):
     return (time.perf_counter() - t0), out
 
 
+def kernel_bandwidth(S, ctx, torch, nbytes=4 << 30, reps=5):
+    """fp64k and blkcopy alone on `nbytes` (well above the 256 MB MALL), timed
+    with HIP events on the launch stream."""
+    stream = torch.cuda.current_stream().cuda_stream
+    nblk = nbytes // 65536
+    src = torch.randint(0, 256, (nbytes,), dtype=torch.uint8, device="cuda")
+    dst = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    fps = torch.empty(nblk, dtype=torch.int64, device="cuda")
+    res = torch.empty(nblk, dtype=torch.int32, device="cuda")
+    base = np.arange(nblk, dtype=np.uint64) * np.uint64(65536)
+    ops = np.zeros(nblk, dtype=[("src", "<u8"), ("dst", "<u8"), ("len", "<u4"), ("op", "<u4")])
+    ops["src"], ops["dst"], ops["len"], ops["op"] = base + np.uint64(src.data_ptr()), base + np.uint64(dst.data_ptr()), 65536, S.SAGE_OP_COPY
+    d_copy = torch.from_numpy(ops.view(np.uint8)).cuda()
+    ops["op"] = S.SAGE_OP_VERIFY
+    d_verify = torch.from_numpy(ops.view(np.uint8)).cuda()
+    torch.cuda.synchronize()
+    out = {}
+    for name, run, moved in (
+            ("fp64k", lambda: S.sage_fingerprint(ctx, src.data_ptr(), nbytes, fps.data_ptr(), stream), nbytes + 8 * nblk),
+            ("blkcopy", lambda: S.sage_blkcopy(ctx, d_copy.data_ptr(), nblk, res.data_ptr(), stream), 2 * nbytes),
+            ("blkcopy_verify", lambda: S.sage_blkcopy(ctx, d_verify.data_ptr(), nblk, res.data_ptr(), stream), 2 * nbytes)):
+        run()
+        torch.cuda.synchronize()
+        S.sage_timing_reset(ctx)
+        S.sage_timing_enable(ctx, True)
+        for _ in range(reps):
+            run()
+        torch.cuda.synchronize()
+        S.sage_timing_enable(ctx, False)
+        ms, n = S.sage_timing_get(ctx, "fp64k" if name == "fp64k" else "blkcopy")
+        avg = ms / max(n, 1)
+        out[name] = {"bytes": int(moved), "avg_ms": round(avg, 4), "GB/s": round(moved / (avg * 1e-3) / 1e9, 1),
+                     "frac_of_8TB/s": round(moved / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    if not bool((res == 0).all().item()):
+        raise RuntimeError("verify after copy reported a difference")
+    del src, dst, fps, res, d_copy, d_verify
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(wl, n_inv=8, seed=0):
     """The oracle on the host: one function's fingerprints + dedup map and
     `n_inv` of its invocations in float64; extrapolated to one step."""
@@ -184,6 +224,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-kernels", action="store_true", help="skip the standalone 4 GiB kernel bandwidth runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (this path has no "
@@ -224,6 +265,9 @@ def main():
         p_elapsed, p_res = timed(torch, lambda: plain_step(S, pctx, wl), args.plain_steps)
         setup_plain = [x for r in p_res for x in r]
         log(f"plain timed: {p_elapsed * 1e3 / args.plain_steps:.2f} ms/step")
+        standalone = None if args.no_kernels else kernel_bandwidth(S, ctx, torch)
+        if standalone:
+            log(f"standalone kernels: {standalone}")
     finally:
         S.sage_close(ctx)
         S.sage_close(pctx)
@@ -271,6 +315,7 @@ def main():
                       "GB/s": round(fp_bytes * args.steps / max(f_ms * 1e-3, 1e-12) / 1e9, 1)},
             "blkcopy": {"avg_ms": round(b_ms / max(b_n, 1), 5), "launches": b_n},
             "ggemm_bf16": {"avg_ms": round(gemm_avg_ms, 5), "launches": g_n}},
+        "kernels_standalone_4GiB": standalone,
     }
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
