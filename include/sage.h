@@ -36,6 +36,11 @@
 extern "C" {
 #endif
 
+/* The library is built with hidden visibility; only this interface is exported. */
+#if defined(__GNUC__)
+#pragma GCC visibility push(default)
+#endif
+
 typedef struct sage_ctx sage_ctx;
 typedef uint64_t sage_fn;
 typedef uint64_t sage_inv;
@@ -235,6 +240,45 @@ typedef struct {
 sage_status sage_blkcopy(sage_ctx* ctx, const sage_blk_op* dev_ops, size_t n_ops,
                          uint32_t* dev_result, void* stream);
 
+/* ---------------------------------------------------------------- serving
+ * Open-loop serving (section "Low System Throughput": Poisson arrivals;
+ * section "Multi-stage Resource Exit": warm reuse; "Other Lessons Learned":
+ * cache replacement).  One internal thread admits queued requests with
+ * fn_setup semantics (evicting unreferenced blocks, least recently released
+ * first; a request that cannot be admitted waits for releases), packs the
+ * admitted requests of one body shape (and I/O flags) into one grouped
+ * launch of at most `max_rows` rows, and keeps up to `inflight_groups`
+ * launches on the device; requests arriving meanwhile join the next launch.
+ * While the loop runs, fn_invoke / fn_invoke_batch return SAGE_ESTATE.
+ * Latencies are measured from sage_submit: setup = until admitted, e2e =
+ * until the output is in the caller's buffer. */
+typedef struct {
+  double setup_ms;
+  double e2e_ms;
+  uint32_t status; /* sage_status of the request */
+} sage_req_info;
+
+typedef struct {
+  uint64_t completed, failed, launches, rows;
+  double setup_p50_ms, setup_p99_ms; /* nearest rank */
+  double e2e_p50_ms, e2e_p99_ms;
+  double span_ms;    /* first arrival to last completion */
+  double throughput; /* completed requests per second over span_ms */
+} sage_serve_report;
+
+sage_status sage_serve_start(sage_ctx* ctx, uint32_t max_rows /* 0 = 8192 */);
+/* Drain queued and in-flight requests, then stop the loop. */
+sage_status sage_serve_stop(sage_ctx* ctx);
+/* Queue one request; in/out as for fn_invoke and owned by the caller until
+ * sage_wait returns for it. */
+sage_status sage_submit(sage_ctx* ctx, sage_fn fn, uint32_t batch, const void* in, size_t in_bytes, void* out,
+                        size_t out_bytes, uint32_t io_flags, uint64_t* req_id);
+/* Wait for a request (timeout_ms < 0: forever; EBUSY on timeout).  Returns
+ * the request's own status. */
+sage_status sage_wait(sage_ctx* ctx, uint64_t req_id, double timeout_ms, sage_req_info* info);
+sage_status sage_serve_stats(sage_ctx* ctx, sage_serve_report* out);
+sage_status sage_serve_reset_stats(sage_ctx* ctx);
+
 /* --------------------------------------------------------------- timing
  * Per-kernel device time measured with HIP events on the stream each launch
  * is issued on, accumulated while timing is on.  Names: "fp64k", "blkcopy",
@@ -251,6 +295,10 @@ sage_status sage_timing_reset(sage_ctx* ctx);
  * serial != 0 the branches run one after the other.  Needs no GPU. */
 sage_status sage_selftest_setup_overlap(double load_ms, double host_ms, double copy_ms, int serial,
                                         double* measured_ms);
+
+#if defined(__GNUC__)
+#pragma GCC visibility pop
+#endif
 
 #ifdef __cplusplus
 }

@@ -54,11 +54,11 @@ def build(verbose: bool = False) -> str:
             continue
         o = os.path.join(obj, src + ".o")
         objs.append(o)
-        jobs.append([cc, *DEVICE_FLAGS, "-fPIC", "-Wall", "-Wno-unused-result", "-c",
+        jobs.append([cc, *DEVICE_FLAGS, "-fPIC", "-fvisibility=hidden", "-Wall", "-Wno-unused-result", "-c",
                      os.path.join(CSRC, src), "-o", o])
     o = os.path.join(obj, "kernels_rt.o")
     objs.append(o)
-    jobs.append([cc, *DEVICE_FLAGS, "-fPIC", "-c", os.path.join(CSRC, "kernels_rt.hip"), "-o", o])
+    jobs.append([cc, *DEVICE_FLAGS, "-fPIC", "-fvisibility=hidden", "-c", os.path.join(CSRC, "kernels_rt.hip"), "-o", o])
     for name, src in (("sage_mlp.hsaco", "body_mlp.hip"), ("sage_stencil.hsaco", "body_stencil.hip")):
         jobs.append([cc, *DEVICE_FLAGS, "--genco", os.path.join(CSRC, src), "-o", os.path.join(LIB, name)])
     with ThreadPoolExecutor(max_workers=min(8, len(jobs))) as ex:

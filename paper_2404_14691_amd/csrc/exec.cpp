@@ -101,10 +101,16 @@ static bool ensure(uint8_t** d, uint8_t** h, size_t* cap, size_t need) {
   return true;
 }
 
-static int take_flight(Ctx& c) {
-  const int f = (int)(c.next_flight++ % c.flights.size());
+static int take_flight(Ctx& c, int want) {
+  const int f = want >= 0 ? want : (int)(c.next_flight++ % c.flights.size());
   if (c.flights[f].busy) finish_flight(c, f);
   return f;
+}
+
+int free_flight(Ctx& c) {
+  for (size_t i = 0; i < c.flights.size(); i++)
+    if (!c.flights[i].busy) return (int)i;
+  return -1;
 }
 
 void finish_flight(Ctx& c, int f) {
@@ -132,7 +138,7 @@ static void launch_kernel(hipFunction_t k, uint32_t grid, hipStream_t s, const G
 // launch covers all groups with one tile list.  Layer 0 reads the inputs
 // through a row table, the last layer writes the outputs through another;
 // hidden layers ping-pong in the flight's workspace.
-int launch_mlp_group(Ctx& c, const std::vector<Call>& calls, uint32_t io) {
+int launch_mlp_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, int flight) {
   const sage_fn_desc& d = calls[0].inv->fn->d;
   const uint32_t W = d.width, L = d.layers;
   const bool bf16 = d.kind == SAGE_MLP_BF16;
@@ -168,7 +174,7 @@ int launch_mlp_group(Ctx& c, const std::vector<Call>& calls, uint32_t io) {
     kname = "mlp_f32_layer";
   }
 
-  const int fi = take_flight(c);
+  const int fi = take_flight(c, flight);
   Flight& F = c.flights[fi];
   bool moved = false;
   moved |= ensure(&F.d_meta, &F.h_meta, &F.meta_cap, kMetaTabOff + (size_t)M * 16);
@@ -273,7 +279,7 @@ int launch_mlp_group(Ctx& c, const std::vector<Call>& calls, uint32_t io) {
 // All calls share one coefficient table.  Every field of every call is
 // swept together; the sweep's output goes to the call's output buffer on
 // the last sweep and alternates with a scratch field before it.
-int launch_stencil_group(Ctx& c, const std::vector<Call>& calls, uint32_t io) {
+int launch_stencil_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, int flight) {
   const sage_fn_desc& d = calls[0].inv->fn->d;
   const uint64_t cells = (uint64_t)d.nx * d.ny * d.nz, fbytes = cells * 4;
   const uint32_t S = d.sweeps;
@@ -281,7 +287,7 @@ int launch_stencil_group(Ctx& c, const std::vector<Call>& calls, uint32_t io) {
   for (const Call& cl : calls) nf += cl.inv->batch;
   const bool host_in = !(io & SAGE_IO_DEVICE_IN), host_out = !(io & SAGE_IO_DEVICE_OUT);
 
-  const int fi = take_flight(c);
+  const int fi = take_flight(c, flight);
   Flight& F = c.flights[fi];
   hipStream_t s = F.s;
   for (const Call& cl : calls) HIPX(hipStreamWaitEvent(s, cl.inv->fn->ready, 0));

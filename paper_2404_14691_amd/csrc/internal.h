@@ -223,6 +223,8 @@ struct Ring {
   size_t ops_cap = 0;
 };
 
+struct Serve;  // serving loop state (serve.cpp)
+
 // -------------------------------------------------------------- autotuner
 struct TuneEntry {
   std::string kernel;
@@ -252,6 +254,7 @@ struct Ctx {
   std::map<std::string, TuneEntry> tune;     // "width:bucket" -> best kernel
   // counters
   uint64_t logical = 0, h2d = 0, reloads = 0, registrations = 0, invocations = 0, mismatches = 0;
+  Serve* serve = nullptr;                    // running serving loop, if any
   bool test_fp_const = false;                // force every fingerprint equal (collision test)
   uint64_t test_fp_value = 0;
 
@@ -281,13 +284,22 @@ struct Call {
   void* out;
   size_t out_bytes;
 };
-int launch_mlp_group(Ctx& c, const std::vector<Call>& calls, uint32_t io);
-int launch_stencil_group(Ctx& c, const std::vector<Call>& calls, uint32_t io);
+// Launch a group on flight `flight` (-1: the next one, waiting if busy).
+int launch_mlp_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, int flight = -1);
+int launch_stencil_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, int flight = -1);
 void finish_flight(Ctx& c, int flight);
 void flights_init(Ctx& c);
 void flights_destroy(Ctx& c);
 std::string tuned_kernel(Ctx& c, uint32_t width, uint32_t rows);
 void tune_load(Ctx& c);
+
+uint64_t setup_internal(Ctx& c, uint64_t fn, uint32_t batch);
+void release_internal(Ctx& c, uint64_t inv);
+Fn& find_fn(Ctx& c, uint64_t id);
+Inv& find_inv(Ctx& c, uint64_t id);
+int free_flight(Ctx& c);  // index of an idle flight, or -1
+Ctx& ctx_ref(sage_ctx* p);
+void serve_destroy(Ctx& c);
 
 size_t in_elem_size(const sage_fn_desc& d);
 size_t in_bytes_for(const sage_fn_desc& d, uint32_t batch);

@@ -27,10 +27,15 @@ Fn& fn_of(Ctx& c, sage_fn id) {
   return *it->second;
 }
 
+// Released invocations leave the table; handles are never reused, so an id
+// below the next one that is not a live function was released before.
 Inv& inv_of(Ctx& c, sage_inv id) {
   auto it = c.invs.find(id);
-  if (it == c.invs.end()) fail(SAGE_ENOTFOUND, "unknown invocation handle %llu", (unsigned long long)id);
-  if (!it->second->live) fail(SAGE_ESTATE, "invocation %llu already released", (unsigned long long)id);
+  if (it == c.invs.end()) {
+    if (id != 0 && id < c.next_id && !c.fns.count(id))
+      fail(SAGE_ESTATE, "invocation %llu already released", (unsigned long long)id);
+    fail(SAGE_ENOTFOUND, "unknown invocation handle %llu", (unsigned long long)id);
+  }
   return *it->second;
 }
 
@@ -76,6 +81,92 @@ void free_inv_buffers(Ctx& c, Inv& v) {
 }
 
 }  // namespace
+
+namespace sage {
+
+// Admission and references for one invocation (see fn_setup in sage.h).
+uint64_t setup_internal(Ctx& c, uint64_t id, uint32_t batch) {
+  if (batch < 1) fail(SAGE_EINVAL, "batch must be >= 1");
+  HIPX(hipSetDevice(c.device));
+  Fn& f = fn_of(c, id);
+  auto v = std::make_unique<Inv>();
+  v->id = c.next_id++;
+  v->fn = &f;
+  v->batch = batch;
+  if (c.cfg.share) {
+    Pool& P = c.pool;
+    std::vector<uint32_t> missing;
+    for (uint32_t cl : f.distinct)
+      if (P.cls[cl].slot == kNone) missing.push_back(cl);
+    if (!missing.empty()) {
+      // admission: all missing classes need slots; evict only if enough can be freed
+      const uint64_t free_slots = P.budget > P.used_ ? P.budget - P.used_ : 0;
+      if (missing.size() > free_slots) {
+        std::unordered_set<uint32_t> mine(f.distinct.begin(), f.distinct.end());
+        std::vector<uint32_t> victims;
+        const uint64_t short_by = missing.size() - free_slots;
+        for (uint32_t cl : P.lru) {
+          if (victims.size() >= short_by) break;
+          if (!mine.count(cl)) victims.push_back(cl);
+        }
+        if (victims.size() < short_by)
+          fail(SAGE_ENOMEM, "cannot admit: %zu blocks missing, %llu evictable", missing.size(),
+               (unsigned long long)(free_slots + victims.size()));
+        for (uint32_t cl : victims) P.evict(cl);
+      }
+      reload_classes(c, f, missing);
+    }
+    refresh_table(c, f);
+    for (uint32_t cl : f.distinct) {
+      Class& k = P.cls[cl];
+      if (k.rc == 0) P.lru_remove(cl);
+      k.rc++;
+    }
+  } else {
+    // private copy of the read-only data for this invocation
+    const size_t bytes = (size_t)f.n_blocks * kBlock;
+    v->priv = c.cache.get(bytes);
+    v->priv_table = (uint64_t*)c.cache.get((size_t)f.n_blocks * 8);
+    try {
+      copy_private(c, f, (uint8_t*)v->priv, c.ctl);
+      std::vector<uint64_t> t(f.n_blocks);
+      for (uint32_t b = 0; b < f.n_blocks; b++) t[b] = (uint64_t)((uint8_t*)v->priv + (uint64_t)b * kBlock);
+      HIPX(hipMemcpyAsync(v->priv_table, t.data(), t.size() * 8, hipMemcpyHostToDevice, c.ctl));
+      HIPX(hipStreamSynchronize(c.ctl));
+    } catch (...) {
+      free_inv_buffers(c, *v);
+      throw;
+    }
+  }
+  v->live = true;
+  f.live++;
+  const uint64_t out = v->id;
+  c.invs[v->id] = std::move(v);
+  return out;
+}
+
+void release_internal(Ctx& c, uint64_t id) {
+  Inv& v = inv_of(c, id);
+  Fn& f = *v.fn;
+  if (c.cfg.share) {
+    Pool& P = c.pool;
+    for (uint32_t cl : f.distinct) {
+      Class& k = P.cls[cl];
+      if (k.rc == 0) fail(SAGE_ESTATE, "reference count underflow");
+      if (--k.rc == 0) P.lru_back(cl);
+    }
+  }
+  free_inv_buffers(c, v);
+  v.live = false;
+  f.live--;
+  c.invs.erase(id);
+}
+
+Fn& find_fn(Ctx& c, uint64_t id) { return fn_of(c, id); }
+Ctx& ctx_ref(sage_ctx* p) { return ctx_of(p); }
+Inv& find_inv(Ctx& c, uint64_t id) { return inv_of(c, id); }
+
+}  // namespace sage
 
 bool Ctx::is_pinned(const void* p, size_t n) const {
   auto it = pinned.upper_bound(const_cast<void*>(p));
@@ -148,6 +239,7 @@ sage_status sage_open(int device, const sage_config* cfg, sage_ctx** out) {
 sage_status sage_close(sage_ctx* p) {
   return guard([&] {
     Ctx& c = ctx_of(p);
+    serve_destroy(c);
     {
       std::lock_guard<std::recursive_mutex> lk(c.mu);
       (void)hipSetDevice(c.device);
@@ -269,63 +361,8 @@ sage_status fn_setup(sage_ctx* p, sage_fn id, uint32_t batch, sage_inv* out) {
   return guard([&] {
     Ctx& c = ctx_of(p);
     if (!out) fail(SAGE_EINVAL, "null output");
-    if (batch < 1) fail(SAGE_EINVAL, "batch must be >= 1");
     std::lock_guard<std::recursive_mutex> lk(c.mu);
-    HIPX(hipSetDevice(c.device));
-    Fn& f = fn_of(c, id);
-    auto v = std::make_unique<Inv>();
-    v->id = c.next_id++;
-    v->fn = &f;
-    v->batch = batch;
-    if (c.cfg.share) {
-      Pool& P = c.pool;
-      std::vector<uint32_t> missing;
-      for (uint32_t cl : f.distinct)
-        if (P.cls[cl].slot == kNone) missing.push_back(cl);
-      if (!missing.empty()) {
-        // admission: all missing classes need slots; evict only if enough can be freed
-        const uint64_t free_slots = P.budget > P.used_ ? P.budget - P.used_ : 0;
-        if (missing.size() > free_slots) {
-          std::unordered_set<uint32_t> mine(f.distinct.begin(), f.distinct.end());
-          std::vector<uint32_t> victims;
-          const uint64_t short_by = missing.size() - free_slots;
-          for (uint32_t cl : P.lru) {
-            if (victims.size() >= short_by) break;
-            if (!mine.count(cl)) victims.push_back(cl);
-          }
-          if (victims.size() < short_by)
-            fail(SAGE_ENOMEM, "cannot admit: %zu blocks missing, %llu evictable", missing.size(),
-                 (unsigned long long)(free_slots + victims.size()));
-          for (uint32_t cl : victims) P.evict(cl);
-        }
-        reload_classes(c, f, missing);
-      }
-      refresh_table(c, f);
-      for (uint32_t cl : f.distinct) {
-        Class& k = P.cls[cl];
-        if (k.rc == 0) P.lru_remove(cl);
-        k.rc++;
-      }
-    } else {
-      // private copy of the read-only data for this invocation
-      const size_t bytes = (size_t)f.n_blocks * kBlock;
-      v->priv = c.cache.get(bytes);
-      v->priv_table = (uint64_t*)c.cache.get((size_t)f.n_blocks * 8);
-      try {
-        copy_private(c, f, (uint8_t*)v->priv, c.ctl);
-        std::vector<uint64_t> t(f.n_blocks);
-        for (uint32_t b = 0; b < f.n_blocks; b++) t[b] = (uint64_t)((uint8_t*)v->priv + (uint64_t)b * kBlock);
-        HIPX(hipMemcpyAsync(v->priv_table, t.data(), t.size() * 8, hipMemcpyHostToDevice, c.ctl));
-        HIPX(hipStreamSynchronize(c.ctl));
-      } catch (...) {
-        free_inv_buffers(c, *v);
-        throw;
-      }
-    }
-    v->live = true;
-    f.live++;
-    *out = v->id;
-    c.invs[v->id] = std::move(v);
+    *out = setup_internal(c, id, batch);
   });
 }
 
@@ -333,19 +370,7 @@ sage_status fn_release(sage_ctx* p, sage_inv id) {
   return guard([&] {
     Ctx& c = ctx_of(p);
     std::lock_guard<std::recursive_mutex> lk(c.mu);
-    Inv& v = inv_of(c, id);
-    Fn& f = *v.fn;
-    if (c.cfg.share) {
-      Pool& P = c.pool;
-      for (uint32_t cl : f.distinct) {
-        Class& k = P.cls[cl];
-        if (k.rc == 0) fail(SAGE_ESTATE, "reference count underflow");
-        if (--k.rc == 0) P.lru_back(cl);
-      }
-    }
-    free_inv_buffers(c, v);
-    v.live = false;
-    f.live--;
+    release_internal(c, id);
   });
 }
 
@@ -388,6 +413,7 @@ sage_status fn_invoke_batch(sage_ctx* p, size_t n, const sage_inv* ids, const vo
     if (n == 0) return;
     if (!ids || !in || !in_bytes || !out || !out_bytes) fail(SAGE_EINVAL, "null argument");
     std::lock_guard<std::recursive_mutex> lk(c.mu);
+    if (c.serve) fail(SAGE_ESTATE, "the serving loop owns the launch flights: use sage_submit");
     HIPX(hipSetDevice(c.device));
     std::vector<Call> calls;
     std::unordered_set<uint64_t> seen;

@@ -69,6 +69,19 @@ class sage_stats(C.Structure):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
 
 
+class sage_req_info(C.Structure):
+    _fields_ = [("setup_ms", C.c_double), ("e2e_ms", C.c_double), ("status", C.c_uint32)]
+
+
+class sage_serve_report(C.Structure):
+    _fields_ = [("completed", C.c_uint64), ("failed", C.c_uint64), ("launches", C.c_uint64), ("rows", C.c_uint64),
+                ("setup_p50_ms", C.c_double), ("setup_p99_ms", C.c_double), ("e2e_p50_ms", C.c_double),
+                ("e2e_p99_ms", C.c_double), ("span_ms", C.c_double), ("throughput", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
 class sage_blk_op(C.Structure):
     _fields_ = [("src", C.c_uint64), ("dst", C.c_uint64), ("len", C.c_uint32), ("op", C.c_uint32)]
 
@@ -103,6 +116,13 @@ _sigs = {
     "sage_timing_reset": (C.c_int, [_P]),
     "sage_selftest_setup_overlap": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_int,
                                               C.POINTER(C.c_double)]),
+    "sage_serve_start": (C.c_int, [_P, C.c_uint32]),
+    "sage_serve_stop": (C.c_int, [_P]),
+    "sage_submit": (C.c_int, [_P, C.c_uint64, C.c_uint32, _P, C.c_size_t, _P, C.c_size_t, C.c_uint32,
+                              C.POINTER(C.c_uint64)]),
+    "sage_wait": (C.c_int, [_P, C.c_uint64, C.c_double, C.POINTER(sage_req_info)]),
+    "sage_serve_stats": (C.c_int, [_P, C.POINTER(sage_serve_report)]),
+    "sage_serve_reset_stats": (C.c_int, [_P]),
 }
 for _name, (_res, _args) in _sigs.items():
     _f = getattr(_lib, _name)
@@ -297,6 +317,40 @@ def sage_selftest_setup_overlap(load_ms: float, host_ms: float, copy_ms: float, 
     _check(_lib.sage_selftest_setup_overlap(load_ms, host_ms, copy_ms, 1 if serial else 0, C.byref(out)),
            "sage_selftest_setup_overlap")
     return out.value
+
+
+# ------------------------------------------------------------------ serving
+def sage_serve_start(ctx: int, max_rows: int = 0) -> None:
+    _check(_lib.sage_serve_start(ctx, max_rows), "sage_serve_start")
+
+
+def sage_serve_stop(ctx: int) -> None:
+    _check(_lib.sage_serve_stop(ctx), "sage_serve_stop")
+
+
+def sage_submit(ctx: int, fn: int, batch: int, inp, out, io_flags: int = 0) -> int:
+    """Queue a request; host arrays must stay alive until sage_wait returns."""
+    ip, ib = _io_ptr(inp, bool(io_flags & SAGE_IO_DEVICE_IN))
+    op, ob = _io_ptr(out, bool(io_flags & SAGE_IO_DEVICE_OUT))
+    rid = C.c_uint64()
+    _check(_lib.sage_submit(ctx, fn, batch, ip, ib, op, ob, io_flags, C.byref(rid)), "sage_submit")
+    return rid.value
+
+
+def sage_wait(ctx: int, req_id: int, timeout_ms: float = -1.0) -> dict:
+    info = sage_req_info()
+    _check(_lib.sage_wait(ctx, req_id, timeout_ms, C.byref(info)), "sage_wait")
+    return {"setup_ms": info.setup_ms, "e2e_ms": info.e2e_ms, "status": info.status}
+
+
+def sage_serve_stats(ctx: int) -> dict:
+    r = sage_serve_report()
+    _check(_lib.sage_serve_stats(ctx, C.byref(r)), "sage_serve_stats")
+    return r.as_dict()
+
+
+def sage_serve_reset_stats(ctx: int) -> None:
+    _check(_lib.sage_serve_reset_stats(ctx), "sage_serve_reset_stats")
 
 
 # ------------------------------------------------------------------ descriptors

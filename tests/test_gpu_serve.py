@@ -1,0 +1,81 @@
+"""The serving loop: requests arriving while others run are admitted as
+memory frees up (with eviction), batched into shared launches, and every
+result equals the same request run alone."""
+import time
+
+import numpy as np
+import pytest
+import torch  # noqa: F401
+
+from oracle import mlp as OM
+from paper_2404_14691_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+WIDTH, LAYERS = 256, 4
+
+
+def test_serving_mix_equals_solo_under_eviction(sage_ctx_factory, torch_cuda):
+    from paper_2404_14691_amd import sage as S
+    budget = 16                                  # < unique blocks of the 3 functions: forces eviction
+    ctx = sage_ctx_factory(pool_budget_bytes=budget * 65536, inflight_groups=3)
+    w = synth.shared_mlp_bf16_functions(n_fns=3, layers=LAYERS, width=WIDTH, share_frac=0.25, seed=11)
+    fns = [S.fn_register(ctx, S.mlp_desc(S.SAGE_MLP_BF16, LAYERS, WIDTH), [S.make_blob(b)]) for b in w.blobs]
+    rng = np.random.default_rng(0)
+    reqs = [(int(rng.integers(0, 3)), int(rng.integers(1, 40))) for _ in range(40)]
+    xs = [synth.bf16_inputs(b, WIDTH, 11, i) for i, (_, b) in enumerate(reqs)]
+    solo = []
+    for (f, b), x in zip(reqs, xs):
+        inv = S.fn_setup(ctx, fns[f], b)
+        y = np.zeros((b, WIDTH), dtype=np.float32)
+        S.fn_invoke(ctx, inv, x, y)
+        S.fn_release(ctx, inv)
+        solo.append(y)
+    for (f, b), x, y in zip(reqs, xs, solo):
+        ref = OM.mlp_forward(OM.bf16_to_f64(x), OM.bf16_to_f64(w.blobs[f]).reshape(LAYERS, WIDTH, WIDTH))
+        assert OM.normwise_error(y, ref) <= 2e-2
+    ev0 = S.sage_get_stats(ctx)["evictions"]
+
+    S.sage_serve_start(ctx)
+    with pytest.raises(S.SageError) as e:
+        S.fn_invoke_batch(ctx, [1], [xs[0]], [solo[0]])
+    assert e.value.status == S.SAGE_ESTATE
+    outs = [np.full((b, WIDTH), np.nan, dtype=np.float32) for _, b in reqs]
+    ids = []
+    for i, ((f, b), x) in enumerate(zip(reqs, xs)):
+        ids.append(S.sage_submit(ctx, fns[f], b, x, outs[i]))
+        if i % 7 == 3:
+            time.sleep(0.002)                     # arrivals while earlier launches run
+    infos = [S.sage_wait(ctx, r, 30000) for r in ids]
+    rep = S.sage_serve_stats(ctx)
+    S.sage_serve_stop(ctx)
+
+    for y, o in zip(solo, outs):
+        assert np.array_equal(y, o)
+    assert all(i["status"] == 0 and i["e2e_ms"] >= i["setup_ms"] >= 0 for i in infos)
+    assert rep["completed"] == len(reqs) and rep["failed"] == 0
+    assert rep["launches"] < len(reqs)            # requests were batched together
+    st = S.sage_get_stats(ctx)
+    assert st["refcount_sum"] == 0 and st["live_setups"] == 0
+    assert st["evictions"] > ev0                  # admission had to evict
+    assert rep["setup_p99_ms"] <= rep["e2e_p99_ms"]
+
+
+def test_serving_rejects_inadmissible_request(sage_ctx_factory, torch_cuda):
+    """A function larger than the whole pool can never be admitted: the
+    request fails with ENOMEM instead of waiting forever."""
+    from paper_2404_14691_amd import sage as S
+    ctx = sage_ctx_factory(pool_budget_bytes=8 * 65536)
+    w = synth.shared_mlp_bf16_functions(n_fns=2, layers=LAYERS, width=WIDTH, share_frac=0.0, seed=12)
+    f0 = S.fn_register(ctx, S.mlp_desc(S.SAGE_MLP_BF16, LAYERS, WIDTH), [S.make_blob(w.blobs[0])])
+    f1 = S.fn_register(ctx, S.mlp_desc(S.SAGE_MLP_BF16, LAYERS, WIDTH), [S.make_blob(w.blobs[1])])
+    inv = S.fn_setup(ctx, f1, 1)                  # pins all 8 slots for f1
+    S.sage_serve_start(ctx)
+    x = synth.bf16_inputs(2, WIDTH, 12, 0)
+    y = np.zeros((2, WIDTH), dtype=np.float32)
+    r = S.sage_submit(ctx, f0, 2, x, y)
+    with pytest.raises(S.SageError) as e:
+        S.sage_wait(ctx, r, 30000)
+    assert e.value.status == S.SAGE_ENOMEM
+    S.sage_serve_stop(ctx)
+    S.fn_release(ctx, inv)
