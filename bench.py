@@ -109,8 +109,7 @@ def shared_step(S, ctx, wl):
         ins.append(i)
         outs.append(o)
     S.fn_invoke_batch(ctx, invs, ins, outs, io)
-    for inv in invs:
-        S.fn_release(ctx, inv)
+    S.fn_release_batch(ctx, invs)
     stats = S.sage_get_stats(ctx)
     for f in fns:
         S.fn_unregister(ctx, f)
@@ -253,8 +252,11 @@ def main():
         # ---- timed: shared + batched, with per-kernel device timing
         S.sage_timing_reset(ctx)
         S.sage_timing_enable(ctx, True)
+        st0 = S.sage_get_stats(ctx)
         elapsed, res = timed(torch, lambda: shared_step(S, ctx, wl), args.steps)
+        st1 = S.sage_get_stats(ctx)
         S.sage_timing_enable(ctx, False)
+        host = {k: round((st1[k] - st0[k]) / args.steps, 3) for k in st1 if k.startswith("t_")}
         log(f"shared timed: {elapsed * 1e3 / args.steps:.2f} ms/step")
         setup_shared = [x for r in res for x in r[0]]
         stats = res[-1][1]
@@ -316,6 +318,7 @@ def main():
             "blkcopy": {"avg_ms": round(b_ms / max(b_n, 1), 5), "launches": b_n},
             "ggemm_bf16": {"avg_ms": round(gemm_avg_ms, 5), "launches": g_n}},
         "kernels_standalone_4GiB": standalone,
+        "host_ms_per_step": host,
     }
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")

@@ -132,6 +132,14 @@ typedef struct {
   uint64_t invocations;
   uint64_t verify_mismatches; /* fingerprint hits whose bytes differed */
   uint64_t workspace_bytes; /* device bytes held for invocation workspaces */
+  /* host wall time (ms) spent in the setup path since open, by stage */
+  double t_register_ms;     /* whole fn_register calls */
+  double t_code_ms;         /* code branch: module load + block-table allocation */
+  double t_fp_wait_ms;      /* data branch: waiting for staged bytes + fingerprints */
+  double t_dedup_ms;        /* data branch: host index lookups and commit */
+  double t_verify_ms;       /* data branch: COPY/VERIFY launches and their results */
+  double t_setup_ms;        /* fn_setup calls (admission, reloads, references) */
+  double t_invoke_ms;       /* fn_invoke / fn_invoke_batch calls */
 } sage_stats;
 
 /* ----------------------------------------------------------------- context */
@@ -183,6 +191,12 @@ sage_status fn_setup(sage_ctx* ctx, sage_fn fn, uint32_t batch, sage_inv* out);
 #define SAGE_IO_DEVICE_IN 1u
 #define SAGE_IO_DEVICE_OUT 2u
 
+/* fn_setup for n requests (fns[i], batches[i]) in order; stops at the first
+ * failure, returning its status, with out[0..k) set for the k that
+ * succeeded (*n_done = k). */
+sage_status fn_setup_batch(sage_ctx* ctx, size_t n, const sage_fn* fns, const uint32_t* batches, sage_inv* out,
+                           size_t* n_done);
+
 /* Run one set-up invocation: in = X / u0 as described in sage_fn_desc,
  * out = Y / u.  The body waits for the function's data (the kernel-executor
  * readiness check, section "Ensuring Function Correctness").  Blocking.
@@ -204,6 +218,9 @@ sage_status fn_invoke_batch(sage_ctx* ctx, size_t n, const sage_inv* invs, const
  * resident until evicted: first exit stage, section "Multi-stage Resource
  * Exit") and free its private buffers.  ESTATE if already released. */
 sage_status fn_release(sage_ctx* ctx, sage_inv inv);
+
+/* fn_release for n invocations; stops at the first failure. */
+sage_status fn_release_batch(sage_ctx* ctx, size_t n, const sage_inv* invs);
 
 /* ---------------------------------------------------------- introspection */
 sage_status sage_get_stats(sage_ctx* ctx, sage_stats* out);

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <chrono>
 #include <condition_variable>
 #include <cstdint>
 #include <cstdio>
@@ -25,6 +26,11 @@
 #include "layout.h"
 
 namespace sage {
+
+// ------------------------------------------------------------------ timing
+inline double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
 
 // ------------------------------------------------------------------ errors
 struct Error {
@@ -88,12 +94,20 @@ class KernelTimer {
 // ------------------------------------------------------------------- pool
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
+// A class is a set of identical blocks; while resident it owns one slot.
+// References are counted per function: `active` is the number of functions
+// with live setups that use the class, so a setup or release touches the
+// classes only when its function's live count crosses zero.  The class's
+// reference count in the paper-level sense (live setups using it) is the
+// sum of the live counts of those functions.
 struct Class {
   uint64_t fp = 0;
   uint32_t len = 0;
   uint32_t slot = kNone;
-  uint32_t rc = 0;
+  uint32_t active = 0;        // functions with live setups using the class
   uint32_t members = 0;       // registered (fn, block) references
+  uint32_t next = kNone;      // next class in its fingerprint chain
+  uint32_t mark = 0;          // protection stamp of the running registration / reload
   bool alive = false;
   bool in_lru = false;
   bool indexed = false;
@@ -115,11 +129,12 @@ class Pool {
   uint32_t new_class(uint64_t fp, uint32_t len);
   void drop_class(uint32_t c);          // dead class: slot freed, index entry removed
   void evict(uint32_t c);
-  void index_add(uint32_t c);
+  void index_add(uint32_t c);           // append to the end of its fingerprint chain
   void index_remove(uint32_t c);
   void lru_back(uint32_t c);
   void lru_remove(uint32_t c);
-  const std::vector<uint32_t>* chain(uint64_t fp) const;
+  uint32_t chain_head(uint64_t fp) const;  // first indexed class with this fingerprint, or kNone
+  uint32_t new_mark() { return ++mark_; }
 
   std::vector<Class> cls;
   std::list<uint32_t> lru;
@@ -129,7 +144,8 @@ class Pool {
   std::vector<uint8_t*> segs_;
   size_t seg_slots_ = 16384;
   std::vector<uint32_t> free_;
-  std::unordered_map<uint64_t, std::vector<uint32_t>> index_;
+  std::unordered_map<uint64_t, uint32_t> index_;  // fingerprint -> chain head
+  uint32_t mark_ = 0;
 };
 
 // --------------------------------------------------------------- modules
@@ -231,6 +247,22 @@ struct TuneEntry {
   double ms;
 };
 
+// Long-lived helper thread that runs the code branch of function setup.
+class Worker {
+ public:
+  void start(int device);
+  void stop();
+  void run(std::function<void()> task);  // queue one task
+  void wait();                           // until the queued task finished; rethrows its error
+ private:
+  std::thread th_;
+  std::mutex mu_;
+  std::condition_variable cv_;
+  std::function<void()> task_;
+  bool has_ = false, done_ = true, quit_ = false;
+  std::exception_ptr err_;
+};
+
 // ------------------------------------------------------------------ context
 struct Ctx {
   int device = 0;
@@ -254,7 +286,9 @@ struct Ctx {
   std::map<std::string, TuneEntry> tune;     // "width:bucket" -> best kernel
   // counters
   uint64_t logical = 0, h2d = 0, reloads = 0, registrations = 0, invocations = 0, mismatches = 0;
+  double t_register = 0, t_code = 0, t_fp_wait = 0, t_dedup = 0, t_verify = 0, t_setup = 0, t_invoke = 0;
   Serve* serve = nullptr;                    // running serving loop, if any
+  Worker worker;                             // code branch of fn_register
   bool test_fp_const = false;                // force every fingerprint equal (collision test)
   uint64_t test_fp_value = 0;
 
@@ -267,8 +301,10 @@ void ring_init(Ctx& c);
 void ring_destroy(Ctx& c);
 void fill_parallel(Ctx& c, uint8_t* dst, const uint8_t* src, size_t n);
 
-// Two setup branches: code load on a helper thread, data on the caller.
-void run_two_branches(const std::function<void()>& code, const std::function<void()>& data, bool serial);
+// Two setup branches: the code branch on `w` (or a new thread when w is
+// null), the data branch on the caller; serial runs code then data.
+void run_two_branches(const std::function<void()>& code, const std::function<void()>& data, bool serial,
+                      Worker* w = nullptr);
 
 Module* load_module(Ctx& c, int kind);
 void register_shared(Ctx& c, Fn& f);

@@ -61,7 +61,15 @@ uint32_t Pool::new_class(uint64_t fp, uint32_t len) {
 }
 
 void Pool::index_add(uint32_t c) {
-  index_[cls[c].fp].push_back(c);
+  cls[c].next = kNone;
+  auto it = index_.find(cls[c].fp);
+  if (it == index_.end()) {
+    index_.emplace(cls[c].fp, c);
+  } else {
+    uint32_t t = it->second;
+    while (cls[t].next != kNone) t = cls[t].next;
+    cls[t].next = c;
+  }
   cls[c].indexed = true;
 }
 
@@ -69,20 +77,22 @@ void Pool::index_remove(uint32_t c) {
   if (!cls[c].indexed) return;
   auto it = index_.find(cls[c].fp);
   if (it != index_.end()) {
-    auto& v = it->second;
-    for (size_t i = 0; i < v.size(); i++)
-      if (v[i] == c) {
-        v.erase(v.begin() + i);
-        break;
-      }
-    if (v.empty()) index_.erase(it);
+    if (it->second == c) {
+      if (cls[c].next == kNone) index_.erase(it);
+      else it->second = cls[c].next;
+    } else {
+      uint32_t t = it->second;
+      while (t != kNone && cls[t].next != c) t = cls[t].next;
+      if (t != kNone) cls[t].next = cls[c].next;
+    }
   }
+  cls[c].next = kNone;
   cls[c].indexed = false;
 }
 
-const std::vector<uint32_t>* Pool::chain(uint64_t fp) const {
+uint32_t Pool::chain_head(uint64_t fp) const {
   auto it = index_.find(fp);
-  return it == index_.end() ? nullptr : &it->second;
+  return it == index_.end() ? kNone : it->second;
 }
 
 void Pool::lru_back(uint32_t c) {

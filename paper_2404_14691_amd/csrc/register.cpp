@@ -206,8 +206,10 @@ void register_shared(Ctx& c, Fn& f) {
   f.cls.assign(f.n_blocks, kNone);
   f.fps.assign(f.n_blocks, 0);
   std::vector<uint32_t> created;
-  std::unordered_set<uint32_t> protect_set;
-  auto protect = [&](uint32_t cl) { return protect_set.count(cl) > 0; };
+  // classes this registration joined, created or is verifying against are
+  // stamped and never chosen as eviction victims while it runs
+  const uint32_t mark = P.new_mark();
+  auto protect = [&](uint32_t cl) { return P.cls[cl].mark == mark; };
   std::vector<int> free_slots;
   for (int s = (int)R.slots; s-- > 0;) free_slots.push_back(s);
 
@@ -240,7 +242,10 @@ void register_shared(Ctx& c, Fn& f) {
   auto process = [&](Chunk& ch) {
     const int slot = ch.slot;
     hipStream_t s = stream_of(slot);
+    double t0 = now_ms();
     HIPX(hipEventSynchronize(R.ev[slot]));
+    double t1 = now_ms();
+    c.t_fp_wait += t1 - t0;
     BlkOp* ops = R.hops[slot];
     uint32_t nops = 0;
     struct Pend {
@@ -264,22 +269,16 @@ void register_shared(Ctx& c, Fn& f) {
       P.index_add(cl);
       created.push_back(cl);
       chunk_new.push_back(cl);
-      protect_set.insert(cl);
+      P.cls[cl].mark = mark;
       f.cls[gb] = cl;
       ops[nops++] = BlkOp{(uint64_t)(ch.data + (uint64_t)i * kBlock), (uint64_t)P.addr(slotid), len, 0};
     };
     // first candidate after `after` (or the first one) with the block's length
     auto next_cand = [&](uint64_t fp, uint32_t len, uint32_t after) -> uint32_t {
-      const auto* chn = P.chain(fp);
-      if (!chn) return kNone;
-      size_t k = 0;
-      if (after != kNone) {
-        while (k < chn->size() && (*chn)[k] != after) k++;
-        k++;
-      }
-      for (; k < chn->size(); k++) {
-        protect_set.insert((*chn)[k]);
-        if (P.cls[(*chn)[k]].len == len) return (*chn)[k];
+      uint32_t k = after == kNone ? P.chain_head(fp) : P.cls[after].next;
+      for (; k != kNone; k = P.cls[k].next) {
+        P.cls[k].mark = mark;
+        if (P.cls[k].len == len) return k;
       }
       return kNone;
     };
@@ -297,12 +296,16 @@ void register_shared(Ctx& c, Fn& f) {
       }
     }
     while (nops > 0) {
+      const double tv = now_ms();
+      c.t_dedup += tv - t1;
       HIPX(hipMemcpyAsync(R.dops[slot], ops, nops * sizeof(BlkOp), hipMemcpyHostToDevice, s));
       const int tok = c.timer.start("blkcopy", s, 1);
       HIPX(launch_blkcopy(R.dops[slot], nops, R.dres[slot], c.max_groups_stream(), s));
       c.timer.stop(tok, s);
       HIPX(hipMemcpyAsync(R.hres[slot], R.dres[slot], nops * 4, hipMemcpyDeviceToHost, s));
       HIPX(hipStreamSynchronize(s));
+      t1 = now_ms();
+      c.t_verify += t1 - tv;
       std::vector<uint32_t> res(R.hres[slot], R.hres[slot] + nops);
       nops = 0;
       std::vector<Pend> again;
@@ -324,6 +327,7 @@ void register_shared(Ctx& c, Fn& f) {
       pend.swap(again);
     }
     for (uint32_t cl : chunk_new) P.cls[cl].pending = nullptr;
+    c.t_dedup += now_ms() - t1;
   };
 
   try {
@@ -349,7 +353,7 @@ void register_shared(Ctx& c, Fn& f) {
   std::sort(f.distinct.begin(), f.distinct.end());
   f.distinct.erase(std::unique(f.distinct.begin(), f.distinct.end()), f.distinct.end());
   for (uint32_t cl : f.distinct)
-    if (P.cls[cl].rc == 0) P.lru_back(cl);
+    if (P.cls[cl].active == 0) P.lru_back(cl);
   c.h2d += f.ro_bytes;
 }
 
@@ -396,8 +400,9 @@ void reload_classes(Ctx& c, Fn& f, const std::vector<uint32_t>& missing) {
   Ring& R = c.ring;
   std::unordered_map<uint32_t, uint32_t> first;
   for (uint32_t b = 0; b < f.n_blocks; b++) first.emplace(f.cls[b], b);
-  std::unordered_set<uint32_t> mine(f.distinct.begin(), f.distinct.end());
-  auto protect = [&](uint32_t cl) { return mine.count(cl) > 0; };
+  const uint32_t mark = P.new_mark();
+  for (uint32_t cl : f.distinct) P.cls[cl].mark = mark;
+  auto protect = [&](uint32_t cl) { return P.cls[cl].mark == mark; };
   const size_t per_slot = R.chunk / kBlock;
   hipStream_t s = c.streams[0];
   size_t i = 0;

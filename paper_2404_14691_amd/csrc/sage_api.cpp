@@ -102,12 +102,13 @@ uint64_t setup_internal(Ctx& c, uint64_t id, uint32_t batch) {
       // admission: all missing classes need slots; evict only if enough can be freed
       const uint64_t free_slots = P.budget > P.used_ ? P.budget - P.used_ : 0;
       if (missing.size() > free_slots) {
-        std::unordered_set<uint32_t> mine(f.distinct.begin(), f.distinct.end());
+        const uint32_t mark = P.new_mark();
+        for (uint32_t cl : f.distinct) P.cls[cl].mark = mark;
         std::vector<uint32_t> victims;
         const uint64_t short_by = missing.size() - free_slots;
         for (uint32_t cl : P.lru) {
           if (victims.size() >= short_by) break;
-          if (!mine.count(cl)) victims.push_back(cl);
+          if (P.cls[cl].mark != mark) victims.push_back(cl);
         }
         if (victims.size() < short_by)
           fail(SAGE_ENOMEM, "cannot admit: %zu blocks missing, %llu evictable", missing.size(),
@@ -117,11 +118,9 @@ uint64_t setup_internal(Ctx& c, uint64_t id, uint32_t batch) {
       reload_classes(c, f, missing);
     }
     refresh_table(c, f);
-    for (uint32_t cl : f.distinct) {
-      Class& k = P.cls[cl];
-      if (k.rc == 0) P.lru_remove(cl);
-      k.rc++;
-    }
+    if (f.live == 0)
+      for (uint32_t cl : f.distinct)
+        if (P.cls[cl].active++ == 0) P.lru_remove(cl);
   } else {
     // private copy of the read-only data for this invocation
     const size_t bytes = (size_t)f.n_blocks * kBlock;
@@ -148,12 +147,13 @@ uint64_t setup_internal(Ctx& c, uint64_t id, uint32_t batch) {
 void release_internal(Ctx& c, uint64_t id) {
   Inv& v = inv_of(c, id);
   Fn& f = *v.fn;
-  if (c.cfg.share) {
+  if (f.live <= 0) fail(SAGE_ESTATE, "reference count underflow");
+  if (c.cfg.share && f.live == 1) {
     Pool& P = c.pool;
-    for (uint32_t cl : f.distinct) {
+    for (uint32_t cl : f.distinct) {  // increasing class order
       Class& k = P.cls[cl];
-      if (k.rc == 0) fail(SAGE_ESTATE, "reference count underflow");
-      if (--k.rc == 0) P.lru_back(cl);
+      if (k.active == 0) fail(SAGE_ESTATE, "reference count underflow");
+      if (--k.active == 0) P.lru_back(cl);
     }
   }
   free_inv_buffers(c, v);
@@ -228,6 +228,7 @@ sage_status sage_open(int device, const sage_config* cfg, sage_ctx** out) {
     ring_init(c);
     flights_init(c);
     tune_load(c);
+    c.worker.start(device);
     if (const char* e = std::getenv("SAGE_TEST_FP_CONST")) {
       c.test_fp_const = true;
       c.test_fp_value = std::strtoull(e, nullptr, 0);
@@ -240,6 +241,7 @@ sage_status sage_close(sage_ctx* p) {
   return guard([&] {
     Ctx& c = ctx_of(p);
     serve_destroy(c);
+    c.worker.stop();
     {
       std::lock_guard<std::recursive_mutex> lk(c.mu);
       (void)hipSetDevice(c.device);
@@ -295,6 +297,7 @@ sage_status fn_register(sage_ctx* p, const sage_fn_desc* desc, const sage_blob* 
     Ctx& c = ctx_of(p);
     if (!desc || !out) fail(SAGE_EINVAL, "null argument");
     std::lock_guard<std::recursive_mutex> lk(c.mu);
+    const double t_start = now_ms();
     HIPX(hipSetDevice(c.device));
     validate(*desc, blobs, n_blobs);
     auto f = std::make_unique<Fn>();
@@ -313,18 +316,21 @@ sage_status fn_register(sage_ctx* p, const sage_fn_desc* desc, const sage_blob* 
     HIPX(hipEventCreateWithFlags(&f->ready, hipEventDisableTiming));
     Fn& F = *f;
     // code branch: module + block table; data branch: the blobs
+    double t_code = 0;
     auto code = [&] {
+      const double t0 = now_ms();
       F.mod = load_module(c, F.d.kind);
       if (c.cfg.share) {
         HIPX(hipSetDevice(c.device));
         HIPX(hipMalloc((void**)&F.d_table, std::max<size_t>(8, (size_t)F.n_blocks * 8)));
       }
+      t_code = now_ms() - t0;
     };
     auto data = [&] {
       if (c.cfg.share) register_shared(c, F);
     };
     try {
-      run_two_branches(code, data, c.cfg.serial_setup != 0);
+      run_two_branches(code, data, c.cfg.serial_setup != 0, &c.worker);
       if (c.cfg.share) refresh_table(c, F);
       HIPX(hipEventRecord(F.ready, c.ctl));
     } catch (...) {
@@ -334,6 +340,8 @@ sage_status fn_register(sage_ctx* p, const sage_fn_desc* desc, const sage_blob* 
     }
     c.logical += F.ro_bytes;
     c.registrations++;
+    c.t_code += t_code;
+    c.t_register += now_ms() - t_start;
     *out = F.id;
     c.fns[F.id] = std::move(f);
   });
@@ -362,7 +370,38 @@ sage_status fn_setup(sage_ctx* p, sage_fn id, uint32_t batch, sage_inv* out) {
     Ctx& c = ctx_of(p);
     if (!out) fail(SAGE_EINVAL, "null output");
     std::lock_guard<std::recursive_mutex> lk(c.mu);
+    const double t0 = now_ms();
     *out = setup_internal(c, id, batch);
+    c.t_setup += now_ms() - t0;
+  });
+}
+
+sage_status fn_setup_batch(sage_ctx* p, size_t n, const sage_fn* fns, const uint32_t* batches, sage_inv* out,
+                           size_t* n_done) {
+  size_t k = 0;
+  const sage_status st = guard([&] {
+    Ctx& c = ctx_of(p);
+    if (n && (!fns || !batches || !out)) fail(SAGE_EINVAL, "null argument");
+    std::lock_guard<std::recursive_mutex> lk(c.mu);
+    const double t0 = now_ms();
+    try {
+      for (; k < n; k++) out[k] = setup_internal(c, fns[k], batches[k]);
+    } catch (...) {
+      c.t_setup += now_ms() - t0;
+      throw;
+    }
+    c.t_setup += now_ms() - t0;
+  });
+  if (n_done) *n_done = k;
+  return st;
+}
+
+sage_status fn_release_batch(sage_ctx* p, size_t n, const sage_inv* invs) {
+  return guard([&] {
+    Ctx& c = ctx_of(p);
+    if (n && !invs) fail(SAGE_EINVAL, "null argument");
+    std::lock_guard<std::recursive_mutex> lk(c.mu);
+    for (size_t i = 0; i < n; i++) release_internal(c, invs[i]);
   });
 }
 
@@ -429,7 +468,9 @@ sage_status fn_invoke_batch(sage_ctx* p, size_t n, const sage_inv* ids, const vo
       if (io & SAGE_IO_DEVICE_OUT) check_aligned(out[i], "device output");
       calls.push_back(Call{&v, in[i], in_bytes[i], out[i], out_bytes[i]});
     }
+    const double t0 = now_ms();
     run_calls(c, calls, io);
+    c.t_invoke += now_ms() - t0;
   });
 }
 
@@ -451,8 +492,8 @@ sage_status sage_get_stats(sage_ctx* p, sage_stats* out) {
         out->resident_bytes += k.len;
         out->resident_slots++;
       }
-      out->refcount_sum += k.rc;
     }
+    for (auto& kv : c.fns) out->refcount_sum += (uint64_t)kv.second->live * kv.second->distinct.size();
     out->logical_bytes = c.logical;
     out->budget_slots = P.budget;
     out->h2d_bytes = c.h2d;
@@ -463,6 +504,13 @@ sage_status sage_get_stats(sage_ctx* p, sage_stats* out) {
     out->invocations = c.invocations;
     out->verify_mismatches = c.mismatches;
     out->workspace_bytes = c.cache.in_use();
+    out->t_register_ms = c.t_register;
+    out->t_code_ms = c.t_code;
+    out->t_fp_wait_ms = c.t_fp_wait;
+    out->t_dedup_ms = c.t_dedup;
+    out->t_verify_ms = c.t_verify;
+    out->t_setup_ms = c.t_setup;
+    out->t_invoke_ms = c.t_invoke;
   });
 }
 
@@ -493,11 +541,22 @@ sage_status sage_fn_block_info(sage_ctx* p, sage_fn id, uint32_t* cls, uint32_t*
     Fn& f = fn_of(c, id);
     if (!c.cfg.share) fail(SAGE_ESTATE, "block classes exist only with sharing on");
     if (n != f.n_blocks) fail(SAGE_EINVAL, "need %u entries", f.n_blocks);
+    // references of a class = live setups of every function using it
+    std::unordered_map<uint32_t, uint32_t> rc;
+    for (uint32_t cl : f.distinct) rc[cl] = 0;
+    for (auto& kv : c.fns) {
+      const Fn& g = *kv.second;
+      if (g.live <= 0) continue;
+      for (uint32_t cl : g.distinct) {
+        auto it = rc.find(cl);
+        if (it != rc.end()) it->second += g.live;
+      }
+    }
     for (uint32_t b = 0; b < f.n_blocks; b++) {
       const Class& k = c.pool.cls[f.cls[b]];
       if (cls) cls[b] = f.cls[b];
       if (slot) slot[b] = k.slot;
-      if (refs) refs[b] = k.rc;
+      if (refs) refs[b] = rc[f.cls[b]];
     }
   });
 }

@@ -178,10 +178,82 @@ void KernelTimer::destroy() {
 // and the data branch run at the same time; compute starts when both are
 // done.  With `serial`, code first, then data (the one-after-the-other
 // baseline).  An error in either branch is rethrown after both finished.
-void run_two_branches(const std::function<void()>& code, const std::function<void()>& data, bool serial) {
+void Worker::start(int device) {
+  quit_ = false;
+  th_ = std::thread([this, device] {
+    (void)hipSetDevice(device);
+    std::unique_lock<std::mutex> lk(mu_);
+    for (;;) {
+      cv_.wait(lk, [&] { return has_ || quit_; });
+      if (quit_) return;
+      auto task = std::move(task_);
+      has_ = false;
+      lk.unlock();
+      std::exception_ptr e;
+      try {
+        task();
+      } catch (...) {
+        e = std::current_exception();
+      }
+      lk.lock();
+      err_ = e;
+      done_ = true;
+      cv_.notify_all();
+    }
+  });
+}
+
+void Worker::stop() {
+  {
+    std::lock_guard<std::mutex> lk(mu_);
+    quit_ = true;
+  }
+  cv_.notify_all();
+  if (th_.joinable()) th_.join();
+}
+
+void Worker::run(std::function<void()> task) {
+  std::lock_guard<std::mutex> lk(mu_);
+  task_ = std::move(task);
+  has_ = true;
+  done_ = false;
+  err_ = nullptr;
+  cv_.notify_all();
+}
+
+void Worker::wait() {
+  std::unique_lock<std::mutex> lk(mu_);
+  cv_.wait(lk, [&] { return done_; });
+  if (err_) {
+    auto e = err_;
+    err_ = nullptr;
+    std::rethrow_exception(e);
+  }
+}
+
+void run_two_branches(const std::function<void()>& code, const std::function<void()>& data, bool serial,
+                      Worker* w) {
   if (serial) {
     code();
     data();
+    return;
+  }
+  if (w) {
+    w->run(code);
+    std::exception_ptr data_err;
+    try {
+      data();
+    } catch (...) {
+      data_err = std::current_exception();
+    }
+    if (data_err) {
+      try {
+        w->wait();
+      } catch (...) {
+      }
+      std::rethrow_exception(data_err);
+    }
+    w->wait();
     return;
   }
   std::exception_ptr code_err;

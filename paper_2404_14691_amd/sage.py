@@ -63,10 +63,17 @@ class sage_stats(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in (
         "logical_bytes", "unique_bytes", "shared_bytes", "private_bytes", "resident_bytes",
         "resident_slots", "budget_slots", "classes", "h2d_bytes", "refcount_sum", "live_setups",
-        "evictions", "reloads", "registrations", "invocations", "verify_mismatches", "workspace_bytes")]
+        "evictions", "reloads", "registrations", "invocations", "verify_mismatches", "workspace_bytes")] + \
+        [(n, C.c_double) for n in ("t_register_ms", "t_code_ms", "t_fp_wait_ms", "t_dedup_ms", "t_verify_ms",
+                                   "t_setup_ms", "t_invoke_ms")]
 
     def as_dict(self) -> dict:
-        return {n: int(getattr(self, n)) for n, _ in self._fields_}
+        return {n: (int(getattr(self, n)) if t is C.c_uint64 else float(getattr(self, n)))
+                for n, t in self._fields_}
+
+    def counters(self) -> dict:
+        """The integer counters only (timers excluded)."""
+        return {n: int(getattr(self, n)) for n, t in self._fields_ if t is C.c_uint64}
 
 
 class sage_req_info(C.Structure):
@@ -103,6 +110,9 @@ _sigs = {
     "fn_invoke_batch": (C.c_int, [_P, C.c_size_t, C.POINTER(C.c_uint64), C.POINTER(_P), C.POINTER(C.c_size_t),
                                   C.POINTER(_P), C.POINTER(C.c_size_t), C.c_uint32]),
     "fn_release": (C.c_int, [_P, C.c_uint64]),
+    "fn_setup_batch": (C.c_int, [_P, C.c_size_t, C.POINTER(C.c_uint64), C.POINTER(C.c_uint32),
+                                 C.POINTER(C.c_uint64), C.POINTER(C.c_size_t)]),
+    "fn_release_batch": (C.c_int, [_P, C.c_size_t, C.POINTER(C.c_uint64)]),
     "sage_get_stats": (C.c_int, [_P, C.POINTER(sage_stats)]),
     "sage_fn_fingerprints": (C.c_int, [_P, C.c_uint64, C.POINTER(C.c_uint64), C.c_size_t]),
     "sage_fn_block_info": (C.c_int, [_P, C.c_uint64, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
@@ -247,6 +257,20 @@ def fn_invoke_batch(ctx: int, invs, inputs, outputs, io_flags: int = 0) -> None:
 
 def fn_release(ctx: int, inv: int) -> None:
     _check(_lib.fn_release(ctx, inv), "fn_release")
+
+
+def fn_setup_batch(ctx: int, fns, batches) -> list:
+    n = len(fns)
+    out = (C.c_uint64 * n)()
+    done = C.c_size_t()
+    st = _lib.fn_setup_batch(ctx, n, (C.c_uint64 * n)(*fns), (C.c_uint32 * n)(*batches), out, C.byref(done))
+    _check(st, "fn_setup_batch")
+    return list(out)
+
+
+def fn_release_batch(ctx: int, invs) -> None:
+    n = len(invs)
+    _check(_lib.fn_release_batch(ctx, n, (C.c_uint64 * n)(*invs)), "fn_release_batch")
 
 
 # ------------------------------------------------------------------ introspection
