@@ -52,22 +52,23 @@ __device__ __forceinline__ uint8_t* c_row(const LayerArgs& la, uint32_t r, uint3
 // column of 8 consecutive rows hit 8 different bank groups.
 __device__ __forceinline__ uint32_t swz(uint32_t r, uint32_t c) { return r * kRowBytes + ((c ^ (r & 7)) << 4); }
 
-// Global -> registers: NL 16-byte chunks per thread for one K stage.
-template <int NL, int NCH>
+// Global -> registers: NL 16-byte chunks per thread for one K stage
+// (NT threads; thread t owns chunk t % 8 of rows t / 8 + (NT / 8) i).
+template <int NL, int NCH, int NT = 256>
 __device__ __forceinline__ void gload(u32x4 (&r)[NL], const uint8_t* const (&p)[NL], uint32_t kt, uint32_t t) {
 #pragma unroll
   for (int i = 0; i < NL; i++)
-    if (NCH % 256 == 0 || t + 256 * i < (uint32_t)NCH)
+    if (NCH % NT == 0 || t + NT * i < (uint32_t)NCH)
       r[i] = *(g_u32x4*)(uintptr_t)(p[i] + kt * kRowBytes);
 }
 
 // Registers -> one LDS stage (swizzled rows).
-template <int NL, int NCH>
+template <int NL, int NCH, int NT = 256>
 __device__ __forceinline__ void sstore(uint8_t* stage, const u32x4 (&r)[NL], uint32_t t, uint32_t chunk) {
 #pragma unroll
   for (int i = 0; i < NL; i++)
-    if (NCH % 256 == 0 || t + 256 * i < (uint32_t)NCH)
-      *reinterpret_cast<u32x4*>(stage + swz((t >> 3) + 32 * i, chunk)) = r[i];
+    if (NCH % NT == 0 || t + NT * i < (uint32_t)NCH)
+      *reinterpret_cast<u32x4*>(stage + swz((t >> 3) + (NT / 8) * i, chunk)) = r[i];
 }
 
 template <int BM, int BN, int WM, int WN>
@@ -180,6 +181,288 @@ __device__ __forceinline__ void ggemm_bf16(const GemmHdr* __restrict__ hdr, cons
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Large-tile variant: BM x BN tile per workgroup of NT = 64 * waves threads,
+// wave tile WM x WN.  Tiles are dealt to the 8 XCDs in contiguous ranges
+// (workgroup w runs on XCD w % 8) of a tile list ordered by group, then by
+// super-columns of SC n-tiles, m-tile fastest inside a super-column, so the
+// workgroups that run together on one XCD share their A and W K-slices in
+// that XCD's L2.
+constexpr uint32_t kXcds = 8;
+
+__device__ __forceinline__ void tile_coords(uint32_t local, uint32_t m_tiles, uint32_t n_tiles, uint32_t sc,
+                                            uint32_t* mt, uint32_t* nt) {
+  const uint32_t per_sc = m_tiles * sc;
+  const uint32_t s = local / per_sc, r = local % per_sc;
+  const uint32_t width = (s + 1) * sc <= n_tiles ? sc : n_tiles - s * sc;
+  *mt = r / width;
+  *nt = s * sc + r % width;
+}
+
+template <int BM, int BN, int WM, int WN>
+__device__ __forceinline__ void ggemm2(const GemmHdr* __restrict__ hdr, const GemmGroup* __restrict__ groups,
+                                       const LayerArgs la, uint8_t* lds) {
+  constexpr int NWN = BN / WN, NWM = BM / WM;
+  constexpr int NT = 64 * NWN * NWM;
+  constexpr int FM = WM / 16, FN = WN / 16;
+  constexpr int A_CH = BM * 8, B_CH = BN * 8;
+  constexpr int A_LD = (A_CH + NT - 1) / NT, B_LD = (B_CH + NT - 1) / NT;
+  constexpr uint32_t A_STAGE = BM * kRowBytes, B_STAGE = BN * kRowBytes;
+  constexpr uint32_t SC = 4;
+  uint8_t* const As = lds;
+  uint8_t* const Bs = lds + 2 * A_STAGE;
+
+  const uint32_t t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const uint32_t wm = wave / NWN, wn = wave % NWN;
+  const uint32_t N = la.N, K = la.K;
+  const uint32_t total = hdr->total_tiles, G = hdr->n_groups;
+  const uint32_t ld_chunk = t & 7;
+  const bool out_f32 = la.flags & kOutF32, relu = la.flags & kRelu;
+  const uint32_t KT = K / BK;
+  const uint32_t n_tiles = N / BN;
+
+  // this workgroup's XCD range of the tile list
+  const uint32_t xcd = blockIdx.x % kXcds, j = blockIdx.x / kXcds, per_xcd = gridDim.x / kXcds;
+  if (j >= per_xcd) return;  // the host launches a multiple of 8 workgroups
+  const uint32_t r0 = (uint32_t)(((uint64_t)total * xcd) / kXcds);
+  const uint32_t r1 = (uint32_t)(((uint64_t)total * (xcd + 1)) / kXcds);
+
+  for (uint32_t tile = r0 + j; tile < r1; tile += per_xcd) {
+    const GemmGroup gr = groups[find_group(groups, G, tile)];
+    const uint32_t m_tiles = (gr.m + BM - 1) / BM;
+    uint32_t mt, nt;
+    tile_coords(tile - gr.tile_start, m_tiles, n_tiles, SC, &mt, &nt);
+    const uint32_t m0 = mt * BM, n0 = nt * BN;
+    const uint64_t* wtab = reinterpret_cast<const uint64_t*>(gr.wtab);
+
+    const uint8_t* ap[A_LD];
+    const uint8_t* bp[B_LD];
+#pragma unroll
+    for (int i = 0; i < A_LD; i++) {
+      const uint32_t row = (t >> 3) + (NT / 8) * i;
+      uint32_t r = m0 + (row < BM ? row : 0);
+      r = r < gr.m ? r : gr.m - 1;
+      ap[i] = a_row(la, gr.row0 + r, 2) + ld_chunk * 16;
+    }
+#pragma unroll
+    for (int i = 0; i < B_LD; i++) {
+      const uint32_t row = (t >> 3) + (NT / 8) * i;
+      const uint64_t off = la.w_off + (uint64_t)(n0 + (row < BN ? row : 0)) * K * 2;
+      bp[i] = reinterpret_cast<const uint8_t*>(wtab[off >> kBlockShift]) + (off & (kBlock - 1)) + ld_chunk * 16;
+    }
+
+    f32x4 acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; i++)
+#pragma unroll
+      for (int jj = 0; jj < FN; jj++) acc[i][jj] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    u32x4 ra[A_LD], rb[B_LD];
+    gload<A_LD, A_CH, NT>(ra, ap, 0, t);
+    gload<B_LD, B_CH, NT>(rb, bp, 0, t);
+    sstore<A_LD, A_CH, NT>(As, ra, t, ld_chunk);
+    sstore<B_LD, B_CH, NT>(Bs, rb, t, ld_chunk);
+    __syncthreads();
+    for (uint32_t kt = 0; kt < KT; kt++) {
+      const uint32_t cur = kt & 1;
+      if (kt + 1 < KT) {
+        gload<A_LD, A_CH, NT>(ra, ap, kt + 1, t);
+        gload<B_LD, B_CH, NT>(rb, bp, kt + 1, t);
+      }
+#pragma unroll
+      for (int ks = 0; ks < 2; ks++) {
+        const uint32_t chunk = ks * 4 + (lane >> 4);
+        bf16x8 af[FM], bfr[FN];
+#pragma unroll
+        for (int i = 0; i < FM; i++) {
+          const uint32_t r = wm * WM + i * 16 + (lane & 15);
+          af[i] = *reinterpret_cast<const bf16x8*>(As + cur * A_STAGE + swz(r, chunk));
+        }
+#pragma unroll
+        for (int jj = 0; jj < FN; jj++) {
+          const uint32_t r = wn * WN + jj * 16 + (lane & 15);
+          bfr[jj] = *reinterpret_cast<const bf16x8*>(Bs + cur * B_STAGE + swz(r, chunk));
+        }
+#pragma unroll
+        for (int i = 0; i < FM; i++)
+#pragma unroll
+          for (int jj = 0; jj < FN; jj++)
+            acc[i][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[jj], acc[i][jj], 0, 0, 0);
+      }
+      if (kt + 1 < KT) {
+        sstore<A_LD, A_CH, NT>(As + (cur ^ 1) * A_STAGE, ra, t, ld_chunk);
+        sstore<B_LD, B_CH, NT>(Bs + (cur ^ 1) * B_STAGE, rb, t, ld_chunk);
+      }
+      __syncthreads();
+    }
+
+#pragma unroll
+    for (int i = 0; i < FM; i++) {
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const uint32_t r = m0 + wm * WM + i * 16 + 4 * (lane >> 4) + q;
+        if (r < gr.m) {
+          uint8_t* crow = c_row(la, gr.row0 + r, out_f32 ? 4 : 2);
+#pragma unroll
+          for (int jj = 0; jj < FN; jj++) {
+            const uint32_t col = n0 + wn * WN + jj * 16 + (lane & 15);
+            float v = acc[i][jj][q];
+            if (relu) v = v > 0.f ? v : 0.f;
+            if (out_f32) reinterpret_cast<float*>(crow)[col] = v;
+            else reinterpret_cast<__bf16*>(crow)[col] = (__bf16)v;
+          }
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Direct-to-LDS variant: K stages of 32 (64 B per row) in an S-deep ring,
+// filled by global_load_lds_dwordx4 (each wave instruction writes 1 KiB of
+// LDS: 16 rows x 64 B; lane i lands at byte 16 i, so it fetches the global
+// chunk that the swizzle puts there).  Loads for stage kt + S - 1 are issued
+// right after the barrier of iteration kt, so S - 1 stages are in flight
+// while one is computed.  Same MFMA and K order as the other shapes.
+constexpr int kRow3 = 64;  // bytes of a row per stage (32 BF16)
+
+// byte offset of chunk c (0..3) of row r in a [rows][32] stage; rows pair up
+// in 128-byte bank lines, so the chunk is XOR-ed with (r / 2) mod 4.
+__device__ __forceinline__ uint32_t swz3(uint32_t r, uint32_t c) { return r * kRow3 + ((c ^ ((r >> 1) & 3)) << 4); }
+
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  // s_waitcnt vmcnt(N), expcnt and lgkmcnt left unconstrained
+  __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
+template <int BM, int BN, int WM, int WN, int S>
+__device__ __forceinline__ void ggemm3(const GemmHdr* __restrict__ hdr, const GemmGroup* __restrict__ groups,
+                                       const LayerArgs la, uint8_t* lds) {
+  constexpr int NWN = BN / WN, NWM = BM / WM;
+  constexpr int NW = NWN * NWM, NT = 64 * NW;
+  constexpr int FM = WM / 16, FN = WN / 16;
+  constexpr uint32_t A_STAGE = BM * kRow3, B_STAGE = BN * kRow3, STAGE = A_STAGE + B_STAGE;
+  constexpr int A_INS = BM / 16 / NW, B_INS = BN / 16 / NW;  // 1 KiB load instructions per wave per stage
+  static_assert(A_INS * 16 * NW == BM && B_INS * 16 * NW == BN, "rows split evenly over waves");
+  constexpr int LPS = A_INS + B_INS;  // loads per wave per stage
+  constexpr uint32_t SC = 4;
+  typedef __attribute__((address_space(3))) void lds_void;
+
+  const uint32_t t = threadIdx.x, lane = t & 63;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  const uint32_t wm = wave / NWN, wn = wave % NWN;
+  const uint32_t N = la.N, K = la.K;
+  const uint32_t total = hdr->total_tiles, G = hdr->n_groups;
+  const bool out_f32 = la.flags & kOutF32, relu = la.flags & kRelu;
+  const uint32_t KT = K / 32;
+  const uint32_t n_tiles = N / BN;
+  const uint32_t lrow = lane >> 2, lslot = lane & 3;
+
+  const uint32_t xcd = blockIdx.x % kXcds, j = blockIdx.x / kXcds, per_xcd = gridDim.x / kXcds;
+  if (j >= per_xcd) return;
+  const uint32_t r0 = (uint32_t)(((uint64_t)total * xcd) / kXcds);
+  const uint32_t r1 = (uint32_t)(((uint64_t)total * (xcd + 1)) / kXcds);
+
+  for (uint32_t tile = r0 + j; tile < r1; tile += per_xcd) {
+    const GemmGroup gr = groups[find_group(groups, G, tile)];
+    const uint32_t m_tiles = (gr.m + BM - 1) / BM;
+    uint32_t mt, nt;
+    tile_coords(tile - gr.tile_start, m_tiles, n_tiles, SC, &mt, &nt);
+    const uint32_t m0 = mt * BM, n0 = nt * BN;
+    const uint64_t* wtab = reinterpret_cast<const uint64_t*>(gr.wtab);
+
+    // per lane: the global chunk it fetches for each of the wave's load instructions
+    const uint8_t* ap[A_INS];
+    const uint8_t* bp[B_INS];
+#pragma unroll
+    for (int q = 0; q < A_INS; q++) {
+      const uint32_t row = (wave * A_INS + q) * 16 + lrow;
+      uint32_t r = m0 + row;
+      r = r < gr.m ? r : gr.m - 1;
+      const uint32_t chunk = lslot ^ ((row >> 1) & 3);
+      ap[q] = a_row(la, gr.row0 + r, 2) + chunk * 16;
+    }
+#pragma unroll
+    for (int q = 0; q < B_INS; q++) {
+      const uint32_t row = (wave * B_INS + q) * 16 + lrow;
+      const uint64_t off = la.w_off + (uint64_t)(n0 + row) * K * 2;
+      const uint32_t chunk = lslot ^ ((row >> 1) & 3);
+      bp[q] = reinterpret_cast<const uint8_t*>(wtab[off >> kBlockShift]) + (off & (kBlock - 1)) + chunk * 16;
+    }
+    auto issue = [&](uint32_t kt) __attribute__((always_inline)) {
+      uint8_t* st = lds + (kt % S) * STAGE;
+#pragma unroll
+      for (int q = 0; q < A_INS; q++)
+        __builtin_amdgcn_global_load_lds((const void*)(ap[q] + kt * kRow3),
+                                         (lds_void*)(st + (wave * A_INS + q) * 1024), 16, 0, 0);
+#pragma unroll
+      for (int q = 0; q < B_INS; q++)
+        __builtin_amdgcn_global_load_lds((const void*)(bp[q] + kt * kRow3),
+                                         (lds_void*)(st + A_STAGE + (wave * B_INS + q) * 1024), 16, 0, 0);
+    };
+
+    f32x4 acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; i++)
+#pragma unroll
+      for (int jj = 0; jj < FN; jj++) acc[i][jj] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+#pragma unroll
+    for (int s0 = 0; s0 < S - 1; s0++)
+      if ((uint32_t)s0 < KT) issue(s0);
+    for (uint32_t kt = 0; kt < KT; kt++) {
+      // stage kt landed when at most (stages issued after it) x LPS loads remain
+      const uint32_t later = (KT - 1 - kt) < (uint32_t)(S - 2) ? (KT - 1 - kt) : (uint32_t)(S - 2);
+      if (later >= 2) wait_vm<2 * LPS>();
+      else if (later == 1) wait_vm<LPS>();
+      else wait_vm<0>();
+      // plain barrier: the wait above already covers this wave's stage-kt loads
+      __builtin_amdgcn_s_barrier();
+      if (kt + S - 1 < KT) issue(kt + S - 1);
+      const uint8_t* st = lds + (kt % S) * STAGE;
+      const uint32_t chunk = lane >> 4;
+      bf16x8 af[FM], bfr[FN];
+#pragma unroll
+      for (int i = 0; i < FM; i++) {
+        const uint32_t r = wm * WM + i * 16 + (lane & 15);
+        af[i] = *reinterpret_cast<const bf16x8*>(st + swz3(r, chunk));
+      }
+#pragma unroll
+      for (int jj = 0; jj < FN; jj++) {
+        const uint32_t r = wn * WN + jj * 16 + (lane & 15);
+        bfr[jj] = *reinterpret_cast<const bf16x8*>(st + A_STAGE + swz3(r, chunk));
+      }
+#pragma unroll
+      for (int i = 0; i < FM; i++)
+#pragma unroll
+        for (int jj = 0; jj < FN; jj++)
+          acc[i][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[jj], acc[i][jj], 0, 0, 0);
+    }
+    __syncthreads();  // the next tile's first loads overwrite stages still being read
+
+#pragma unroll
+    for (int i = 0; i < FM; i++) {
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const uint32_t r = m0 + wm * WM + i * 16 + 4 * (lane >> 4) + q;
+        if (r < gr.m) {
+          uint8_t* crow = c_row(la, gr.row0 + r, out_f32 ? 4 : 2);
+#pragma unroll
+          for (int jj = 0; jj < FN; jj++) {
+            const uint32_t col = n0 + wn * WN + jj * 16 + (lane & 15);
+            float v = acc[i][jj][q];
+            if (relu) v = v > 0.f ? v : 0.f;
+            if (out_f32) reinterpret_cast<float*>(crow)[col] = v;
+            else reinterpret_cast<__bf16*>(crow)[col] = (__bf16)v;
+          }
+        }
+      }
+    }
+  }
+}
+
 }  // namespace
 
 #define SAGE_GGEMM(BM, BN, WM, WN, OCC)                                                               \
@@ -196,6 +479,36 @@ SAGE_GGEMM(64, 128, 32, 64, 2)
 SAGE_GGEMM(128, 128, 64, 64, 2)
 SAGE_GGEMM(256, 128, 128, 64, 1)
 SAGE_GGEMM(128, 256, 64, 128, 1)
+
+// large tiles, 8 waves, XCD-aware tile ranges
+#define SAGE_GGEMM2(BM, BN, WM, WN)                                                                   \
+  extern "C" __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN), 1) void ggemm2_bf16_##BM##x##BN(  \
+      const GemmHdr* __restrict__ hdr, const GemmGroup* __restrict__ groups, LayerArgs la) {           \
+    __shared__ __attribute__((aligned(16))) uint8_t lds[2 * (BM + BN) * kRowBytes];                    \
+    ggemm2<BM, BN, WM, WN>(hdr, groups, la, lds);                                                      \
+  }
+
+SAGE_GGEMM2(256, 256, 128, 64)
+SAGE_GGEMM2(256, 128, 128, 32)
+SAGE_GGEMM2(128, 256, 64, 64)
+// 4 waves of 128 x 128: fewer LDS reads per MFMA (accumulators in AGPRs)
+#define SAGE_GGEMM2W(BM, BN, WM, WN)                                                                  \
+  extern "C" __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN), 1) void ggemm4_bf16_##BM##x##BN(  \
+      const GemmHdr* __restrict__ hdr, const GemmGroup* __restrict__ groups, LayerArgs la) {           \
+    __shared__ __attribute__((aligned(16))) uint8_t lds[2 * (BM + BN) * kRowBytes];                    \
+    ggemm2<BM, BN, WM, WN>(hdr, groups, la, lds);                                                      \
+  }
+SAGE_GGEMM2W(256, 256, 128, 128)
+
+// direct-to-LDS, S-stage ring
+#define SAGE_GGEMM3(BM, BN, WM, WN, S)                                                                \
+  extern "C" __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN), 1) void ggemm3_bf16_##BM##x##BN(  \
+      const GemmHdr* __restrict__ hdr, const GemmGroup* __restrict__ groups, LayerArgs la) {           \
+    __shared__ __attribute__((aligned(1024))) uint8_t lds[S * (BM + BN) * kRow3];                      \
+    ggemm3<BM, BN, WM, WN, S>(hdr, groups, la, lds);                                                   \
+  }
+SAGE_GGEMM3(256, 256, 128, 64, 4)
+SAGE_GGEMM3(256, 128, 128, 32, 4)
 
 // ---------------------------------------------------------------- FP32 MLP
 // Tiles: (group, block of 8 output columns); wave w of the workgroup owns

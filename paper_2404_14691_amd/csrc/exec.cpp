@@ -31,13 +31,18 @@ size_t out_bytes_for(const sage_fn_desc& d, uint32_t batch) {
 // ------------------------------------------------------------- tile shapes
 struct TileShape {
   const char* name;
-  uint32_t bm, bn, occupancy;
+  uint32_t bm, bn, occupancy, threads;
 };
+// ggemm2_* deal contiguous tile ranges to the 8 XCDs: their grid must be a
+// multiple of 8 (it is #CUs x occupancy).
 static const TileShape kShapes[] = {
-    {"ggemm_bf16_16x64", 16, 64, 2},    {"ggemm_bf16_32x64", 32, 64, 2},
-    {"ggemm_bf16_32x128", 32, 128, 2},  {"ggemm_bf16_64x128", 64, 128, 2},
-    {"ggemm_bf16_128x128", 128, 128, 2}, {"ggemm_bf16_256x128", 256, 128, 1},
-    {"ggemm_bf16_128x256", 128, 256, 1},
+    {"ggemm_bf16_16x64", 16, 64, 2, 256},     {"ggemm_bf16_32x64", 32, 64, 2, 256},
+    {"ggemm_bf16_32x128", 32, 128, 2, 256},   {"ggemm_bf16_64x128", 64, 128, 2, 256},
+    {"ggemm_bf16_128x128", 128, 128, 2, 256}, {"ggemm_bf16_256x128", 256, 128, 1, 256},
+    {"ggemm_bf16_128x256", 128, 256, 1, 256}, {"ggemm2_bf16_256x256", 256, 256, 1, 512},
+    {"ggemm2_bf16_256x128", 256, 128, 1, 512}, {"ggemm2_bf16_128x256", 128, 256, 1, 512},
+    {"ggemm4_bf16_256x256", 256, 256, 1, 256}, {"ggemm3_bf16_256x256", 256, 256, 1, 512},
+    {"ggemm3_bf16_256x128", 256, 128, 1, 512},
 };
 
 static const TileShape& shape_of(const std::string& name) {
@@ -123,13 +128,13 @@ void finish_flight(Ctx& c, int f) {
   c.timer.collect();
 }
 
-static void launch_kernel(hipFunction_t k, uint32_t grid, hipStream_t s, const GemmHdr* hdr, const GemmGroup* groups,
-                          const LayerArgs& la) {
+static void launch_kernel(hipFunction_t k, uint32_t grid, uint32_t threads, hipStream_t s, const GemmHdr* hdr,
+                          const GemmGroup* groups, const LayerArgs& la) {
   const GemmHdr* h = hdr;
   const GemmGroup* g = groups;
   LayerArgs a = la;
   void* params[] = {&h, &g, &a};
-  HIPX(hipModuleLaunchKernel(k, grid, 1, 1, 256, 1, 1, 0, s, params, nullptr));
+  HIPX(hipModuleLaunchKernel(k, grid, 1, 1, threads, 1, 1, 0, s, params, nullptr));
 }
 
 // ---------------------------------------------------------------- MLP group
@@ -162,14 +167,15 @@ int launch_mlp_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, int fl
   for (const Call& cl : calls) M += cl.inv->batch;
 
   std::string kname;
-  uint32_t bm = 8, bn = 8, occ = 4;
+  uint32_t bm = 8, bn = 8, occ = 4, threads = 256;
   if (bf16) {
-    kname = tuned_kernel(c, W, M);
+    kname = c.force_tile.empty() ? tuned_kernel(c, W, M) : c.force_tile;
     const TileShape& ts = shape_of(kname);
     if (W % ts.bn) fail(SAGE_EINVAL, "tile %s does not divide width %u", kname.c_str(), W);
     bm = ts.bm;
     bn = ts.bn;
     occ = ts.occupancy;
+    threads = ts.threads;
   } else {
     kname = "mlp_f32_layer";
   }
@@ -230,7 +236,8 @@ int launch_mlp_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, int fl
 
   Module* mod = calls[0].inv->fn->mod;
   hipFunction_t kfn = mod->get(kname.c_str());
-  const uint32_t grid = (uint32_t)c.cus * occ;
+  uint32_t grid = (uint32_t)c.cus * occ;
+  if (bf16) grid = std::max<uint32_t>(8, grid / 8 * 8);  // XCD-ranged kernels need a multiple of 8
   const GemmHdr* d_hdr = reinterpret_cast<const GemmHdr*>(F.d_meta);
   const GemmGroup* d_grp = reinterpret_cast<const GemmGroup*>(F.d_meta + kMetaGroupsOff);
   const uint64_t* d_in_tab = reinterpret_cast<const uint64_t*>(F.d_meta + kMetaTabOff);
@@ -256,7 +263,7 @@ int launch_mlp_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, int fl
     if (it == F.graphs.end()) {
       hipStream_t cap = s;
       HIPX(hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed));
-      for (uint32_t l = 0; l < L; l++) launch_kernel(kfn, grid, cap, d_hdr, d_grp, layer_args(l));
+      for (uint32_t l = 0; l < L; l++) launch_kernel(kfn, grid, threads, cap, d_hdr, d_grp, layer_args(l));
       hipGraph_t g = nullptr;
       HIPX(hipStreamEndCapture(cap, &g));
       hipGraphExec_t ex = nullptr;
@@ -266,7 +273,7 @@ int launch_mlp_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, int fl
     }
     HIPX(hipGraphLaunch(it->second, s));
   } else {
-    for (uint32_t l = 0; l < L; l++) launch_kernel(kfn, grid, s, d_hdr, d_grp, layer_args(l));
+    for (uint32_t l = 0; l < L; l++) launch_kernel(kfn, grid, threads, s, d_hdr, d_grp, layer_args(l));
   }
   c.timer.stop(tok, s);
   if (host_out) HIPX(hipMemcpyAsync(F.h_out, F.d_out, (size_t)M * W * 4, hipMemcpyDeviceToHost, s));
@@ -433,9 +440,9 @@ std::string tuned_kernel(Ctx& c, uint32_t width, uint32_t rows) {
     la.N = la.K = width;
     la.flags = kRelu;
     hipFunction_t k = mod->get(ts.name);
-    const uint32_t grid = (uint32_t)c.cus * ts.occupancy;
+    const uint32_t grid = std::max<uint32_t>(8, (uint32_t)c.cus * ts.occupancy / 8 * 8);
     auto run = [&] {
-      launch_kernel(k, grid, s, (const GemmHdr*)meta, (const GemmGroup*)(meta + 16), la);
+      launch_kernel(k, grid, ts.threads, s, (const GemmHdr*)meta, (const GemmGroup*)(meta + 16), la);
     };
     run();
     const int reps = 5;

@@ -99,20 +99,37 @@ constexpr uint32_t kNone = 0xFFFFFFFFu;
 // with live setups that use the class, so a setup or release touches the
 // classes only when its function's live count crosses zero.  The class's
 // reference count in the paper-level sense (live setups using it) is the
-// sum of the live counts of those functions.
+// sum of the live counts of those functions.  Class storage is recycled;
+// `seq` (creation order) is what orders classes.
 struct Class {
   uint64_t fp = 0;
+  uint64_t seq = 0;           // creation order
   uint32_t len = 0;
   uint32_t slot = kNone;
   uint32_t active = 0;        // functions with live setups using the class
   uint32_t members = 0;       // registered (fn, block) references
   uint32_t next = kNone;      // next class in its fingerprint chain
   uint32_t mark = 0;          // protection stamp of the running registration / reload
+  uint32_t lru_prev = kNone, lru_next = kNone;
   bool alive = false;
   bool in_lru = false;
   bool indexed = false;
-  std::list<uint32_t>::iterator lru_it;
   const uint8_t* pending = nullptr;  // device bytes of its first block while its chunk is in flight
+};
+
+// Open-addressing map fingerprint -> first class of its chain.
+class FpIndex {
+ public:
+  uint32_t find(uint64_t fp) const;
+  void set(uint64_t fp, uint32_t head);  // insert or overwrite
+  void erase(uint64_t fp);
+  void clear();
+
+ private:
+  void grow();
+  std::vector<uint64_t> key_;
+  std::vector<uint32_t> val_;  // kNone = empty
+  size_t mask_ = 0, n_ = 0;
 };
 
 class Pool {
@@ -124,29 +141,51 @@ class Pool {
   }
   // Take a free slot, growing the arena up to the budget, else evicting the
   // front unreferenced class that `protect` does not hold.  kNone if none.
-  uint32_t alloc_slot(const std::function<bool(uint32_t)>& protect);
+  template <class Protect>
+  uint32_t alloc_slot(const Protect& protect);
   void free_slot(uint32_t s) { free_.push_back(s); used_--; }
   uint32_t new_class(uint64_t fp, uint32_t len);
-  void drop_class(uint32_t c);          // dead class: slot freed, index entry removed
+  void drop_class(uint32_t c);          // dead class: slot freed, index entry removed, storage recycled
   void evict(uint32_t c);
   void index_add(uint32_t c);           // append to the end of its fingerprint chain
   void index_remove(uint32_t c);
   void lru_back(uint32_t c);
   void lru_remove(uint32_t c);
-  uint32_t chain_head(uint64_t fp) const;  // first indexed class with this fingerprint, or kNone
+  uint32_t lru_front() const { return lru_head_; }
+  uint32_t chain_head(uint64_t fp) const { return index_.find(fp); }
   uint32_t new_mark() { return ++mark_; }
+  bool by_seq(uint32_t a, uint32_t b) const { return cls[a].seq < cls[b].seq; }
 
   std::vector<Class> cls;
-  std::list<uint32_t> lru;
-  uint64_t budget = 0, used_ = 0, evictions = 0, epoch = 0;
+  uint64_t budget = 0, used_ = 0, evictions = 0, epoch = 0, live_classes = 0;
 
  private:
+  bool grow_arena();
   std::vector<uint8_t*> segs_;
   size_t seg_slots_ = 16384;
   std::vector<uint32_t> free_;
-  std::unordered_map<uint64_t, uint32_t> index_;  // fingerprint -> chain head
+  std::vector<uint32_t> free_cls_;
+  FpIndex index_;
+  uint32_t lru_head_ = kNone, lru_tail_ = kNone;
   uint32_t mark_ = 0;
+  uint64_t seq_ = 0;
 };
+
+template <class Protect>
+uint32_t Pool::alloc_slot(const Protect& protect) {
+  if (free_.empty() && used_ < budget) grow_arena();
+  if (free_.empty() || used_ >= budget) {
+    uint32_t victim = lru_head_;
+    while (victim != kNone && protect(victim)) victim = cls[victim].lru_next;
+    if (victim == kNone) return kNone;
+    evict(victim);
+  }
+  if (free_.empty()) return kNone;
+  const uint32_t s = free_.back();
+  free_.pop_back();
+  used_++;
+  return s;
+}
 
 // --------------------------------------------------------------- modules
 struct Module {
@@ -278,7 +317,7 @@ struct Ctx {
   std::map<int, std::unique_ptr<Module>> modules;  // per kind
   std::mutex module_mu;
   std::map<uint64_t, std::unique_ptr<Fn>> fns;
-  std::map<uint64_t, std::unique_ptr<Inv>> invs;
+  std::unordered_map<uint64_t, std::unique_ptr<Inv>> invs;
   std::vector<Flight> flights;
   size_t next_flight = 0;
   uint64_t next_id = 1;
@@ -289,11 +328,13 @@ struct Ctx {
   double t_register = 0, t_code = 0, t_fp_wait = 0, t_dedup = 0, t_verify = 0, t_setup = 0, t_invoke = 0;
   Serve* serve = nullptr;                    // running serving loop, if any
   Worker worker;                             // code branch of fn_register
+  std::string force_tile;                    // SAGE_TILE: fixed GEMM tile shape (tests)
   bool test_fp_const = false;                // force every fingerprint equal (collision test)
   uint64_t test_fp_value = 0;
 
   bool is_pinned(const void* p, size_t n) const;
   int max_groups_stream() const { return cus * 8; }
+  int max_groups_copy() const { return cus * 32; }
 };
 
 // ------------------------------------------------------------- components

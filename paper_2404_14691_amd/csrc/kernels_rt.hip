@@ -83,56 +83,85 @@ __global__ __launch_bounds__(256) void fp64k_kernel(const uint8_t* __restrict__ 
   }
 }
 
-// One workgroup per operation.  Full blocks move as 16 x 16 B per thread,
-// all loads first; short blocks fall back to a strided loop plus bytes.
+// One block operation by one workgroup: COPY moves len bytes, VERIFY
+// compares them (result = 1 when any byte differs).  Full blocks move as
+// 16 x 16 B per thread with all loads first; short blocks use a strided
+// loop plus single bytes.
+__device__ __forceinline__ void block_op(const BlkOp& op, uint32_t* result, uint32_t t) {
+  const u32x4* s = reinterpret_cast<const u32x4*>(op.src);
+  const uint32_t nvec = op.len >> 4;
+  if (op.op == 0) {
+    u32x4* d = reinterpret_cast<u32x4*>(op.dst);
+    if (nvec == kBlock / 16) {
+      u32x4 v[16];
+#pragma unroll
+      for (int i = 0; i < 16; i++) v[i] = __builtin_nontemporal_load(s + t + i * 256);
+#pragma unroll
+      for (int i = 0; i < 16; i++) __builtin_nontemporal_store(v[i], d + t + i * 256);
+    } else {
+      for (uint32_t i = t; i < nvec; i += 256) d[i] = s[i];
+      const uint32_t q = nvec * 16 + t;
+      if (q < op.len) reinterpret_cast<uint8_t*>(op.dst)[q] = reinterpret_cast<const uint8_t*>(op.src)[q];
+    }
+  } else {
+    const u32x4* d = reinterpret_cast<const u32x4*>(op.dst);
+    int diff = 0;
+    if (nvec == kBlock / 16) {
+      u32x4 v[8], w[8];
+#pragma unroll
+      for (int h = 0; h < 2; h++) {
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+          v[i] = __builtin_nontemporal_load(s + t + (h * 8 + i) * 256);
+          w[i] = __builtin_nontemporal_load(d + t + (h * 8 + i) * 256);
+        }
+#pragma unroll
+        for (int i = 0; i < 8; i++)
+          diff |= (v[i].x != w[i].x) | (v[i].y != w[i].y) | (v[i].z != w[i].z) | (v[i].w != w[i].w);
+      }
+    } else {
+      for (uint32_t i = t; i < nvec; i += 256) {
+        const u32x4 a = s[i], b = d[i];
+        diff |= (a.x != b.x) | (a.y != b.y) | (a.z != b.z) | (a.w != b.w);
+      }
+      const uint32_t q = nvec * 16 + t;
+      if (q < op.len)
+        diff |= reinterpret_cast<const uint8_t*>(op.src)[q] != reinterpret_cast<const uint8_t*>(op.dst)[q];
+    }
+    diff = __syncthreads_or(diff);
+    if (t == 0) *result = diff ? 1u : 0u;
+  }
+}
+
+// Two operations per workgroup iteration: when both are full-block COPYs
+// all 32 loads of the pair are in flight before the first store
+// (nontemporal both ways: the data is not read again soon).
 __global__ __launch_bounds__(256) void blkcopy_kernel(const BlkOp* __restrict__ ops, uint32_t n,
                                                       uint32_t* __restrict__ result) {
   const uint32_t t = threadIdx.x;
-  for (uint32_t o = blockIdx.x; o < n; o += gridDim.x) {
-    const BlkOp op = ops[o];
-    const u32x4* s = reinterpret_cast<const u32x4*>(op.src);
-    const uint32_t nvec = op.len >> 4;
-    if (op.op == 0) {
-      u32x4* d = reinterpret_cast<u32x4*>(op.dst);
-      if (nvec == kBlock / 16) {
-        u32x4 v[16];
+  for (uint32_t o = blockIdx.x * 2u; o < n; o += gridDim.x * 2u) {
+    const BlkOp op0 = ops[o];
+    const bool has1 = o + 1 < n;
+    const BlkOp op1 = has1 ? ops[o + 1] : op0;
+    if (has1 && op0.op == 0 && op1.op == 0 && op0.len == kBlock && op1.len == kBlock) {
+      const u32x4* s0 = reinterpret_cast<const u32x4*>(op0.src);
+      const u32x4* s1 = reinterpret_cast<const u32x4*>(op1.src);
+      u32x4* d0 = reinterpret_cast<u32x4*>(op0.dst);
+      u32x4* d1 = reinterpret_cast<u32x4*>(op1.dst);
+      u32x4 v[32];
 #pragma unroll
-        for (int i = 0; i < 16; i++) v[i] = __builtin_nontemporal_load(s + t + i * 256);
+      for (int i = 0; i < 16; i++) {
+        v[i] = __builtin_nontemporal_load(s0 + t + i * 256);
+        v[16 + i] = __builtin_nontemporal_load(s1 + t + i * 256);
+      }
 #pragma unroll
-        for (int i = 0; i < 16; i++) d[t + i * 256] = v[i];
-      } else {
-        for (uint32_t i = t; i < nvec; i += 256) d[i] = s[i];
-        const uint32_t q = nvec * 16 + t;
-        if (q < op.len)
-          reinterpret_cast<uint8_t*>(op.dst)[q] = reinterpret_cast<const uint8_t*>(op.src)[q];
+      for (int i = 0; i < 16; i++) {
+        __builtin_nontemporal_store(v[i], d0 + t + i * 256);
+        __builtin_nontemporal_store(v[16 + i], d1 + t + i * 256);
       }
     } else {
-      const u32x4* d = reinterpret_cast<const u32x4*>(op.dst);
-      int diff = 0;
-      if (nvec == kBlock / 16) {
-        u32x4 v[8], w[8];
-#pragma unroll
-        for (int h = 0; h < 2; h++) {
-#pragma unroll
-          for (int i = 0; i < 8; i++) {
-            v[i] = __builtin_nontemporal_load(s + t + (h * 8 + i) * 256);
-            w[i] = __builtin_nontemporal_load(d + t + (h * 8 + i) * 256);
-          }
-#pragma unroll
-          for (int i = 0; i < 8; i++)
-            diff |= (v[i].x != w[i].x) | (v[i].y != w[i].y) | (v[i].z != w[i].z) | (v[i].w != w[i].w);
-        }
-      } else {
-        for (uint32_t i = t; i < nvec; i += 256) {
-          const u32x4 a = s[i], b = d[i];
-          diff |= (a.x != b.x) | (a.y != b.y) | (a.z != b.z) | (a.w != b.w);
-        }
-        const uint32_t q = nvec * 16 + t;
-        if (q < op.len)
-          diff |= reinterpret_cast<const uint8_t*>(op.src)[q] != reinterpret_cast<const uint8_t*>(op.dst)[q];
-      }
-      diff = __syncthreads_or(diff);
-      if (t == 0) result[o] = diff ? 1u : 0u;
+      block_op(op0, result + o, t);
+      if (has1) block_op(op1, result + o + 1, t);
     }
   }
 }
@@ -148,7 +177,8 @@ hipError_t launch_fp64k(const void* data, uint64_t nbytes, uint64_t* out, int ma
 
 hipError_t launch_blkcopy(const BlkOp* ops, uint32_t n, uint32_t* result, int max_groups, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  const uint32_t grid = n < (uint32_t)max_groups ? n : (uint32_t)max_groups;
+  const uint32_t pairs = (n + 1) / 2;
+  const uint32_t grid = pairs < (uint32_t)max_groups ? pairs : (uint32_t)max_groups;
   hipLaunchKernelGGL(blkcopy_kernel, dim3(grid), dim3(256), 0, s, ops, n, result);
   return hipGetLastError();
 }

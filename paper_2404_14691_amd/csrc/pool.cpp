@@ -1,10 +1,80 @@
 // Shared block pool: an arena of 64 KiB slots, the fingerprint index of
 // resident classes, references and the eviction order of unreferenced
-// classes (front = least recently released).
+// classes (front = least recently released).  All lists are intrusive in
+// the class records, so the steady state allocates nothing.
 #include "internal.h"
 
 namespace sage {
 
+// ---------------------------------------------------------------- FpIndex
+static inline size_t fp_hash(uint64_t fp) { return (size_t)(fp ^ (fp >> 29)) * 0x9E3779B97F4A7C15ull >> 7; }
+
+uint32_t FpIndex::find(uint64_t fp) const {
+  if (!n_) return kNone;
+  for (size_t i = fp_hash(fp) & mask_;; i = (i + 1) & mask_) {
+    if (val_[i] == kNone) return kNone;
+    if (key_[i] == fp) return val_[i];
+  }
+}
+
+void FpIndex::grow() {
+  std::vector<uint64_t> k = std::move(key_);
+  std::vector<uint32_t> v = std::move(val_);
+  const size_t cap = k.empty() ? 1024 : k.size() * 2;
+  key_.assign(cap, 0);
+  val_.assign(cap, kNone);
+  mask_ = cap - 1;
+  n_ = 0;
+  for (size_t i = 0; i < k.size(); i++)
+    if (v[i] != kNone) set(k[i], v[i]);
+}
+
+void FpIndex::set(uint64_t fp, uint32_t head) {
+  if ((n_ + 1) * 2 > key_.size()) grow();
+  for (size_t i = fp_hash(fp) & mask_;; i = (i + 1) & mask_) {
+    if (val_[i] == kNone) {
+      key_[i] = fp;
+      val_[i] = head;
+      n_++;
+      return;
+    }
+    if (key_[i] == fp) {
+      val_[i] = head;
+      return;
+    }
+  }
+}
+
+// Linear probing with backward-shift deletion (no tombstones).
+void FpIndex::erase(uint64_t fp) {
+  if (!n_) return;
+  size_t i = fp_hash(fp) & mask_;
+  for (;; i = (i + 1) & mask_) {
+    if (val_[i] == kNone) return;
+    if (key_[i] == fp) break;
+  }
+  for (size_t j = (i + 1) & mask_;; j = (j + 1) & mask_) {
+    if (val_[j] == kNone) break;
+    const size_t home = fp_hash(key_[j]) & mask_;
+    // move j back to i when its home is not in the cyclic range (i, j]
+    const bool in_range = i <= j ? (home > i && home <= j) : (home > i || home <= j);
+    if (!in_range) {
+      key_[i] = key_[j];
+      val_[i] = val_[j];
+      i = j;
+    }
+  }
+  val_[i] = kNone;
+  n_--;
+}
+
+void FpIndex::clear() {
+  key_.clear();
+  val_.clear();
+  mask_ = n_ = 0;
+}
+
+// ---------------------------------------------------------------- Pool
 void Pool::init(uint64_t budget_slots, size_t seg_slots) {
   budget = budget_slots;
   seg_slots_ = seg_slots;
@@ -14,59 +84,55 @@ void Pool::destroy() {
   for (uint8_t* s : segs_) (void)hipFree(s);
   segs_.clear();
   free_.clear();
+  free_cls_.clear();
   index_.clear();
-  lru.clear();
   cls.clear();
-  used_ = 0;
+  lru_head_ = lru_tail_ = kNone;
+  used_ = live_classes = 0;
 }
 
-uint32_t Pool::alloc_slot(const std::function<bool(uint32_t)>& protect) {
+bool Pool::grow_arena() {
   const uint64_t cap = (uint64_t)segs_.size() * seg_slots_;
-  if (free_.empty() && used_ < budget && cap < budget) {
-    const uint64_t n = std::min<uint64_t>(seg_slots_, budget - cap);
-    uint8_t* p = nullptr;
-    if (hipMalloc(&p, n * kBlock) == hipSuccess) {
-      const uint32_t base = (uint32_t)cap;
-      segs_.push_back(p);
-      for (uint64_t i = n; i-- > 0;) free_.push_back(base + (uint32_t)i);
-    } else {
-      (void)hipGetLastError();
-      budget = used_;  // the device is full: the budget stops at what is held
-    }
+  if (cap >= budget) return false;
+  const uint64_t n = std::min<uint64_t>(seg_slots_, budget - cap);
+  uint8_t* p = nullptr;
+  if (hipMalloc(&p, n * kBlock) != hipSuccess) {
+    (void)hipGetLastError();
+    budget = used_;  // the device is full: the budget stops at what is held
+    return false;
   }
-  if (free_.empty() || used_ >= budget) {
-    uint32_t victim = kNone;
-    for (uint32_t c : lru)
-      if (!protect(c)) {
-        victim = c;
-        break;
-      }
-    if (victim == kNone) return kNone;
-    evict(victim);
-  }
-  if (free_.empty()) return kNone;
-  const uint32_t s = free_.back();
-  free_.pop_back();
-  used_++;
-  return s;
+  const uint32_t base = (uint32_t)cap;
+  segs_.push_back(p);
+  for (uint64_t i = n; i-- > 0;) free_.push_back(base + (uint32_t)i);
+  return true;
 }
 
 uint32_t Pool::new_class(uint64_t fp, uint32_t len) {
-  Class c;
-  c.fp = fp;
-  c.len = len;
-  c.alive = true;
-  cls.push_back(c);
-  return (uint32_t)cls.size() - 1;
+  uint32_t c;
+  if (!free_cls_.empty()) {
+    c = free_cls_.back();
+    free_cls_.pop_back();
+  } else {
+    cls.emplace_back();
+    c = (uint32_t)cls.size() - 1;
+  }
+  Class& k = cls[c];
+  k = Class{};
+  k.fp = fp;
+  k.len = len;
+  k.seq = seq_++;
+  k.alive = true;
+  live_classes++;
+  return c;
 }
 
 void Pool::index_add(uint32_t c) {
   cls[c].next = kNone;
-  auto it = index_.find(cls[c].fp);
-  if (it == index_.end()) {
-    index_.emplace(cls[c].fp, c);
+  const uint32_t h = index_.find(cls[c].fp);
+  if (h == kNone) {
+    index_.set(cls[c].fp, c);
   } else {
-    uint32_t t = it->second;
+    uint32_t t = h;
     while (cls[t].next != kNone) t = cls[t].next;
     cls[t].next = c;
   }
@@ -75,39 +141,39 @@ void Pool::index_add(uint32_t c) {
 
 void Pool::index_remove(uint32_t c) {
   if (!cls[c].indexed) return;
-  auto it = index_.find(cls[c].fp);
-  if (it != index_.end()) {
-    if (it->second == c) {
-      if (cls[c].next == kNone) index_.erase(it);
-      else it->second = cls[c].next;
-    } else {
-      uint32_t t = it->second;
-      while (t != kNone && cls[t].next != c) t = cls[t].next;
-      if (t != kNone) cls[t].next = cls[c].next;
-    }
+  const uint32_t h = index_.find(cls[c].fp);
+  if (h == c) {
+    if (cls[c].next == kNone) index_.erase(cls[c].fp);
+    else index_.set(cls[c].fp, cls[c].next);
+  } else if (h != kNone) {
+    uint32_t t = h;
+    while (t != kNone && cls[t].next != c) t = cls[t].next;
+    if (t != kNone) cls[t].next = cls[c].next;
   }
   cls[c].next = kNone;
   cls[c].indexed = false;
 }
 
-uint32_t Pool::chain_head(uint64_t fp) const {
-  auto it = index_.find(fp);
-  return it == index_.end() ? kNone : it->second;
-}
-
-void Pool::lru_back(uint32_t c) {
-  Class& k = cls[c];
-  if (k.in_lru) lru.erase(k.lru_it);
-  lru.push_back(c);
-  k.lru_it = std::prev(lru.end());
-  k.in_lru = true;
-}
-
 void Pool::lru_remove(uint32_t c) {
   Class& k = cls[c];
   if (!k.in_lru) return;
-  lru.erase(k.lru_it);
+  if (k.lru_prev != kNone) cls[k.lru_prev].lru_next = k.lru_next;
+  else lru_head_ = k.lru_next;
+  if (k.lru_next != kNone) cls[k.lru_next].lru_prev = k.lru_prev;
+  else lru_tail_ = k.lru_prev;
+  k.lru_prev = k.lru_next = kNone;
   k.in_lru = false;
+}
+
+void Pool::lru_back(uint32_t c) {
+  lru_remove(c);
+  Class& k = cls[c];
+  k.lru_prev = lru_tail_;
+  k.lru_next = kNone;
+  if (lru_tail_ != kNone) cls[lru_tail_].lru_next = c;
+  else lru_head_ = c;
+  lru_tail_ = c;
+  k.in_lru = true;
 }
 
 void Pool::evict(uint32_t c) {
@@ -124,6 +190,7 @@ void Pool::evict(uint32_t c) {
 
 void Pool::drop_class(uint32_t c) {
   Class& k = cls[c];
+  if (!k.alive) return;
   lru_remove(c);
   index_remove(c);
   if (k.slot != kNone) {
@@ -132,6 +199,8 @@ void Pool::drop_class(uint32_t c) {
   }
   k.alive = false;
   k.pending = nullptr;
+  live_classes--;
+  free_cls_.push_back(c);
 }
 
 }  // namespace sage

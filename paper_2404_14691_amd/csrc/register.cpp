@@ -300,7 +300,7 @@ void register_shared(Ctx& c, Fn& f) {
       c.t_dedup += tv - t1;
       HIPX(hipMemcpyAsync(R.dops[slot], ops, nops * sizeof(BlkOp), hipMemcpyHostToDevice, s));
       const int tok = c.timer.start("blkcopy", s, 1);
-      HIPX(launch_blkcopy(R.dops[slot], nops, R.dres[slot], c.max_groups_stream(), s));
+      HIPX(launch_blkcopy(R.dops[slot], nops, R.dres[slot], c.max_groups_copy(), s));
       c.timer.stop(tok, s);
       HIPX(hipMemcpyAsync(R.hres[slot], R.dres[slot], nops * 4, hipMemcpyDeviceToHost, s));
       HIPX(hipStreamSynchronize(s));
@@ -349,9 +349,15 @@ void register_shared(Ctx& c, Fn& f) {
     throw;
   }
   for (uint32_t cl : f.cls) P.cls[cl].members++;
-  f.distinct = f.cls;
-  std::sort(f.distinct.begin(), f.distinct.end());
-  f.distinct.erase(std::unique(f.distinct.begin(), f.distinct.end()), f.distinct.end());
+  // distinct classes in creation order (the order ties are broken in)
+  const uint32_t dmark = P.new_mark();
+  f.distinct.clear();
+  for (uint32_t cl : f.cls)
+    if (P.cls[cl].mark != dmark) {
+      P.cls[cl].mark = dmark;
+      f.distinct.push_back(cl);
+    }
+  std::sort(f.distinct.begin(), f.distinct.end(), [&](uint32_t a, uint32_t b) { return P.by_seq(a, b); });
   for (uint32_t cl : f.distinct)
     if (P.cls[cl].active == 0) P.lru_back(cl);
   c.h2d += f.ro_bytes;
@@ -433,7 +439,7 @@ void reload_classes(Ctx& c, Fn& f, const std::vector<uint32_t>& missing) {
     if (staged) HIPX(hipMemcpyAsync(R.dev[0], R.host[0], staged * kBlock, hipMemcpyHostToDevice, s));
     HIPX(hipMemcpyAsync(R.dops[0], ops, nops * sizeof(BlkOp), hipMemcpyHostToDevice, s));
     const int tok = c.timer.start("blkcopy", s, 1);
-    HIPX(launch_blkcopy(R.dops[0], nops, R.dres[0], c.max_groups_stream(), s));
+    HIPX(launch_blkcopy(R.dops[0], nops, R.dres[0], c.max_groups_copy(), s));
     c.timer.stop(tok, s);
     HIPX(hipStreamSynchronize(s));
   }

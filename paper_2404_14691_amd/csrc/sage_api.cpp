@@ -106,10 +106,8 @@ uint64_t setup_internal(Ctx& c, uint64_t id, uint32_t batch) {
         for (uint32_t cl : f.distinct) P.cls[cl].mark = mark;
         std::vector<uint32_t> victims;
         const uint64_t short_by = missing.size() - free_slots;
-        for (uint32_t cl : P.lru) {
-          if (victims.size() >= short_by) break;
+        for (uint32_t cl = P.lru_front(); cl != kNone && victims.size() < short_by; cl = P.cls[cl].lru_next)
           if (P.cls[cl].mark != mark) victims.push_back(cl);
-        }
         if (victims.size() < short_by)
           fail(SAGE_ENOMEM, "cannot admit: %zu blocks missing, %llu evictable", missing.size(),
                (unsigned long long)(free_slots + victims.size()));
@@ -229,6 +227,7 @@ sage_status sage_open(int device, const sage_config* cfg, sage_ctx** out) {
     flights_init(c);
     tune_load(c);
     c.worker.start(device);
+    if (const char* e = std::getenv("SAGE_TILE")) c.force_tile = e;
     if (const char* e = std::getenv("SAGE_TEST_FP_CONST")) {
       c.test_fp_const = true;
       c.test_fp_value = std::strtoull(e, nullptr, 0);
@@ -595,7 +594,7 @@ sage_status sage_blkcopy(sage_ctx* p, const sage_blk_op* ops, size_t n, uint32_t
     if (n > 0xFFFFFFFFull) fail(SAGE_EINVAL, "too many operations");
     hipStream_t s = stream ? (hipStream_t)stream : c.ctl;
     const int tok = c.timer.start("blkcopy", s, 1);
-    HIPX(launch_blkcopy(reinterpret_cast<const BlkOp*>(ops), (uint32_t)n, result, c.max_groups_stream(), s));
+    HIPX(launch_blkcopy(reinterpret_cast<const BlkOp*>(ops), (uint32_t)n, result, c.max_groups_copy(), s));
     c.timer.stop(tok, s);
   });
 }

@@ -88,6 +88,41 @@ def test_bf16_shared_equals_private_and_eager(sage_ctx_factory, torch_cuda):
         assert np.array_equal(a, c)
 
 
+TILES = ["ggemm_bf16_16x64", "ggemm_bf16_32x64", "ggemm_bf16_32x128", "ggemm_bf16_64x128",
+         "ggemm_bf16_128x128", "ggemm_bf16_256x128", "ggemm_bf16_128x256", "ggemm2_bf16_256x256",
+         "ggemm2_bf16_256x128", "ggemm2_bf16_128x256", "ggemm4_bf16_256x256", "ggemm3_bf16_256x256",
+         "ggemm3_bf16_256x128"]
+
+
+def test_bf16_every_tile_shape_same_bits(sage_ctx_factory, torch_cuda, monkeypatch):
+    """Every tile shape (forced, autotuner bypassed) walks K in the same order
+    with the same MFMA: all give identical bits, and match the oracle; more
+    than 256 rows in a group exercise several m-tiles of the largest tiles."""
+    from paper_2404_14691_amd import sage as S
+    layers, width = 2, 512
+    batches = [300, 5, 70, 1]
+    w = synth.shared_mlp_bf16_functions(n_fns=2, layers=layers, width=width, share_frac=0.3, seed=9)
+    xs = [synth.bf16_inputs(b, width, 9, i) for i, b in enumerate(batches)]
+    first = None
+    for tile in TILES:
+        monkeypatch.setenv("SAGE_TILE", tile)
+        ctx = sage_ctx_factory()
+        monkeypatch.delenv("SAGE_TILE")
+        fns = [S.fn_register(ctx, S.mlp_desc(S.SAGE_MLP_BF16, layers, width), [S.make_blob(b)]) for b in w.blobs]
+        invs = [S.fn_setup(ctx, fns[i % 2], b) for i, b in enumerate(batches)]
+        ys = [np.zeros((b, width), dtype=np.float32) for b in batches]
+        S.fn_invoke_batch(ctx, invs, xs, ys)
+        S.fn_release_batch(ctx, invs)
+        if first is None:
+            first = ys
+            for i, (x, y) in enumerate(zip(xs, ys)):
+                W = OM.bf16_to_f64(w.blobs[i % 2]).reshape(layers, width, width)
+                assert OM.normwise_error(y, OM.mlp_forward(OM.bf16_to_f64(x), W)) <= BF16_TOL
+        else:
+            for a, b in zip(first, ys):
+                assert np.array_equal(a, b), tile
+
+
 def test_bf16_permutation_weights_exact(sage_ctx_factory, torch_cuda):
     """Permutation-matrix weights: every output is one input value, passed
     through ReLU: the block-table indexing and the MFMA fragment layout must
