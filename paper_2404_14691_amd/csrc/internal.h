@@ -215,6 +215,7 @@ struct Fn {
   uint64_t* d_table = nullptr;        // device: block -> address
   std::vector<uint64_t> h_table;      // host copy of d_table
   uint64_t table_epoch = ~0ull;
+  uint64_t resident_epoch = ~0ull;    // pool eviction epoch at which all classes were resident
   int live = 0;
   Module* mod = nullptr;
   hipEvent_t ready = nullptr;         // data of the function is in place
@@ -322,6 +323,8 @@ struct Ctx {
   size_t next_flight = 0;
   uint64_t next_id = 1;
   std::map<void*, size_t> pinned;            // sage_host_alloc ranges
+  uint64_t* h_stage = nullptr;               // pinned staging for block-table uploads
+  size_t h_stage_cap = 0;
   std::map<std::string, TuneEntry> tune;     // "width:bucket" -> best kernel
   // counters
   uint64_t logical = 0, h2d = 0, reloads = 0, registrations = 0, invocations = 0, mismatches = 0;

@@ -451,7 +451,15 @@ void refresh_table(Ctx& c, Fn& f) {
   std::vector<uint64_t> t(f.n_blocks);
   for (uint32_t b = 0; b < f.n_blocks; b++) t[b] = (uint64_t)c.pool.addr(c.pool.cls[f.cls[b]].slot);
   if (t != f.h_table) {
-    HIPX(hipMemcpyAsync(f.d_table, t.data(), t.size() * 8, hipMemcpyHostToDevice, c.ctl));
+    if (c.h_stage_cap < t.size()) {
+      if (c.h_stage) HIPX(hipHostFree(c.h_stage));
+      c.h_stage = nullptr;
+      c.h_stage_cap = 0;
+      HIPX(hipHostMalloc((void**)&c.h_stage, std::max<size_t>(t.size(), 65536) * 8, hipHostMallocDefault));
+      c.h_stage_cap = std::max<size_t>(t.size(), 65536);
+    }
+    std::memcpy(c.h_stage, t.data(), t.size() * 8);
+    HIPX(hipMemcpyAsync(f.d_table, c.h_stage, t.size() * 8, hipMemcpyHostToDevice, c.ctl));
     HIPX(hipStreamSynchronize(c.ctl));
     f.h_table.swap(t);
   }

@@ -96,8 +96,9 @@ uint64_t setup_internal(Ctx& c, uint64_t id, uint32_t batch) {
   if (c.cfg.share) {
     Pool& P = c.pool;
     std::vector<uint32_t> missing;
-    for (uint32_t cl : f.distinct)
-      if (P.cls[cl].slot == kNone) missing.push_back(cl);
+    if (f.resident_epoch != P.epoch)  // something was evicted since all of f was last resident
+      for (uint32_t cl : f.distinct)
+        if (P.cls[cl].slot == kNone) missing.push_back(cl);
     if (!missing.empty()) {
       // admission: all missing classes need slots; evict only if enough can be freed
       const uint64_t free_slots = P.budget > P.used_ ? P.budget - P.used_ : 0;
@@ -116,6 +117,7 @@ uint64_t setup_internal(Ctx& c, uint64_t id, uint32_t batch) {
       reload_classes(c, f, missing);
     }
     refresh_table(c, f);
+    f.resident_epoch = P.epoch;
     if (f.live == 0)
       for (uint32_t cl : f.distinct)
         if (P.cls[cl].active++ == 0) P.lru_remove(cl);
@@ -259,6 +261,8 @@ sage_status sage_close(sage_ctx* p) {
       c.modules.clear();
       for (auto& kv : c.pinned) (void)hipHostFree(kv.first);
       c.pinned.clear();
+      if (c.h_stage) (void)hipHostFree(c.h_stage);
+      c.h_stage = nullptr;
       c.timer.destroy();
       for (hipStream_t s : c.streams) (void)hipStreamDestroy(s);
       (void)hipStreamDestroy(c.ctl);
