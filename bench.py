@@ -188,6 +188,59 @@ def kernel_bandwidth(S, ctx, torch, nbytes=4 << 30, reps=5):
     return out
 
 
+def host_link(S, torch, wl):
+    """Registration from host memory (the path the paper parallelizes): raw
+    pinned H2D peak, then 4-function registration from pinned and pageable
+    sources, pipelined vs one-after-the-other setup vs no staging ring."""
+    out = {}
+    nbytes = 1 << 30
+    h = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+    d = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    d.copy_(h, non_blocking=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        d.copy_(h, non_blocking=True)
+    torch.cuda.synchronize()
+    out["pinned_h2d_GBps"] = round(3 * nbytes / (time.perf_counter() - t0) / 1e9, 2)
+    del h, d
+    total = sum(b.nbytes for b in wl.host_blobs)
+    desc = S.mlp_desc(S.SAGE_MLP_BF16, wl.layers, wl.width)
+    variants = [("pinned_pipelined", {}, True), ("pageable_pipelined", {}, False),
+                ("pageable_serial_setup", {"serial_setup": 1}, False),
+                ("pageable_no_ring", {"ring_slots": 1, "streams": 1}, False)]
+    for name, over, pinned in variants:
+        cfg = S.sage_config_default()
+        cfg.pool_budget_bytes = 2 << 30
+        for k, v in over.items():
+            setattr(cfg, k, v)
+        ctx = S.sage_open(0, cfg)
+        try:
+            srcs = []
+            for b in wl.host_blobs:
+                if pinned:
+                    a = S.pinned_array(ctx, b.shape, b.dtype)
+                    a[:] = b
+                    srcs.append(a)
+                else:
+                    srcs.append(b)
+            best = None
+            for _ in range(2):
+                t0 = time.perf_counter()
+                fns = [S.fn_register(ctx, desc, [S.make_blob(a)]) for a in srcs]
+                dt = time.perf_counter() - t0
+                for f in fns:
+                    S.fn_unregister(ctx, f)
+                best = dt if best is None else min(best, dt)
+            out[name] = {"register_4fn_ms": round(best * 1e3, 2), "GBps": round(total / best / 1e9, 2)}
+            if pinned:
+                for a in srcs:
+                    S.sage_host_free(ctx, a.ctypes.data)
+        finally:
+            S.sage_close(ctx)
+    return out
+
+
 def cpu_baseline(wl, n_inv=8, seed=0):
     """The oracle on the host: one function's fingerprints + dedup map and
     `n_inv` of its invocations in float64; extrapolated to one step."""
@@ -224,6 +277,9 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-kernels", action="store_true", help="skip the standalone 4 GiB kernel bandwidth runs")
+    ap.add_argument("--no-host-link", action="store_true", help="skip the host-memory registration runs")
+    ap.add_argument("--workload", default="sharing",
+                    help="sharing (default) | batching | stencil | mlp_f32 | serving")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (this path has no "
@@ -233,11 +289,19 @@ def main():
     import torch
     from paper_2404_14691_amd import sage as S
 
+    if args.workload != "sharing":
+        import bench_workloads
+        print(bench_workloads.WORKLOADS[args.workload](S, torch, log), flush=True)
+        return
+
     log("generating workload")
     wl = Workload(torch)
     log(f"workload ready: {len(wl.requests)} requests, {wl.rows} rows")
     cfg = S.sage_config_default()
     cfg.pool_budget_bytes = 8 << 30
+    tune_file = os.path.join(ROOT, "gpurun_out", "tune_cache.txt")
+    if os.path.isdir(os.path.dirname(tune_file)):
+        cfg.tune_cache = tune_file.encode()
     ctx = S.sage_open(0, cfg)
     pcfg = S.sage_config_default()
     pcfg.share = 0
@@ -320,6 +384,10 @@ def main():
         "kernels_standalone_4GiB": standalone,
         "host_ms_per_step": host,
     }
+    if not args.no_host_link:
+        log("host-link registration runs ...")
+        line["host_link_not_headline"] = host_link(S, torch, wl)
+        log(f"host link: {line['host_link_not_headline']}")
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         line["cpu_baseline"] = cpu_baseline(wl)

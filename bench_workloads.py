@@ -1,0 +1,337 @@
+"""Secondary benchmark workloads, run through `bench.py --workload NAME`.
+
+batching : 1 function, 8-layer BF16 MLP width 4096, 256 invocations with
+           lognormal batch sizes (median 8, clipped 1..128) in one group.
+stencil  : 7-point FP32 stencil on 512^3 with a shared 512 MiB coefficient
+           grid, 32 invocations x 20 Jacobi sweeps.
+mlp_f32  : 2-layer FP32 MLP 2048x2048, 16 sequential invocations of 8 rows,
+           weights and inputs in host memory.
+serving  : open-loop Poisson arrivals over 16 BF16 MLP functions with sizes
+           lognormal in [64 MiB, 4 GiB], 20 % block overlap, pool budget
+           below the unique bytes (admission + eviction), rates
+           200/500/1000/2000 requests/s.
+Each prints one JSON line with the same top-level fields as bench.py.
+"""
+from __future__ import annotations
+
+import json
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def _pct(v, q):
+    s = sorted(v)
+    k = max(1, int(np.ceil(q / 100.0 * len(s))))
+    return s[k - 1]
+
+
+def _line(metric, value, unit, steps, warmup, ms, config, dtype, **extra):
+    d = {"metric": metric, "value": round(value, 2), "unit": unit, "n_gpus": 1, "steps": steps, "warmup": warmup,
+         "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+         "dtype": dtype, "data": "synthetic", "config": config}
+    d.update(extra)
+    return json.dumps(d)
+
+
+# ---------------------------------------------------------------- batching
+def batching(S, torch, log, steps=10, warmup=2):
+    from paper_2404_14691_amd import synth
+    W, L = 4096, 8
+    w = synth.shared_mlp_bf16_functions(n_fns=1, layers=L, width=W, share_frac=0.0, seed=3)
+    dev = torch.from_numpy(w.blobs[0].view(np.uint8)).cuda()
+    batches = [int(b) for b in synth.lognormal_batches(256, seed=3)]
+    rows = sum(batches)
+    x = torch.zeros((rows, W), dtype=torch.bfloat16, device="cuda").normal_()
+    y = torch.zeros((rows, W), dtype=torch.float32, device="cuda")
+    offs = np.concatenate([[0], np.cumsum(batches)[:-1]])
+    ins = [(x.data_ptr() + int(o) * W * 2, b * W * 2) for o, b in zip(offs, batches)]
+    outs = [(y.data_ptr() + int(o) * W * 4, b * W * 4) for o, b in zip(offs, batches)]
+    io = S.SAGE_IO_DEVICE_IN | S.SAGE_IO_DEVICE_OUT
+    desc = S.mlp_desc(S.SAGE_MLP_BF16, L, W)
+    blob = [S.make_blob(dev.data_ptr(), dev.numel(), where=S.SAGE_SRC_DEVICE)]
+    torch.cuda.synchronize()
+
+    def shared(ctx):
+        t0 = time.perf_counter()
+        fn = S.fn_register(ctx, desc, blob)
+        reg = (time.perf_counter() - t0) * 1e3
+        setup = []
+        invs = []
+        for b in batches:
+            t0 = time.perf_counter()
+            invs.append(S.fn_setup(ctx, fn, b))
+            setup.append((time.perf_counter() - t0) * 1e3)
+        setup[0] += reg
+        S.fn_invoke_batch(ctx, invs, ins, outs, io)
+        S.fn_release_batch(ctx, invs)
+        S.fn_unregister(ctx, fn)
+        return setup
+
+    def plain(ctx):
+        t0 = time.perf_counter()
+        fn = S.fn_register(ctx, desc, blob)
+        reg = (time.perf_counter() - t0) * 1e3
+        setup = []
+        for i, b in enumerate(batches):
+            t0 = time.perf_counter()
+            inv = S.fn_setup(ctx, fn, b)
+            setup.append((time.perf_counter() - t0) * 1e3 + (reg if i == 0 else 0))
+            S.fn_invoke(ctx, inv, ins[i], outs[i], io)
+            S.fn_release(ctx, inv)
+        S.fn_unregister(ctx, fn)
+        return setup
+
+    cfg = S.sage_config_default()
+    cfg.pool_budget_bytes = 1 << 30
+    ctx = S.sage_open(0, cfg)
+    pcfg = S.sage_config_default()
+    pcfg.share = 0
+    pcfg.pool_budget_bytes = 1 << 20
+    pctx = S.sage_open(0, pcfg)
+    try:
+        for _ in range(warmup):
+            shared(ctx)
+        plain(pctx)
+        S.sage_timing_reset(ctx)
+        S.sage_timing_enable(ctx, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = [shared(ctx) for _ in range(steps)]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        S.sage_timing_enable(ctx, False)
+        g_ms, g_n = S.sage_timing_get(ctx, "ggemm_bf16")
+        t0 = time.perf_counter()
+        pres = [plain(pctx)]
+        torch.cuda.synchronize()
+        pel = time.perf_counter() - t0
+    finally:
+        S.sage_close(ctx)
+        S.sage_close(pctx)
+    su = [v for r in res for v in r]
+    ps = [v for r in pres for v in r]
+    avg = g_ms / max(g_n, 1)
+    ach = 2.0 * rows * W * W / (avg * 1e-3) / 1e12
+    value = 256 * steps / el
+    return _line("setup p50/p99 ms + invocations/sec, shared+batched vs plain, 1 MI355X", value, "invocations/s",
+                 steps, warmup, el / steps * 1e3,
+                 {"workload": "batching: 1 function, 8-layer BF16 MLP width 4096, 256 invocations, batch "
+                              "lognormal(median 8) clipped 1..128, one grouped launch per layer", "rows": rows},
+                 "bf16",
+                 setup_ms={"shared": {"p50": round(_pct(su, 50), 4), "p99": round(_pct(su, 99), 3)},
+                           "plain": {"p50": round(_pct(ps, 50), 4), "p99": round(_pct(ps, 99), 3)}},
+                 plain={"value": round(256 / pel, 2), "ms_per_step": round(pel * 1e3, 2)},
+                 speedup_vs_plain=round(value / (256 / pel), 2),
+                 roofline={"bound": "mfma", "achieved": round(ach, 2), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                           "frac": round(ach / BF16_PEAK_TFLOPS, 4), "traffic": None, "kernel": "ggemm_bf16",
+                           "avg_launch_ms": round(avg, 5)})
+
+
+# ---------------------------------------------------------------- stencil
+def stencil(S, torch, log, steps=2, warmup=1, n=512, n_inv=32, sweeps=20):
+    from paper_2404_14691_amd import synth
+    c = synth.stencil_coefficients(n, seed=0)
+    dc = torch.from_numpy(c).cuda()
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    fields = [torch.randn((n, n, n), generator=g, device="cuda") for _ in range(n_inv)]
+    outs = [torch.empty_like(f) for f in fields]
+    io = S.SAGE_IO_DEVICE_IN | S.SAGE_IO_DEVICE_OUT
+    fb = n * n * n * 4
+    desc = S.stencil_desc(n, n, n, sweeps)
+    blob = [S.make_blob(dc.data_ptr(), dc.numel() * 4, where=S.SAGE_SRC_DEVICE)]
+    ins = [(f.data_ptr(), fb) for f in fields]
+    ous = [(o.data_ptr(), fb) for o in outs]
+    torch.cuda.synchronize()
+
+    def shared(ctx):
+        fn = S.fn_register(ctx, desc, blob)
+        invs = S.fn_setup_batch(ctx, [fn] * n_inv, [1] * n_inv)
+        S.fn_invoke_batch(ctx, invs, ins, ous, io)
+        S.fn_release_batch(ctx, invs)
+        S.fn_unregister(ctx, fn)
+
+    def plain(ctx):
+        fn = S.fn_register(ctx, desc, blob)
+        for i in range(n_inv):
+            inv = S.fn_setup(ctx, fn, 1)
+            S.fn_invoke(ctx, inv, ins[i], ous[i], io)
+            S.fn_release(ctx, inv)
+        S.fn_unregister(ctx, fn)
+
+    cfg = S.sage_config_default()
+    cfg.pool_budget_bytes = 1 << 30
+    ctx = S.sage_open(0, cfg)
+    pcfg = S.sage_config_default()
+    pcfg.share = 0
+    pcfg.pool_budget_bytes = 1 << 20
+    pctx = S.sage_open(0, pcfg)
+    try:
+        for _ in range(warmup):
+            shared(ctx)
+        S.sage_timing_reset(ctx)
+        S.sage_timing_enable(ctx, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            shared(ctx)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        S.sage_timing_enable(ctx, False)
+        k_ms, k_n = S.sage_timing_get(ctx, "stencil7")
+        plain(pctx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plain(pctx)
+        torch.cuda.synchronize()
+        pel = time.perf_counter() - t0
+    finally:
+        S.sage_close(ctx)
+        S.sage_close(pctx)
+    cells = n ** 3
+    avg = k_ms / max(k_n, 1)                      # one sweep launch over all 32 fields
+    alg = n_inv * cells * 8 + cells * 4           # u read + u' written per field, c once
+    gbs = alg / (avg * 1e-3) / 1e9
+    value = n_inv * steps / el
+    return _line("invocations/sec, shared+batched vs plain, 1 MI355X", value, "invocations/s", steps, warmup,
+                 el / steps * 1e3,
+                 {"workload": "stencil: 7-point FP32 Jacobi on 512^3, shared 512 MiB coefficient grid, 32 "
+                              "invocations x 20 sweeps, one launch per sweep for all fields"},
+                 "f32", plain={"value": round(n_inv / pel, 3), "ms_per_step": round(pel * 1e3, 2)},
+                 speedup_vs_plain=round(value / (n_inv / pel), 2),
+                 roofline={"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "stencil7_sweep",
+                           "avg_launch_ms": round(avg, 4), "bytes_per_launch": alg})
+
+
+# ---------------------------------------------------------------- FP32 MLP
+def mlp_f32(S, torch, log, reps=5):
+    from paper_2404_14691_amd import synth
+    wl = synth.mlp_f32_workload()
+    blob = wl.weights.reshape(-1)
+    desc = S.mlp_desc(S.SAGE_MLP_F32, 2, 2048)
+    res = {}
+    for name, share in (("shared", 1), ("plain", 0)):
+        cfg = S.sage_config_default()
+        cfg.share = share
+        cfg.pool_budget_bytes = 256 << 20
+        ctx = S.sage_open(0, cfg)
+        try:
+            times, lat = [], []
+            for r in range(reps + 1):
+                y = np.zeros((8, 2048), dtype=np.float32)
+                t0 = time.perf_counter()
+                fn = S.fn_register(ctx, desc, [S.make_blob(blob)])
+                one = []
+                for x in wl.inputs:
+                    t1 = time.perf_counter()
+                    inv = S.fn_setup(ctx, fn, 8)
+                    S.fn_invoke(ctx, inv, x, y)
+                    S.fn_release(ctx, inv)
+                    one.append((time.perf_counter() - t1) * 1e3)
+                S.fn_unregister(ctx, fn)
+                if r:
+                    times.append(time.perf_counter() - t0)
+                    lat += one
+            res[name] = {"ms_16_invocations": round(min(times) * 1e3, 3), "invocation_ms_p50": round(_pct(lat, 50), 4),
+                         "invocation_ms_p99": round(_pct(lat, 99), 4)}
+        finally:
+            S.sage_close(ctx)
+    value = 16 / (res["shared"]["ms_16_invocations"] * 1e-3)
+    return _line("invocations/sec, shared vs plain, 1 MI355X", value, "invocations/s", reps, 1,
+                 res["shared"]["ms_16_invocations"],
+                 {"workload": "mlp_f32: 2-layer FP32 MLP 2048x2048 (32 MiB weights in host memory), 16 sequential "
+                              "invocations of 8 rows, host inputs/outputs; includes fn_register"},
+                 "f32", detail=res,
+                 speedup_vs_plain=round(res["plain"]["ms_16_invocations"] / res["shared"]["ms_16_invocations"], 2))
+
+
+# ---------------------------------------------------------------- serving
+def serving(S, torch, log, rates=(200, 500, 1000, 2000), duration=3.0, budget_frac=0.5):
+    from paper_2404_14691_amd import synth
+    W = 4096
+    sw = synth.serving_workload(rate=1.0, duration=1.0, seed=0)
+    layers = sw.layers
+    layer_bytes = W * W * 2
+    sizes = [l * layer_bytes for l in layers]
+    # weights generated on the device (seeded) with 20 % of blocks copied from a common pool
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    per = 32768
+    maxb = max(sizes) // 65536
+    pool = (torch.randn((maxb, per), generator=g, device="cuda") / 64.0).to(torch.bfloat16)
+    blobs = []
+    for f, nbytes in enumerate(sizes):
+        nb = nbytes // 65536
+        b = (torch.randn((nb, per), generator=g, device="cuda") / 64.0).to(torch.bfloat16)
+        share = torch.rand(nb, generator=g, device="cuda") < sw.overlap_frac
+        b[share] = pool[:nb][share]
+        blobs.append(b)
+    torch.cuda.synchronize()
+    logical = sum(sizes)
+    maxrows = 64
+    xin = torch.zeros((maxrows, W), dtype=torch.bfloat16, device="cuda").normal_()
+    io = S.SAGE_IO_DEVICE_IN | S.SAGE_IO_DEVICE_OUT
+    cfg = S.sage_config_default()
+    cfg.pool_budget_bytes = 1 << 40
+    ctx = S.sage_open(0, cfg)
+    results = {}
+    try:
+        fns = [S.fn_register(ctx, S.mlp_desc(S.SAGE_MLP_BF16, l, W),
+                             [S.make_blob(b.data_ptr(), b.numel() * 2, where=S.SAGE_SRC_DEVICE)])
+               for l, b in zip(layers, blobs)]
+        unique = S.sage_get_stats(ctx)["unique_bytes"]
+        S.sage_close(ctx)
+        cfg.pool_budget_bytes = int(unique * budget_frac)
+        ctx = S.sage_open(0, cfg)
+        fns = [S.fn_register(ctx, S.mlp_desc(S.SAGE_MLP_BF16, l, W),
+                             [S.make_blob(b.data_ptr(), b.numel() * 2, where=S.SAGE_SRC_DEVICE)])
+               for l, b in zip(layers, blobs)]
+        S.sage_serve_start(ctx)
+        for rate in rates:
+            wl = synth.serving_workload(rate=rate, duration=duration, seed=rate)
+            n = len(wl.arrivals)
+            ys = torch.empty((n, maxrows, W), dtype=torch.float32, device="cuda") if n * maxrows * W * 4 < (8 << 30) \
+                else None
+            if ys is None:
+                raise RuntimeError("serving output buffer too large")
+            torch.cuda.synchronize()
+            S.sage_serve_reset_stats(ctx)
+            ev0 = S.sage_get_stats(ctx)["evictions"]
+            ids = []
+            t_start = time.perf_counter()
+            for i in range(n):
+                while time.perf_counter() - t_start < wl.arrivals[i]:
+                    pass
+                b = int(wl.batch[i])
+                ids.append(S.sage_submit(ctx, fns[int(wl.fn[i])], b, (xin.data_ptr(), b * W * 2),
+                                         (ys[i].data_ptr(), b * W * 4), io))
+            for r in ids:
+                S.sage_wait(ctx, r, 120000)
+            rep = S.sage_serve_stats(ctx)
+            st = S.sage_get_stats(ctx)
+            results[str(rate)] = {"requests": n, "throughput": round(rep["throughput"], 1),
+                                  "setup_ms": {"p50": round(rep["setup_p50_ms"], 3), "p99": round(rep["setup_p99_ms"], 3)},
+                                  "e2e_ms": {"p50": round(rep["e2e_p50_ms"], 3), "p99": round(rep["e2e_p99_ms"], 3)},
+                                  "launches": rep["launches"], "rows": rep["rows"],
+                                  "evictions": st["evictions"] - ev0, "failed": rep["failed"]}
+            log(f"serving {rate}/s: {results[str(rate)]}")
+            del ys
+        S.sage_serve_stop(ctx)
+    finally:
+        S.sage_close(ctx)
+    top = results[str(rates[-1])]
+    return _line("setup/e2e p50/p99 ms + invocations/sec under Poisson load, 1 MI355X", top["throughput"],
+                 "invocations/s", len(rates), 0, 0.0,
+                 {"workload": f"serving: Poisson arrivals over 16 BF16 MLP functions (width 4096, sizes lognormal "
+                              f"64 MiB..4 GiB, {logical / 2**30:.1f} GiB logical, 20% block overlap), batch U[1,64], "
+                              f"{duration:.0f} s per rate, pool budget {budget_frac:.0%} of unique bytes",
+                  "unique_bytes": int(unique), "pool_budget_bytes": int(unique * budget_frac)},
+                 "bf16", rates=results)
+
+
+WORKLOADS = {"batching": batching, "stencil": stencil, "mlp_f32": mlp_f32, "serving": serving}

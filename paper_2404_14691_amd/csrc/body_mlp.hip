@@ -463,6 +463,162 @@ __device__ __forceinline__ void ggemm3(const GemmHdr* __restrict__ hdr, const Ge
   }
 }
 
+// ---------------------------------------------------------------------------
+// As ggemm3, plus register double-buffering of the MFMA fragments: the LDS
+// reads of stage kt + 1 are issued before the MFMAs of stage kt, so LDS
+// latency hides under matrix work.  Stage j's LDS buffer is refilled (stage
+// j + S) only after every wave's reads of stage j completed (lgkmcnt(0)
+// before the barrier that precedes the refill).
+template <int BM, int BN, int WM, int WN, int S>
+__device__ __forceinline__ void ggemm5(const GemmHdr* __restrict__ hdr, const GemmGroup* __restrict__ groups,
+                                       const LayerArgs la, uint8_t* lds) {
+  constexpr int NWN = BN / WN, NWM = BM / WM;
+  constexpr int NW = NWN * NWM, NT = 64 * NW;
+  constexpr int FM = WM / 16, FN = WN / 16;
+  constexpr uint32_t A_STAGE = BM * kRow3, B_STAGE = BN * kRow3, STAGE = A_STAGE + B_STAGE;
+  constexpr int A_INS = BM / 16 / NW, B_INS = BN / 16 / NW;
+  static_assert(A_INS * 16 * NW == BM && B_INS * 16 * NW == BN, "rows split evenly over waves");
+  constexpr int LPS = A_INS + B_INS;
+  constexpr uint32_t SC = 4;
+  typedef __attribute__((address_space(3))) void lds_void;
+  (void)NT;
+
+  const uint32_t t = threadIdx.x, lane = t & 63;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  const uint32_t wm = wave / NWN, wn = wave % NWN;
+  const uint32_t N = la.N, K = la.K;
+  const uint32_t total = hdr->total_tiles, G = hdr->n_groups;
+  const bool out_f32 = la.flags & kOutF32, relu = la.flags & kRelu;
+  const uint32_t KT = K / 32;
+  const uint32_t n_tiles = N / BN;
+  const uint32_t lrow = lane >> 2, lslot = lane & 3;
+
+  const uint32_t xcd = blockIdx.x % kXcds, j = blockIdx.x / kXcds, per_xcd = gridDim.x / kXcds;
+  if (j >= per_xcd) return;
+  const uint32_t r0 = (uint32_t)(((uint64_t)total * xcd) / kXcds);
+  const uint32_t r1 = (uint32_t)(((uint64_t)total * (xcd + 1)) / kXcds);
+
+  for (uint32_t tile = r0 + j; tile < r1; tile += per_xcd) {
+    const GemmGroup gr = groups[find_group(groups, G, tile)];
+    const uint32_t m_tiles = (gr.m + BM - 1) / BM;
+    uint32_t mt, nt;
+    tile_coords(tile - gr.tile_start, m_tiles, n_tiles, SC, &mt, &nt);
+    const uint32_t m0 = mt * BM, n0 = nt * BN;
+    const uint64_t* wtab = reinterpret_cast<const uint64_t*>(gr.wtab);
+
+    const uint8_t* ap[A_INS];
+    const uint8_t* bp[B_INS];
+#pragma unroll
+    for (int q = 0; q < A_INS; q++) {
+      const uint32_t row = (wave * A_INS + q) * 16 + lrow;
+      uint32_t r = m0 + row;
+      r = r < gr.m ? r : gr.m - 1;
+      ap[q] = a_row(la, gr.row0 + r, 2) + (lslot ^ ((row >> 1) & 3)) * 16;
+    }
+#pragma unroll
+    for (int q = 0; q < B_INS; q++) {
+      const uint32_t row = (wave * B_INS + q) * 16 + lrow;
+      const uint64_t off = la.w_off + (uint64_t)(n0 + row) * K * 2;
+      bp[q] = reinterpret_cast<const uint8_t*>(wtab[off >> kBlockShift]) + (off & (kBlock - 1)) +
+              (lslot ^ ((row >> 1) & 3)) * 16;
+    }
+    auto issue = [&](uint32_t kt) __attribute__((always_inline)) {
+      uint8_t* st = lds + (kt % S) * STAGE;
+#pragma unroll
+      for (int q = 0; q < A_INS; q++)
+        __builtin_amdgcn_global_load_lds((const void*)(ap[q] + kt * kRow3),
+                                         (lds_void*)(st + (wave * A_INS + q) * 1024), 16, 0, 0);
+#pragma unroll
+      for (int q = 0; q < B_INS; q++)
+        __builtin_amdgcn_global_load_lds((const void*)(bp[q] + kt * kRow3),
+                                         (lds_void*)(st + A_STAGE + (wave * B_INS + q) * 1024), 16, 0, 0);
+    };
+    const uint32_t chunk = lane >> 4;
+    auto read_frags = [&](uint32_t kt, bf16x8 (&af)[FM], bf16x8 (&bf)[FN]) __attribute__((always_inline)) {
+      const uint8_t* st = lds + (kt % S) * STAGE;
+#pragma unroll
+      for (int i = 0; i < FM; i++)
+        af[i] = *reinterpret_cast<const bf16x8*>(st + swz3(wm * WM + i * 16 + (lane & 15), chunk));
+#pragma unroll
+      for (int jj = 0; jj < FN; jj++)
+        bf[jj] = *reinterpret_cast<const bf16x8*>(st + A_STAGE + swz3(wn * WN + jj * 16 + (lane & 15), chunk));
+    };
+
+    f32x4 acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; i++)
+#pragma unroll
+      for (int jj = 0; jj < FN; jj++) acc[i][jj] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+#pragma unroll
+    for (int s0 = 0; s0 < S; s0++)
+      if ((uint32_t)s0 < KT) issue(s0);
+    {
+      const uint32_t later = (KT - 1) < (uint32_t)(S - 1) ? (KT - 1) : (uint32_t)(S - 1);
+      if (later >= 3) wait_vm<3 * LPS>();
+      else if (later == 2) wait_vm<2 * LPS>();
+      else if (later == 1) wait_vm<LPS>();
+      else wait_vm<0>();
+    }
+    __builtin_amdgcn_s_barrier();
+    bf16x8 fa[FM], fb[FN], ga[FM], gb[FN];
+    read_frags(0, fa, fb);
+    auto mfma_all = [&](const bf16x8 (&a)[FM], const bf16x8 (&b)[FN]) __attribute__((always_inline)) {
+#pragma unroll
+      for (int i = 0; i < FM; i++)
+#pragma unroll
+        for (int jj = 0; jj < FN; jj++)
+          acc[i][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[jj], acc[i][jj], 0, 0, 0);
+    };
+    // two K-steps per trip with the fragment buffers swapped by name, so no
+    // register copies and no control-flow merge sits between reads and MFMAs
+    uint32_t kt = 0;
+    auto step = [&](bf16x8 (&ca)[FM], bf16x8 (&cb)[FN], bf16x8 (&na)[FM], bf16x8 (&nb)[FN])
+        __attribute__((always_inline)) {
+      const uint32_t later = (KT - 2 - kt) < (uint32_t)(S - 2) ? (KT - 2 - kt) : (uint32_t)(S - 2);
+      if (later >= 2) wait_vm<2 * LPS>();
+      else if (later == 1) wait_vm<LPS>();
+      else wait_vm<0>();
+      __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): this wave's reads of stage kt are done
+      __builtin_amdgcn_s_barrier();
+      if (kt + S < KT) issue(kt + S);
+      read_frags(kt + 1, na, nb);
+      mfma_all(ca, cb);
+      kt++;
+    };
+    while (kt + 2 < KT) {
+      step(fa, fb, ga, gb);
+      step(ga, gb, fa, fb);
+    }
+    if (kt + 1 < KT) {
+      step(fa, fb, ga, gb);
+      mfma_all(ga, gb);
+    } else {
+      mfma_all(fa, fb);
+    }
+    __syncthreads();  // the next tile's first loads overwrite stages still being read
+
+#pragma unroll
+    for (int i = 0; i < FM; i++) {
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const uint32_t r = m0 + wm * WM + i * 16 + 4 * (lane >> 4) + q;
+        if (r < gr.m) {
+          uint8_t* crow = c_row(la, gr.row0 + r, out_f32 ? 4 : 2);
+#pragma unroll
+          for (int jj = 0; jj < FN; jj++) {
+            const uint32_t col = n0 + wn * WN + jj * 16 + (lane & 15);
+            float v = acc[i][jj][q];
+            if (relu) v = v > 0.f ? v : 0.f;
+            if (out_f32) reinterpret_cast<float*>(crow)[col] = v;
+            else reinterpret_cast<__bf16*>(crow)[col] = (__bf16)v;
+          }
+        }
+      }
+    }
+  }
+}
+
 }  // namespace
 
 #define SAGE_GGEMM(BM, BN, WM, WN, OCC)                                                               \
@@ -509,6 +665,15 @@ SAGE_GGEMM2W(256, 256, 128, 128)
   }
 SAGE_GGEMM3(256, 256, 128, 64, 4)
 SAGE_GGEMM3(256, 128, 128, 32, 4)
+
+// direct-to-LDS ring + fragment double-buffering
+#define SAGE_GGEMM5(BM, BN, WM, WN, S)                                                                \
+  extern "C" __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN), 1) void ggemm5_bf16_##BM##x##BN(  \
+      const GemmHdr* __restrict__ hdr, const GemmGroup* __restrict__ groups, LayerArgs la) {           \
+    __shared__ __attribute__((aligned(1024))) uint8_t lds[S * (BM + BN) * kRow3];                      \
+    ggemm5<BM, BN, WM, WN, S>(hdr, groups, la, lds);                                                   \
+  }
+SAGE_GGEMM5(256, 128, 128, 32, 4)
 
 // ---------------------------------------------------------------- FP32 MLP
 // Tiles: (group, block of 8 output columns); wave w of the workgroup owns

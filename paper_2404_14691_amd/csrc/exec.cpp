@@ -42,7 +42,7 @@ static const TileShape kShapes[] = {
     {"ggemm_bf16_128x256", 128, 256, 1, 256}, {"ggemm2_bf16_256x256", 256, 256, 1, 512},
     {"ggemm2_bf16_256x128", 256, 128, 1, 512}, {"ggemm2_bf16_128x256", 128, 256, 1, 512},
     {"ggemm4_bf16_256x256", 256, 256, 1, 256}, {"ggemm3_bf16_256x256", 256, 256, 1, 512},
-    {"ggemm3_bf16_256x128", 256, 128, 1, 512},
+    {"ggemm3_bf16_256x128", 256, 128, 1, 512}, {"ggemm5_bf16_256x128", 256, 128, 1, 512},
 };
 
 static const TileShape& shape_of(const std::string& name) {
@@ -169,7 +169,7 @@ int launch_mlp_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, int fl
   std::string kname;
   uint32_t bm = 8, bn = 8, occ = 4, threads = 256;
   if (bf16) {
-    kname = c.force_tile.empty() ? tuned_kernel(c, W, M) : c.force_tile;
+    kname = c.force_tile.empty() ? tuned_kernel(c, W, M, (uint32_t)tabs.size()) : c.force_tile;
     const TileShape& ts = shape_of(kname);
     if (W % ts.bn) fail(SAGE_EINVAL, "tile %s does not divide width %u", kname.c_str(), W);
     bm = ts.bm;
@@ -343,19 +343,19 @@ int launch_stencil_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, in
     sa.ny = d.ny;
     sa.nz = d.nz;
     sa.n_fields = nf;
-    sa.tiles_x = (d.nx + kStencilTX - 1) / kStencilTX;
-    sa.tiles_y = (d.ny + kStencilTY - 1) / kStencilTY;
-    sa.tiles_z = (d.nz + kStencilTZ - 1) / kStencilTZ;
+    sa.tiles_x = (d.nx + kStencil2TX - 1) / kStencil2TX;
+    sa.tiles_y = (d.ny + kStencil2TY - 1) / kStencil2TY;
+    sa.tiles_z = (d.nz + kStencil2TZ - 1) / kStencil2TZ;
     sa.spatial_tiles = sa.tiles_x * sa.tiles_y * sa.tiles_z;
     const uint64_t groups = (uint64_t)((sa.spatial_tiles + 7) / 8) * 8 * nf;
     if (groups > 0x7FFFFFFFull) fail(SAGE_EINVAL, "stencil launch too large");
-    hipFunction_t k = calls[0].inv->fn->mod->get("stencil7_sweep");
+    hipFunction_t k = calls[0].inv->fn->mod->get("stencil7_sweep2");
     const int tok = c.timer.start("stencil7", s, S);
     for (uint32_t sw = 0; sw < S; sw++) {
       sa.src = reinterpret_cast<const uint64_t*>(F.d_meta) + (size_t)sw * 2 * nf;
       sa.dst = sa.src + nf;
       void* params[] = {&sa};
-      HIPX(hipModuleLaunchKernel(k, (uint32_t)groups, 1, 1, 256, 1, 1, 0, s, params, nullptr));
+      HIPX(hipModuleLaunchKernel(k, (uint32_t)groups, 1, 1, 1024, 1, 1, 0, s, params, nullptr));
     }
     c.timer.stop(tok, s);
   }
@@ -396,24 +396,32 @@ void tune_load(Ctx& c) {
   }
 }
 
-std::string tuned_kernel(Ctx& c, uint32_t width, uint32_t rows) {
+// Key: (width, row bucket, group bucket).  The synthetic launch has the
+// bucketed number of groups, each with its own weights and an equal share
+// of the rows, since the group count changes both weight traffic and the
+// padding of each group's last row tile.
+std::string tuned_kernel(Ctx& c, uint32_t width, uint32_t rows, uint32_t groups) {
   const uint32_t bucket = bucket_of(rows);
-  const std::string key = std::to_string(width) + ":" + std::to_string(bucket);
+  uint32_t gb = 1;
+  while (gb < groups && gb < 8) gb <<= 1;
+  while (gb > 1 && bucket / gb < 1) gb >>= 1;
+  const std::string key = std::to_string(width) + ":" + std::to_string(bucket) + ":" + std::to_string(gb);
   auto it = c.tune.find(key);
   if (it != c.tune.end()) return it->second.kernel;
   Module* mod = load_module(c, SAGE_MLP_BF16);
-  // synthetic layer: weights contiguous, block table pointing into them
   const size_t wbytes = (size_t)width * width * 2, nblk = (wbytes + kBlock - 1) / kBlock;
-  uint8_t* w = (uint8_t*)c.cache.get(wbytes);
+  uint8_t* w = (uint8_t*)c.cache.get(wbytes * gb);
   uint8_t* a = (uint8_t*)c.cache.get((size_t)bucket * width * 2);
   uint8_t* o = (uint8_t*)c.cache.get((size_t)bucket * width * 2);
-  uint8_t* meta = (uint8_t*)c.cache.get(4096 + nblk * 8);
-  std::vector<uint64_t> tab(nblk);
-  for (size_t b = 0; b < nblk; b++) tab[b] = (uint64_t)(w + b * kBlock);
+  uint8_t* meta = (uint8_t*)c.cache.get(4096 + gb * nblk * 8);
+  std::vector<uint64_t> tab(gb * nblk);
+  for (uint32_t g = 0; g < gb; g++)
+    for (size_t b = 0; b < nblk; b++) tab[g * nblk + b] = (uint64_t)(w + g * wbytes + b * kBlock);
   hipStream_t s = c.ctl;
-  HIPX(hipMemsetAsync(w, 0, wbytes, s));
-  HIPX(hipMemsetAsync(a, 0, (size_t)bucket * width * 2, s));
-  HIPX(hipMemcpyAsync(meta + 4096, tab.data(), nblk * 8, hipMemcpyHostToDevice, s));
+  // small non-zero values (BF16 0x3C00 = 1/128): data-dependent power stays realistic
+  HIPX(hipMemsetD16Async((hipDeviceptr_t)w, 0x3C00, wbytes * gb / 2, s));
+  HIPX(hipMemsetD16Async((hipDeviceptr_t)a, 0x3C00, (size_t)bucket * width, s));
+  HIPX(hipMemcpyAsync(meta + 4096, tab.data(), tab.size() * 8, hipMemcpyHostToDevice, s));
   HIPX(hipStreamSynchronize(s));
   hipEvent_t e0, e1;
   HIPX(hipEventCreate(&e0));
@@ -422,17 +430,20 @@ std::string tuned_kernel(Ctx& c, uint32_t width, uint32_t rows) {
   double best_ms = 1e30;
   for (const auto& ts : kShapes) {
     if (width % ts.bn) continue;
-    struct {
-      GemmHdr h;
-      GemmGroup g;
-    } m{};
-    m.h.n_groups = 1;
-    m.h.total_tiles = ((bucket + ts.bm - 1) / ts.bm) * (width / ts.bn);
-    m.h.total_rows = bucket;
-    m.g.wtab = (uint64_t)(meta + 4096);
-    m.g.m = bucket;
-    HIPX(hipMemcpyAsync(meta, &m.h, sizeof(GemmHdr), hipMemcpyHostToDevice, s));
-    HIPX(hipMemcpyAsync(meta + 16, &m.g, sizeof(GemmGroup), hipMemcpyHostToDevice, s));
+    GemmHdr h{};
+    std::vector<GemmGroup> gr(gb);
+    uint32_t tiles = 0, row = 0;
+    for (uint32_t g = 0; g < gb; g++) {
+      const uint32_t m = bucket / gb + (g < bucket % gb ? 1 : 0);
+      gr[g] = GemmGroup{(uint64_t)(meta + 4096 + g * nblk * 8), m, row, tiles, 0};
+      tiles += ((m + ts.bm - 1) / ts.bm) * (width / ts.bn);
+      row += m;
+    }
+    h.n_groups = gb;
+    h.total_tiles = tiles;
+    h.total_rows = bucket;
+    HIPX(hipMemcpyAsync(meta, &h, sizeof(GemmHdr), hipMemcpyHostToDevice, s));
+    HIPX(hipMemcpyAsync(meta + 16, gr.data(), gb * sizeof(GemmGroup), hipMemcpyHostToDevice, s));
     HIPX(hipStreamSynchronize(s));
     LayerArgs la{};
     la.a_base = a;

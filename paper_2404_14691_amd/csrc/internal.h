@@ -325,7 +325,7 @@ struct Ctx {
   std::map<void*, size_t> pinned;            // sage_host_alloc ranges
   uint64_t* h_stage = nullptr;               // pinned staging for block-table uploads
   size_t h_stage_cap = 0;
-  std::map<std::string, TuneEntry> tune;     // "width:bucket" -> best kernel
+  std::map<std::string, TuneEntry> tune;     // "width:rows:groups" bucket -> best kernel
   // counters
   uint64_t logical = 0, h2d = 0, reloads = 0, registrations = 0, invocations = 0, mismatches = 0;
   double t_register = 0, t_code = 0, t_fp_wait = 0, t_dedup = 0, t_verify = 0, t_setup = 0, t_invoke = 0;
@@ -370,7 +370,7 @@ int launch_stencil_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, in
 void finish_flight(Ctx& c, int flight);
 void flights_init(Ctx& c);
 void flights_destroy(Ctx& c);
-std::string tuned_kernel(Ctx& c, uint32_t width, uint32_t rows);
+std::string tuned_kernel(Ctx& c, uint32_t width, uint32_t rows, uint32_t groups);
 void tune_load(Ctx& c);
 
 uint64_t setup_internal(Ctx& c, uint64_t fn, uint32_t batch);

@@ -68,8 +68,9 @@ struct StencilArgs {
   uint32_t spatial_tiles;              // tiles_x * tiles_y * tiles_z
 };
 
-constexpr int kStencilTX = 64;  // cells along x per workgroup row
+constexpr int kStencilTX = 64;  // stencil7_sweep: cells along x per workgroup row
 constexpr int kStencilTY = 4;   // rows along y per workgroup
 constexpr int kStencilTZ = 32;  // planes along z each workgroup marches
+constexpr int kStencil2TX = 256, kStencil2TY = 16, kStencil2TZ = 64;  // stencil7_sweep2 tile
 
 }  // namespace sage

@@ -144,7 +144,7 @@ Module* load_module(Ctx& c, int kind) {
     fail(SAGE_EIO, "hipModuleLoad(%s): %s", path.c_str(), hipGetErrorString(e));
   }
   if (key == SAGE_STENCIL7_F32) {
-    m->get("stencil7_sweep");
+    m->get("stencil7_sweep2");
   } else {
     m->get("mlp_f32_layer");
     m->get("ggemm_bf16_128x128");

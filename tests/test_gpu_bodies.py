@@ -91,7 +91,7 @@ def test_bf16_shared_equals_private_and_eager(sage_ctx_factory, torch_cuda):
 TILES = ["ggemm_bf16_16x64", "ggemm_bf16_32x64", "ggemm_bf16_32x128", "ggemm_bf16_64x128",
          "ggemm_bf16_128x128", "ggemm_bf16_256x128", "ggemm_bf16_128x256", "ggemm2_bf16_256x256",
          "ggemm2_bf16_256x128", "ggemm2_bf16_128x256", "ggemm4_bf16_256x256", "ggemm3_bf16_256x256",
-         "ggemm3_bf16_256x128"]
+         "ggemm3_bf16_256x128", "ggemm5_bf16_256x128"]
 
 
 def test_bf16_every_tile_shape_same_bits(sage_ctx_factory, torch_cuda, monkeypatch):
