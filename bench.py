@@ -22,6 +22,7 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -35,6 +36,12 @@ sys.path.insert(0, ROOT)
 METRIC = "setup p50/p99 ms + invocations/sec, shared+batched vs plain, 1 MI355X"
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0
+# HBM traffic of the grouped GEMM comes from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# runs summarised in this file; it is reported only while the GEMM sources
+# and the launch plan are the ones the counters were taken on.
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "ggemm_bf16_sharing_counters.md")
+GEMM_SOURCES = ("paper_2404_14691_amd/csrc/body_mlp.hip", "paper_2404_14691_amd/csrc/exec.cpp",
+                "paper_2404_14691_amd/csrc/layout.h")
 
 
 _T0 = time.time()
@@ -136,6 +143,30 @@ def plain_step(S, ctx, wl):
     for f in fns:
         S.fn_unregister(ctx, f)
     return setup_ms
+
+
+def gemm_sources_digest():
+    h = hashlib.sha256()
+    for f in GEMM_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_record(plan):
+    """The committed counter record for this GEMM source and plan, or None."""
+    try:
+        with open(TRAFFIC_RECORD) as fh:
+            lines = fh.read().splitlines()
+    except OSError:
+        return None
+    digest = gemm_sources_digest()
+    for line in lines:
+        if line.startswith("traffic-record: "):
+            rec = json.loads(line[len("traffic-record: "):])
+            if rec.get("sources") == digest and rec.get("plan") == plan:
+                return rec
+    return None
 
 
 def timed(torch, fn, steps):
@@ -325,6 +356,7 @@ def main():
         setup_shared = [x for r in res for x in r[0]]
         stats = res[-1][1]
         g_ms, g_n = S.sage_timing_get(ctx, "ggemm_bf16")
+        plan = S.sage_last_launch(ctx)
         f_ms, f_n = S.sage_timing_get(ctx, "fp64k")
         b_ms, b_n = S.sage_timing_get(ctx, "blkcopy")
         # ---- plain
@@ -345,6 +377,7 @@ def main():
     flops_launch = 2.0 * wl.rows * wl.width * wl.width
     gemm_avg_ms = g_ms / max(g_n, 1)
     achieved = flops_launch / (gemm_avg_ms * 1e-3) / 1e12
+    traffic = traffic_record(plan)
     fp_bytes = (sum(b.numel() for b in wl.dev_blobs) + 8 * sum(b.numel() for b in wl.dev_blobs) // 65536)
     line = {
         "metric": METRIC,
@@ -373,9 +406,12 @@ def main():
         "pool": {"logical_bytes": stats["logical_bytes"], "unique_bytes": stats["unique_bytes"],
                  "shared_bytes": stats["shared_bytes"], "private_bytes": stats["private_bytes"]},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / BF16_PEAK_TFLOPS, 4), "traffic": None,
-                     "kernel": "ggemm_bf16", "avg_launch_ms": round(gemm_avg_ms, 5),
-                     "flop_per_launch": flops_launch},
+                     "frac": round(achieved / BF16_PEAK_TFLOPS, 4),
+                     "traffic": traffic["hbm_bytes_per_layer"] if traffic else None,
+                     "kernel": "grouped BF16 GEMM layer: " + plan, "avg_launch_ms": round(gemm_avg_ms, 5),
+                     "launch": "one layer (main launch + thin-tile tail launch when split)",
+                     "flop_per_launch": flops_launch,
+                     "traffic_source": os.path.relpath(TRAFFIC_RECORD, ROOT) if traffic else None},
         "kernels": {
             "fp64k": {"avg_ms": round(f_ms / max(f_n, 1), 5), "launches": f_n,
                       "GB/s": round(fp_bytes * args.steps / max(f_ms * 1e-3, 1e-12) / 1e9, 1)},

@@ -337,7 +337,21 @@ __device__ __forceinline__ void wait_vm() {
   __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
 }
 
-template <int BM, int BN, int WM, int WN, int S>
+// s_waitcnt until at most min(later, L) stages of LPS loads each are in flight
+template <int LPS, int L>
+__device__ __forceinline__ void wait_stages(uint32_t later) {
+  if constexpr (L <= 0) {
+    wait_vm<0>();
+  } else {
+    if (later >= (uint32_t)L) wait_vm<L * LPS>();
+    else wait_stages<LPS, L - 1>(later);
+  }
+}
+
+// S-slice ring of 32-wide K slices, consumed KG slices per barrier: a step
+// waits for its KG slices, refills the KG ring positions the previous step
+// read, then multiplies slice by slice (the K order of every other shape).
+template <int BM, int BN, int WM, int WN, int S, int KG = 1>
 __device__ __forceinline__ void ggemm3(const GemmHdr* __restrict__ hdr, const GemmGroup* __restrict__ groups,
                                        const LayerArgs la, uint8_t* lds) {
   constexpr int NWN = BN / WN, NWM = BM / WM;
@@ -409,36 +423,40 @@ __device__ __forceinline__ void ggemm3(const GemmHdr* __restrict__ hdr, const Ge
 #pragma unroll
       for (int jj = 0; jj < FN; jj++) acc[i][jj] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+    static_assert(S >= 2 * KG, "a step refills only positions the previous step read");
 #pragma unroll
-    for (int s0 = 0; s0 < S - 1; s0++)
+    for (int s0 = 0; s0 < S - KG; s0++)
       if ((uint32_t)s0 < KT) issue(s0);
-    for (uint32_t kt = 0; kt < KT; kt++) {
-      // stage kt landed when at most (stages issued after it) x LPS loads remain
-      const uint32_t later = (KT - 1 - kt) < (uint32_t)(S - 2) ? (KT - 1 - kt) : (uint32_t)(S - 2);
-      if (later >= 2) wait_vm<2 * LPS>();
-      else if (later == 1) wait_vm<LPS>();
-      else wait_vm<0>();
-      // plain barrier: the wait above already covers this wave's stage-kt loads
+    for (uint32_t kt0 = 0; kt0 < KT; kt0 += KG) {
+      // slices issued after this step's last one: min(S - 2 KG, KT - kt0 - KG)
+      const uint32_t later = (KT - kt0 - KG) < (uint32_t)(S - 2 * KG) ? (KT - kt0 - KG) : (uint32_t)(S - 2 * KG);
+      wait_stages<LPS, S - 2 * KG>(later);
+      // plain barrier: the wait above already covers this wave's loads
       __builtin_amdgcn_s_barrier();
-      if (kt + S - 1 < KT) issue(kt + S - 1);
-      const uint8_t* st = lds + (kt % S) * STAGE;
-      const uint32_t chunk = lane >> 4;
-      bf16x8 af[FM], bfr[FN];
 #pragma unroll
-      for (int i = 0; i < FM; i++) {
-        const uint32_t r = wm * WM + i * 16 + (lane & 15);
-        af[i] = *reinterpret_cast<const bf16x8*>(st + swz3(r, chunk));
+      for (int g = 0; g < KG; g++)
+        if (kt0 + S - KG + g < KT) issue(kt0 + S - KG + g);
+#pragma unroll
+      for (int g = 0; g < KG; g++) {
+        const uint8_t* st = lds + ((kt0 + g) % S) * STAGE;
+        const uint32_t chunk = lane >> 4;
+        bf16x8 af[FM], bfr[FN];
+#pragma unroll
+        for (int i = 0; i < FM; i++) {
+          const uint32_t r = wm * WM + i * 16 + (lane & 15);
+          af[i] = *reinterpret_cast<const bf16x8*>(st + swz3(r, chunk));
+        }
+#pragma unroll
+        for (int jj = 0; jj < FN; jj++) {
+          const uint32_t r = wn * WN + jj * 16 + (lane & 15);
+          bfr[jj] = *reinterpret_cast<const bf16x8*>(st + A_STAGE + swz3(r, chunk));
+        }
+#pragma unroll
+        for (int i = 0; i < FM; i++)
+#pragma unroll
+          for (int jj = 0; jj < FN; jj++)
+            acc[i][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[jj], acc[i][jj], 0, 0, 0);
       }
-#pragma unroll
-      for (int jj = 0; jj < FN; jj++) {
-        const uint32_t r = wn * WN + jj * 16 + (lane & 15);
-        bfr[jj] = *reinterpret_cast<const bf16x8*>(st + A_STAGE + swz3(r, chunk));
-      }
-#pragma unroll
-      for (int i = 0; i < FM; i++)
-#pragma unroll
-        for (int jj = 0; jj < FN; jj++)
-          acc[i][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[jj], acc[i][jj], 0, 0, 0);
     }
     __syncthreads();  // the next tile's first loads overwrite stages still being read
 
@@ -555,10 +573,7 @@ __device__ __forceinline__ void ggemm5(const GemmHdr* __restrict__ hdr, const Ge
       if ((uint32_t)s0 < KT) issue(s0);
     {
       const uint32_t later = (KT - 1) < (uint32_t)(S - 1) ? (KT - 1) : (uint32_t)(S - 1);
-      if (later >= 3) wait_vm<3 * LPS>();
-      else if (later == 2) wait_vm<2 * LPS>();
-      else if (later == 1) wait_vm<LPS>();
-      else wait_vm<0>();
+      wait_stages<LPS, S - 1>(later);
     }
     __builtin_amdgcn_s_barrier();
     bf16x8 fa[FM], fb[FN], ga[FM], gb[FN];
@@ -576,9 +591,7 @@ __device__ __forceinline__ void ggemm5(const GemmHdr* __restrict__ hdr, const Ge
     auto step = [&](bf16x8 (&ca)[FM], bf16x8 (&cb)[FN], bf16x8 (&na)[FM], bf16x8 (&nb)[FN])
         __attribute__((always_inline)) {
       const uint32_t later = (KT - 2 - kt) < (uint32_t)(S - 2) ? (KT - 2 - kt) : (uint32_t)(S - 2);
-      if (later >= 2) wait_vm<2 * LPS>();
-      else if (later == 1) wait_vm<LPS>();
-      else wait_vm<0>();
+      wait_stages<LPS, S - 2>(later);
       __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): this wave's reads of stage kt are done
       __builtin_amdgcn_s_barrier();
       if (kt + S < KT) issue(kt + S);
@@ -586,17 +599,157 @@ __device__ __forceinline__ void ggemm5(const GemmHdr* __restrict__ hdr, const Ge
       mfma_all(ca, cb);
       kt++;
     };
+    // KT is even and >= 2: K is a multiple of BN (>= 128), checked by the host
     while (kt + 2 < KT) {
       step(fa, fb, ga, gb);
       step(ga, gb, fa, fb);
     }
-    if (kt + 1 < KT) {
-      step(fa, fb, ga, gb);
-      mfma_all(ga, gb);
-    } else {
-      mfma_all(fa, fb);
-    }
+    step(fa, fb, ga, gb);
+    mfma_all(ga, gb);
     __syncthreads();  // the next tile's first loads overwrite stages still being read
+
+#pragma unroll
+    for (int i = 0; i < FM; i++) {
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const uint32_t r = m0 + wm * WM + i * 16 + 4 * (lane >> 4) + q;
+        if (r < gr.m) {
+          uint8_t* crow = c_row(la, gr.row0 + r, out_f32 ? 4 : 2);
+#pragma unroll
+          for (int jj = 0; jj < FN; jj++) {
+            const uint32_t col = n0 + wn * WN + jj * 16 + (lane & 15);
+            float v = acc[i][jj][q];
+            if (relu) v = v > 0.f ? v : 0.f;
+            if (out_f32) reinterpret_cast<float*>(crow)[col] = v;
+            else reinterpret_cast<__bf16*>(crow)[col] = (__bf16)v;
+          }
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Ping-pong schedule over the ggemm3 ring: eight waves in two groups of four
+// (waves w and w + 4 share a SIMD).  Every wave alternates a memory phase
+// (LDS reads of one K-slice's fragments, global loads of a later slice) and
+// a matrix phase (that slice's MFMAs), each ended by a workgroup barrier;
+// the second group starts one barrier late, so while one wave of a SIMD
+// multiplies, its partner fetches.  Ring safety: a slice's buffer is
+// refilled S - 1 slices later, after both groups' reads of it completed
+// (lgkmcnt(0) before each phase's barrier); a slice is read only after
+// every wave waited for its own loads of it before an earlier barrier.
+__device__ __forceinline__ void phase_sync() {
+  __builtin_amdgcn_sched_barrier(0);
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int BM, int BN, int WM, int WN, int S>
+__device__ __forceinline__ void ggemm6(const GemmHdr* __restrict__ hdr, const GemmGroup* __restrict__ groups,
+                                       const LayerArgs la, uint8_t* lds) {
+  constexpr int NWN = BN / WN, NWM = BM / WM;
+  constexpr int NW = NWN * NWM;
+  static_assert(NW == 8, "two groups of four waves");
+  constexpr int FM = WM / 16, FN = WN / 16;
+  constexpr uint32_t A_STAGE = BM * kRow3, B_STAGE = BN * kRow3, STAGE = A_STAGE + B_STAGE;
+  constexpr int A_INS = BM / 16 / NW, B_INS = BN / 16 / NW;
+  static_assert(A_INS * 16 * NW == BM && B_INS * 16 * NW == BN, "rows split evenly over waves");
+  constexpr int LPS = A_INS + B_INS;
+  constexpr uint32_t SC = 4;
+  typedef __attribute__((address_space(3))) void lds_void;
+
+  const uint32_t t = threadIdx.x, lane = t & 63;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  const uint32_t wm = wave / NWN, wn = wave % NWN;
+  const bool lag = wave >= 4;
+  const uint32_t N = la.N, K = la.K;
+  const uint32_t total = hdr->total_tiles, G = hdr->n_groups;
+  const bool out_f32 = la.flags & kOutF32, relu = la.flags & kRelu;
+  const uint32_t KT = K / 32;
+  const uint32_t n_tiles = N / BN;
+  const uint32_t lrow = lane >> 2, lslot = lane & 3;
+
+  const uint32_t xcd = blockIdx.x % kXcds, j = blockIdx.x / kXcds, per_xcd = gridDim.x / kXcds;
+  if (j >= per_xcd) return;
+  const uint32_t r0 = (uint32_t)(((uint64_t)total * xcd) / kXcds);
+  const uint32_t r1 = (uint32_t)(((uint64_t)total * (xcd + 1)) / kXcds);
+
+  for (uint32_t tile = r0 + j; tile < r1; tile += per_xcd) {
+    const GemmGroup gr = groups[find_group(groups, G, tile)];
+    const uint32_t m_tiles = (gr.m + BM - 1) / BM;
+    uint32_t mt, nt;
+    tile_coords(tile - gr.tile_start, m_tiles, n_tiles, SC, &mt, &nt);
+    const uint32_t m0 = mt * BM, n0 = nt * BN;
+    const uint64_t* wtab = reinterpret_cast<const uint64_t*>(gr.wtab);
+
+    const uint8_t* ap[A_INS];
+    const uint8_t* bp[B_INS];
+#pragma unroll
+    for (int q = 0; q < A_INS; q++) {
+      const uint32_t row = (wave * A_INS + q) * 16 + lrow;
+      uint32_t r = m0 + row;
+      r = r < gr.m ? r : gr.m - 1;
+      ap[q] = a_row(la, gr.row0 + r, 2) + (lslot ^ ((row >> 1) & 3)) * 16;
+    }
+#pragma unroll
+    for (int q = 0; q < B_INS; q++) {
+      const uint32_t row = (wave * B_INS + q) * 16 + lrow;
+      const uint64_t off = la.w_off + (uint64_t)(n0 + row) * K * 2;
+      bp[q] = reinterpret_cast<const uint8_t*>(wtab[off >> kBlockShift]) + (off & (kBlock - 1)) +
+              (lslot ^ ((row >> 1) & 3)) * 16;
+    }
+    auto issue = [&](uint32_t kt) __attribute__((always_inline)) {
+      uint8_t* st = lds + (kt % S) * STAGE;
+#pragma unroll
+      for (int q = 0; q < A_INS; q++)
+        __builtin_amdgcn_global_load_lds((const void*)(ap[q] + kt * kRow3),
+                                         (lds_void*)(st + (wave * A_INS + q) * 1024), 16, 0, 0);
+#pragma unroll
+      for (int q = 0; q < B_INS; q++)
+        __builtin_amdgcn_global_load_lds((const void*)(bp[q] + kt * kRow3),
+                                         (lds_void*)(st + A_STAGE + (wave * B_INS + q) * 1024), 16, 0, 0);
+    };
+
+    f32x4 acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; i++)
+#pragma unroll
+      for (int jj = 0; jj < FN; jj++) acc[i][jj] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+#pragma unroll
+    for (int s0 = 0; s0 < S - 1; s0++)
+      if ((uint32_t)s0 < KT) issue(s0);
+    wait_stages<LPS, S - 2>((KT - 1) < (uint32_t)(S - 2) ? (KT - 1) : (uint32_t)(S - 2));
+    phase_sync();  // slice 0 is in LDS
+    if (lag) phase_sync();
+    const uint32_t chunk = lane >> 4;
+    for (uint32_t kt = 0; kt < KT; kt++) {
+      // memory phase
+      const uint8_t* st = lds + (kt % S) * STAGE;
+      bf16x8 af[FM], bfr[FN];
+#pragma unroll
+      for (int i = 0; i < FM; i++)
+        af[i] = *reinterpret_cast<const bf16x8*>(st + swz3(wm * WM + i * 16 + (lane & 15), chunk));
+#pragma unroll
+      for (int jj = 0; jj < FN; jj++)
+        bfr[jj] = *reinterpret_cast<const bf16x8*>(st + A_STAGE + swz3(wn * WN + jj * 16 + (lane & 15), chunk));
+      if (kt + S - 1 < KT) issue(kt + S - 1);
+      if (kt + 1 < KT) {
+        const uint32_t later = (KT - 2 - kt) < (uint32_t)(S - 2) ? (KT - 2 - kt) : (uint32_t)(S - 2);
+        wait_stages<LPS, S - 2>(later);  // this wave's loads of slice kt + 1 landed
+      }
+      __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): fragments in registers, slice kt free
+      phase_sync();
+      // matrix phase
+#pragma unroll
+      for (int i = 0; i < FM; i++)
+#pragma unroll
+        for (int jj = 0; jj < FN; jj++)
+          acc[i][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[jj], acc[i][jj], 0, 0, 0);
+      phase_sync();
+    }
+    if (!lag) phase_sync();  // both groups leave the tile after the same number of barriers
 
 #pragma unroll
     for (int i = 0; i < FM; i++) {
@@ -657,14 +810,54 @@ SAGE_GGEMM2(128, 256, 64, 64)
 SAGE_GGEMM2W(256, 256, 128, 128)
 
 // direct-to-LDS, S-stage ring
-#define SAGE_GGEMM3(BM, BN, WM, WN, S)                                                                \
-  extern "C" __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN), 1) void ggemm3_bf16_##BM##x##BN(  \
+#define SAGE_GGEMM3G(NAME, BM, BN, WM, WN, S, G)                                                      \
+  extern "C" __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN), 1) void NAME(                    \
       const GemmHdr* __restrict__ hdr, const GemmGroup* __restrict__ groups, LayerArgs la) {           \
     __shared__ __attribute__((aligned(1024))) uint8_t lds[S * (BM + BN) * kRow3];                      \
-    ggemm3<BM, BN, WM, WN, S>(hdr, groups, la, lds);                                                   \
+    ggemm3<BM, BN, WM, WN, S, G>(hdr, groups, la, lds);                                                \
   }
-SAGE_GGEMM3(256, 256, 128, 64, 4)
-SAGE_GGEMM3(256, 128, 128, 32, 4)
+#define SAGE_GGEMM3(NAME, BM, BN, WM, WN, S) SAGE_GGEMM3G(NAME, BM, BN, WM, WN, S, 1)
+SAGE_GGEMM3(ggemm3_bf16_256x256, 256, 256, 128, 64, 4)
+SAGE_GGEMM3(ggemm3_bf16_256x128, 256, 128, 128, 32, 4)
+SAGE_GGEMM3(ggemm3s5_bf16_256x256, 256, 256, 128, 64, 5)      // five stages: all 160 KiB of LDS
+SAGE_GGEMM3(ggemm3w16_bf16_256x256, 256, 256, 64, 64, 4)      // 16 waves of 64 x 64
+SAGE_GGEMM3(ggemm3w16s5_bf16_256x256, 256, 256, 64, 64, 5)
+// thin tiles with an eight-stage ring: few rows (small batches, and the
+// ragged last row tiles split off a large-tile launch) are bound by the
+// latency of the K walk, which the deep ring hides
+SAGE_GGEMM3(ggemm3_bf16_16x64, 16, 64, 16, 64, 8)
+SAGE_GGEMM3(ggemm3_bf16_32x64, 32, 64, 16, 64, 8)
+SAGE_GGEMM3(ggemm3_bf16_64x64, 64, 64, 32, 32, 8)
+SAGE_GGEMM3(ggemm3_bf16_128x64, 128, 64, 32, 64, 8)
+// sixteen-slice rings consumed four slices per barrier (K a multiple of 128)
+SAGE_GGEMM3G(ggemm3g4_bf16_16x64, 16, 64, 16, 64, 16, 4)
+SAGE_GGEMM3G(ggemm3g4_bf16_32x64, 32, 64, 16, 64, 16, 4)
+SAGE_GGEMM3G(ggemm3g4_bf16_64x64, 64, 64, 32, 32, 16, 4)
+SAGE_GGEMM3G(ggemm3g4_bf16_128x64, 128, 64, 32, 64, 12, 4)
+SAGE_GGEMM3G(ggemm3g2_bf16_256x256, 256, 256, 128, 64, 4, 2)
+// narrow thin tiles: a few rows still spread W over 128..256 workgroups
+// (16 x 16 with its register use capped at two waves per SIMD)
+#define SAGE_GGEMM3T(NAME, BM, BN, WM, WN, S, G, WPE)                                                 \
+  extern "C" __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN))                                  \
+      __attribute__((amdgpu_waves_per_eu(WPE))) void NAME(                                             \
+      const GemmHdr* __restrict__ hdr, const GemmGroup* __restrict__ groups, LayerArgs la) {           \
+    __shared__ __attribute__((aligned(1024))) uint8_t lds[S * (BM + BN) * kRow3];                      \
+    ggemm3<BM, BN, WM, WN, S, G>(hdr, groups, la, lds);                                                \
+  }
+SAGE_GGEMM3T(ggemm3t_bf16_16x16, 16, 16, 16, 16, 16, 4, 2)
+SAGE_GGEMM3G(ggemm3t_bf16_16x32, 16, 32, 16, 32, 16, 4)
+SAGE_GGEMM3G(ggemm3t_bf16_32x32, 32, 32, 16, 32, 16, 4)
+
+// ping-pong over the direct-to-LDS ring
+#define SAGE_GGEMM6(NAME, BM, BN, WM, WN, S)                                                          \
+  extern "C" __global__ __launch_bounds__(512, 1) void NAME(                                           \
+      const GemmHdr* __restrict__ hdr, const GemmGroup* __restrict__ groups, LayerArgs la) {           \
+    __shared__ __attribute__((aligned(1024))) uint8_t lds[S * (BM + BN) * kRow3];                      \
+    ggemm6<BM, BN, WM, WN, S>(hdr, groups, la, lds);                                                   \
+  }
+SAGE_GGEMM6(ggemm6_bf16_256x256, 256, 256, 128, 64, 4)
+SAGE_GGEMM6(ggemm6s5_bf16_256x256, 256, 256, 128, 64, 5)
+SAGE_GGEMM6(ggemm6_bf16_256x128, 256, 128, 64, 64, 4)
 
 // direct-to-LDS ring + fragment double-buffering
 #define SAGE_GGEMM5(BM, BN, WM, WN, S)                                                                \
@@ -674,6 +867,7 @@ SAGE_GGEMM3(256, 128, 128, 32, 4)
     ggemm5<BM, BN, WM, WN, S>(hdr, groups, la, lds);                                                   \
   }
 SAGE_GGEMM5(256, 128, 128, 32, 4)
+SAGE_GGEMM5(256, 256, 128, 128, 4)
 
 // ---------------------------------------------------------------- FP32 MLP
 // Tiles: (group, block of 8 output columns); wave w of the workgroup owns

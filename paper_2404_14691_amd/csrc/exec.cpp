@@ -32,18 +32,31 @@ size_t out_bytes_for(const sage_fn_desc& d, uint32_t batch) {
 struct TileShape {
   const char* name;
   uint32_t bm, bn, occupancy, threads;
+  bool ranged;     // tiles dealt to XCDs in contiguous ranges (grid a multiple of 8)
+  uint32_t kalign = 64;  // K must be a multiple of this
 };
-// ggemm2_* deal contiguous tile ranges to the 8 XCDs: their grid must be a
-// multiple of 8 (it is #CUs x occupancy).
 static const TileShape kShapes[] = {
-    {"ggemm_bf16_16x64", 16, 64, 2, 256},     {"ggemm_bf16_32x64", 32, 64, 2, 256},
-    {"ggemm_bf16_32x128", 32, 128, 2, 256},   {"ggemm_bf16_64x128", 64, 128, 2, 256},
-    {"ggemm_bf16_128x128", 128, 128, 2, 256}, {"ggemm_bf16_256x128", 256, 128, 1, 256},
-    {"ggemm_bf16_128x256", 128, 256, 1, 256}, {"ggemm2_bf16_256x256", 256, 256, 1, 512},
-    {"ggemm2_bf16_256x128", 256, 128, 1, 512}, {"ggemm2_bf16_128x256", 128, 256, 1, 512},
-    {"ggemm4_bf16_256x256", 256, 256, 1, 256}, {"ggemm3_bf16_256x256", 256, 256, 1, 512},
-    {"ggemm3_bf16_256x128", 256, 128, 1, 512}, {"ggemm5_bf16_256x128", 256, 128, 1, 512},
+    {"ggemm_bf16_16x64", 16, 64, 2, 256, false},      {"ggemm_bf16_32x64", 32, 64, 2, 256, false},
+    {"ggemm_bf16_32x128", 32, 128, 2, 256, false},    {"ggemm_bf16_64x128", 64, 128, 2, 256, false},
+    {"ggemm_bf16_128x128", 128, 128, 2, 256, false},  {"ggemm_bf16_256x128", 256, 128, 1, 256, false},
+    {"ggemm_bf16_128x256", 128, 256, 1, 256, false},  {"ggemm2_bf16_256x256", 256, 256, 1, 512, true},
+    {"ggemm2_bf16_256x128", 256, 128, 1, 512, true},  {"ggemm2_bf16_128x256", 128, 256, 1, 512, true},
+    {"ggemm4_bf16_256x256", 256, 256, 1, 256, true},  {"ggemm3_bf16_256x256", 256, 256, 1, 512, true},
+    {"ggemm3_bf16_256x128", 256, 128, 1, 512, true},  {"ggemm5_bf16_256x128", 256, 128, 1, 512, true},
+    {"ggemm5_bf16_256x256", 256, 256, 1, 256, true},  {"ggemm3s5_bf16_256x256", 256, 256, 1, 512, true},
+    {"ggemm3w16_bf16_256x256", 256, 256, 1, 1024, true}, {"ggemm3w16s5_bf16_256x256", 256, 256, 1, 1024, true},
+    {"ggemm3_bf16_16x64", 16, 64, 4, 64, true},       {"ggemm3_bf16_32x64", 32, 64, 3, 128, true},
+    {"ggemm3_bf16_64x64", 64, 64, 2, 256, true},      {"ggemm3_bf16_128x64", 128, 64, 1, 256, true},
+    {"ggemm6_bf16_256x256", 256, 256, 1, 512, true},  {"ggemm6s5_bf16_256x256", 256, 256, 1, 512, true},
+    {"ggemm6_bf16_256x128", 256, 128, 1, 512, true},
+    {"ggemm3g4_bf16_16x64", 16, 64, 2, 64, true, 128},  {"ggemm3g4_bf16_32x64", 32, 64, 1, 128, true, 128},
+    {"ggemm3g4_bf16_64x64", 64, 64, 1, 256, true, 128}, {"ggemm3g4_bf16_128x64", 128, 64, 1, 256, true, 128},
+    {"ggemm3g2_bf16_256x256", 256, 256, 1, 512, true},
+    {"ggemm3t_bf16_16x16", 16, 16, 4, 64, true, 128},   {"ggemm3t_bf16_16x32", 16, 32, 3, 64, true, 128},
+    {"ggemm3t_bf16_32x32", 32, 32, 2, 128, true, 128},
 };
+
+static bool fits(const TileShape& ts, uint32_t W) { return W % ts.bn == 0 && W % ts.kalign == 0; }
 
 static const TileShape& shape_of(const std::string& name) {
   for (const auto& s : kShapes)
@@ -52,9 +65,21 @@ static const TileShape& shape_of(const std::string& name) {
 }
 
 // ------------------------------------------------------------------ flights
+// meta buffer: [main header | main groups][tail header | tail groups][input row
+// table][output row table]
 constexpr uint32_t kMaxGroups = 256;
 constexpr size_t kMetaGroupsOff = 16;
-constexpr size_t kMetaTabOff = kMetaGroupsOff + kMaxGroups * sizeof(GemmGroup);
+constexpr size_t kMetaTailOff = kMetaGroupsOff + kMaxGroups * sizeof(GemmGroup);
+constexpr size_t kMetaTabOff = 2 * kMetaTailOff;
+constexpr uint32_t kXcdCount = 8;
+
+struct MlpPlan {
+  const TileShape* main = nullptr;
+  const TileShape* tail = nullptr;   // thin shape of the split-off ragged row tiles
+  std::vector<uint8_t> split;        // per group: its ragged last row tile runs in the tail launch
+};
+uint32_t shape_grid(const Ctx& c, const TileShape& ts);
+MlpPlan plan_mlp(Ctx& c, uint32_t W, const std::vector<uint32_t>& m);
 
 void flights_init(Ctx& c) {
   c.flights.resize(std::max<uint32_t>(1, c.cfg.inflight_groups));
@@ -143,6 +168,11 @@ static void launch_kernel(hipFunction_t k, uint32_t grid, uint32_t threads, hipS
 // launch covers all groups with one tile list.  Layer 0 reads the inputs
 // through a row table, the last layer writes the outputs through another;
 // hidden layers ping-pong in the flight's workspace.
+//
+// A BF16 layer may run as two launches: the main tile shape over every
+// group's full row tiles, and a thin tile shape over the ragged last row
+// tiles of some groups, when that removes a nearly empty last wave of large
+// tiles (see plan_mlp).  Both cover disjoint outputs of the same row space.
 int launch_mlp_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, int flight) {
   const sage_fn_desc& d = calls[0].inv->fn->d;
   const uint32_t W = d.width, L = d.layers;
@@ -164,21 +194,13 @@ int launch_mlp_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, int fl
   }
   if (tabs.size() > kMaxGroups) fail(SAGE_EINVAL, "more than %u weight tables in one launch", kMaxGroups);
   uint32_t M = 0;
-  for (const Call& cl : calls) M += cl.inv->batch;
+  std::vector<uint32_t> gm(tabs.size(), 0);
+  for (size_t g = 0; g < tabs.size(); g++)
+    for (size_t i : members[g]) gm[g] += calls[i].inv->batch;
+  for (uint32_t m : gm) M += m;
 
-  std::string kname;
-  uint32_t bm = 8, bn = 8, occ = 4, threads = 256;
-  if (bf16) {
-    kname = c.force_tile.empty() ? tuned_kernel(c, W, M, (uint32_t)tabs.size()) : c.force_tile;
-    const TileShape& ts = shape_of(kname);
-    if (W % ts.bn) fail(SAGE_EINVAL, "tile %s does not divide width %u", kname.c_str(), W);
-    bm = ts.bm;
-    bn = ts.bn;
-    occ = ts.occupancy;
-    threads = ts.threads;
-  } else {
-    kname = "mlp_f32_layer";
-  }
+  MlpPlan plan;
+  if (bf16) plan = plan_mlp(c, W, gm);
 
   const int fi = take_flight(c, flight);
   Flight& F = c.flights[fi];
@@ -194,16 +216,14 @@ int launch_mlp_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, int fl
 
   GemmHdr* hdr = reinterpret_cast<GemmHdr*>(F.h_meta);
   GemmGroup* grp = reinterpret_cast<GemmGroup*>(F.h_meta + kMetaGroupsOff);
+  GemmHdr* thdr = reinterpret_cast<GemmHdr*>(F.h_meta + kMetaTailOff);
+  GemmGroup* tgrp = reinterpret_cast<GemmGroup*>(F.h_meta + kMetaTailOff + kMetaGroupsOff);
   uint64_t* in_tab = reinterpret_cast<uint64_t*>(F.h_meta + kMetaTabOff);
   uint64_t* out_tab = in_tab + rows_cap;
-  uint32_t row = 0, tiles = 0;
+  uint32_t row = 0, tiles = 0, ttiles = 0, ng = 0, nt = 0;
   F.deliver.clear();
   for (size_t g = 0; g < tabs.size(); g++) {
-    GemmGroup& G = grp[g];
-    G.wtab = (uint64_t)tabs[g];
-    G.row0 = row;
-    G.tile_start = tiles;
-    G.pad = 0;
+    const uint32_t row0 = row;
     for (size_t i : members[g]) {
       const Call& cl = calls[i];
       const uint32_t b = cl.inv->batch;
@@ -218,28 +238,51 @@ int launch_mlp_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, int fl
       if (host_out) F.deliver.push_back({cl.out, {(size_t)row * W * 4, (size_t)b * W * 4}});
       row += b;
     }
-    G.m = row - G.row0;
-    tiles += bf16 ? ((G.m + bm - 1) / bm) * (W / bn) : W / 8;
+    const uint32_t m = gm[g];
+    if (!bf16) {
+      grp[ng++] = GemmGroup{(uint64_t)tabs[g], m, row0, tiles, 0};
+      tiles += W / 8;
+      continue;
+    }
+    const uint32_t part = plan.tail && plan.split[g] ? m % plan.main->bm : 0;
+    if (m - part) {
+      grp[ng++] = GemmGroup{(uint64_t)tabs[g], m - part, row0, tiles, 0};
+      tiles += ((m - part + plan.main->bm - 1) / plan.main->bm) * (W / plan.main->bn);
+    }
+    if (part) {
+      tgrp[nt++] = GemmGroup{(uint64_t)tabs[g], part, row0 + (m - part), ttiles, 0};
+      ttiles += ((part + plan.tail->bm - 1) / plan.tail->bm) * (W / plan.tail->bn);
+    }
   }
-  hdr->n_groups = (uint32_t)tabs.size();
-  hdr->total_tiles = tiles;
-  hdr->total_rows = M;
-  hdr->pad = 0;
+  *hdr = GemmHdr{ng, tiles, M, 0};
+  *thdr = GemmHdr{nt, ttiles, M, 0};
+  const bool split = nt > 0;
+  const TileShape* ms = bf16 ? plan.main : nullptr;
+  const std::string kname = bf16 ? ms->name : "mlp_f32_layer";
+  c.last_launch = kname + ":" + std::to_string(tiles);
+  if (split) c.last_launch += std::string("+") + plan.tail->name + ":" + std::to_string(ttiles);
 
   hipStream_t s = F.s;
   // readiness gate: the body waits until every function's data is in place
   for (const Call& cl : calls) HIPX(hipStreamWaitEvent(s, cl.inv->fn->ready, 0));
-  HIPX(hipMemcpyAsync(F.d_meta, F.h_meta, kMetaGroupsOff + tabs.size() * sizeof(GemmGroup), hipMemcpyHostToDevice, s));
+  HIPX(hipMemcpyAsync(F.d_meta, F.h_meta, kMetaGroupsOff + ng * sizeof(GemmGroup), hipMemcpyHostToDevice, s));
+  if (split)
+    HIPX(hipMemcpyAsync(F.d_meta + kMetaTailOff, F.h_meta + kMetaTailOff, kMetaGroupsOff + nt * sizeof(GemmGroup),
+                        hipMemcpyHostToDevice, s));
   HIPX(hipMemcpyAsync(F.d_meta + kMetaTabOff, in_tab, (size_t)M * 8, hipMemcpyHostToDevice, s));
   HIPX(hipMemcpyAsync(F.d_meta + kMetaTabOff + rows_cap * 8, out_tab, (size_t)M * 8, hipMemcpyHostToDevice, s));
   if (host_in) HIPX(hipMemcpyAsync(F.d_in, F.h_in, (size_t)M * W * es_in, hipMemcpyHostToDevice, s));
 
   Module* mod = calls[0].inv->fn->mod;
   hipFunction_t kfn = mod->get(kname.c_str());
-  uint32_t grid = (uint32_t)c.cus * occ;
-  if (bf16) grid = std::max<uint32_t>(8, grid / 8 * 8);  // XCD-ranged kernels need a multiple of 8
+  hipFunction_t tfn = split ? mod->get(plan.tail->name) : nullptr;
+  const uint32_t grid = bf16 ? shape_grid(c, *ms) : (uint32_t)c.cus * 4;
+  const uint32_t threads = bf16 ? ms->threads : 256;
+  const uint32_t tgrid = split ? shape_grid(c, *plan.tail) : 0, tthreads = split ? plan.tail->threads : 0;
   const GemmHdr* d_hdr = reinterpret_cast<const GemmHdr*>(F.d_meta);
   const GemmGroup* d_grp = reinterpret_cast<const GemmGroup*>(F.d_meta + kMetaGroupsOff);
+  const GemmHdr* d_thdr = reinterpret_cast<const GemmHdr*>(F.d_meta + kMetaTailOff);
+  const GemmGroup* d_tgrp = reinterpret_cast<const GemmGroup*>(F.d_meta + kMetaTailOff + kMetaGroupsOff);
   const uint64_t* d_in_tab = reinterpret_cast<const uint64_t*>(F.d_meta + kMetaTabOff);
   const uint64_t* d_out_tab = d_in_tab + rows_cap;
   const size_t half = F.ws_cap / 2;
@@ -255,15 +298,23 @@ int launch_mlp_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, int fl
     la.flags = (l + 1 < L ? kRelu : 0u) | (l + 1 == L ? kOutF32 : 0u);
     return la;
   };
+  auto layers = [&](hipStream_t st) {
+    for (uint32_t l = 0; l < L; l++) {
+      const LayerArgs la = layer_args(l);
+      if (tiles) launch_kernel(kfn, grid, threads, st, d_hdr, d_grp, la);
+      if (split) launch_kernel(tfn, tgrid, tthreads, st, d_thdr, d_tgrp, la);
+    }
+  };
   const char* tname = bf16 ? "ggemm_bf16" : "mlp_f32";
   const int tok = c.timer.start(tname, s, L);
   if (c.cfg.batch) {
-    const GraphKey key{kname, L, W};
+    const GraphKey key{kname + (split ? std::string("+") + plan.tail->name : std::string()) + (tiles ? "" : "/tail"),
+                       L, W};
     auto it = F.graphs.find(key);
     if (it == F.graphs.end()) {
       hipStream_t cap = s;
       HIPX(hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed));
-      for (uint32_t l = 0; l < L; l++) launch_kernel(kfn, grid, threads, cap, d_hdr, d_grp, layer_args(l));
+      layers(cap);
       hipGraph_t g = nullptr;
       HIPX(hipStreamEndCapture(cap, &g));
       hipGraphExec_t ex = nullptr;
@@ -273,7 +324,7 @@ int launch_mlp_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, int fl
     }
     HIPX(hipGraphLaunch(it->second, s));
   } else {
-    for (uint32_t l = 0; l < L; l++) launch_kernel(kfn, grid, threads, s, d_hdr, d_grp, layer_args(l));
+    layers(s);
   }
   c.timer.stop(tok, s);
   if (host_out) HIPX(hipMemcpyAsync(F.h_out, F.d_out, (size_t)M * W * 4, hipMemcpyDeviceToHost, s));
@@ -369,13 +420,25 @@ int launch_stencil_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, in
 }
 
 // ---------------------------------------------------------------- autotuner
-// Tile shape per (width, row bucket): every shape is timed on a synthetic
-// layer of that size and the fastest kept.  All shapes give bit-identical
-// results (same MFMA, same K order), so tuning never changes outputs.
-static uint32_t bucket_of(uint32_t rows) {
-  uint32_t b = 16;
-  while (b < rows) b <<= 1;
-  return b;
+// Each tile shape's time for one full wave of tiles (one tile per workgroup
+// of its grid, K = width deep) is measured once per width on a synthetic
+// layer.  A launch of T tiles then costs waves(T) full-wave times, where a
+// ranged shape's waves are set by its largest XCD range.  All shapes give
+// bit-identical results (same MFMA, same K order), so neither the choice
+// nor a main/tail split changes any output.
+uint32_t shape_grid(const Ctx& c, const TileShape& ts) {
+  return std::max<uint32_t>(8, (uint32_t)c.cus * ts.occupancy / 8 * 8);
+}
+
+static uint64_t waves_of(const TileShape& ts, uint32_t grid, uint64_t tiles) {
+  if (!tiles) return 0;
+  if (!ts.ranged) return (tiles + grid - 1) / grid;
+  const uint64_t per_range = (tiles + kXcdCount - 1) / kXcdCount, per_xcd = grid / kXcdCount;
+  return (per_range + per_xcd - 1) / per_xcd;
+}
+
+static uint64_t tiles_of(const TileShape& ts, uint32_t W, uint32_t rows) {
+  return (uint64_t)((rows + ts.bm - 1) / ts.bm) * (W / ts.bn);
 }
 
 static void tune_save(Ctx& c) {
@@ -392,58 +455,53 @@ void tune_load(Ctx& c) {
   while (in >> key >> k >> ms) {
     bool ok = false;
     for (const auto& s : kShapes) ok |= k == s.name;
-    if (ok) c.tune[key] = TuneEntry{k, ms};
+    if (ok && ms > 0) c.tune[key] = TuneEntry{k, ms};
   }
 }
 
-// Key: (width, row bucket, group bucket).  The synthetic launch has the
-// bucketed number of groups, each with its own weights and an equal share
-// of the rows, since the group count changes both weight traffic and the
-// padding of each group's last row tile.
-std::string tuned_kernel(Ctx& c, uint32_t width, uint32_t rows, uint32_t groups) {
-  const uint32_t bucket = bucket_of(rows);
-  uint32_t gb = 1;
-  while (gb < groups && gb < 8) gb <<= 1;
-  while (gb > 1 && bucket / gb < 1) gb >>= 1;
-  const std::string key = std::to_string(width) + ":" + std::to_string(bucket) + ":" + std::to_string(gb);
-  auto it = c.tune.find(key);
-  if (it != c.tune.end()) return it->second.kernel;
+static std::string tune_key(uint32_t width, const TileShape& ts) {
+  return std::to_string(width) + ":" + ts.name;
+}
+
+// Full-wave time of every shape that divides `width`, measured on first use.
+static void tune_width(Ctx& c, uint32_t width) {
+  bool all = true;
+  for (const auto& ts : kShapes)
+    if (fits(ts, width)) all &= c.tune.count(tune_key(width, ts)) > 0;
+  if (all) return;
   Module* mod = load_module(c, SAGE_MLP_BF16);
+  uint32_t max_rows = 0;
+  for (const auto& ts : kShapes) {
+    if (!fits(ts, width)) continue;
+    const uint32_t nt = width / ts.bn, grid = shape_grid(c, ts);
+    max_rows = std::max(max_rows, ((grid + nt - 1) / nt) * ts.bm);
+  }
   const size_t wbytes = (size_t)width * width * 2, nblk = (wbytes + kBlock - 1) / kBlock;
-  uint8_t* w = (uint8_t*)c.cache.get(wbytes * gb);
-  uint8_t* a = (uint8_t*)c.cache.get((size_t)bucket * width * 2);
-  uint8_t* o = (uint8_t*)c.cache.get((size_t)bucket * width * 2);
-  uint8_t* meta = (uint8_t*)c.cache.get(4096 + gb * nblk * 8);
-  std::vector<uint64_t> tab(gb * nblk);
-  for (uint32_t g = 0; g < gb; g++)
-    for (size_t b = 0; b < nblk; b++) tab[g * nblk + b] = (uint64_t)(w + g * wbytes + b * kBlock);
+  uint8_t* w = (uint8_t*)c.cache.get(wbytes);
+  uint8_t* a = (uint8_t*)c.cache.get((size_t)max_rows * width * 2);
+  uint8_t* o = (uint8_t*)c.cache.get((size_t)max_rows * width * 2);
+  uint8_t* meta = (uint8_t*)c.cache.get(4096 + nblk * 8);
+  std::vector<uint64_t> tab(nblk);
+  for (size_t b = 0; b < nblk; b++) tab[b] = (uint64_t)(w + b * kBlock);
   hipStream_t s = c.ctl;
-  // small non-zero values (BF16 0x3C00 = 1/128): data-dependent power stays realistic
-  HIPX(hipMemsetD16Async((hipDeviceptr_t)w, 0x3C00, wbytes * gb / 2, s));
-  HIPX(hipMemsetD16Async((hipDeviceptr_t)a, 0x3C00, (size_t)bucket * width, s));
+  // small non-zero values (BF16 0x3C00 = 1/128), alternating sign in the
+  // weights: data-dependent power stays closer to a real layer's
+  HIPX(hipMemsetD32Async((hipDeviceptr_t)w, 0xBC003C00u, wbytes / 4, s));
+  HIPX(hipMemsetD16Async((hipDeviceptr_t)a, 0x3C00, (size_t)max_rows * width, s));
   HIPX(hipMemcpyAsync(meta + 4096, tab.data(), tab.size() * 8, hipMemcpyHostToDevice, s));
   HIPX(hipStreamSynchronize(s));
   hipEvent_t e0, e1;
   HIPX(hipEventCreate(&e0));
   HIPX(hipEventCreate(&e1));
-  std::string best;
-  double best_ms = 1e30;
   for (const auto& ts : kShapes) {
-    if (width % ts.bn) continue;
-    GemmHdr h{};
-    std::vector<GemmGroup> gr(gb);
-    uint32_t tiles = 0, row = 0;
-    for (uint32_t g = 0; g < gb; g++) {
-      const uint32_t m = bucket / gb + (g < bucket % gb ? 1 : 0);
-      gr[g] = GemmGroup{(uint64_t)(meta + 4096 + g * nblk * 8), m, row, tiles, 0};
-      tiles += ((m + ts.bm - 1) / ts.bm) * (width / ts.bn);
-      row += m;
-    }
-    h.n_groups = gb;
-    h.total_tiles = tiles;
-    h.total_rows = bucket;
-    HIPX(hipMemcpyAsync(meta, &h, sizeof(GemmHdr), hipMemcpyHostToDevice, s));
-    HIPX(hipMemcpyAsync(meta + 16, gr.data(), gb * sizeof(GemmGroup), hipMemcpyHostToDevice, s));
+    if (!fits(ts, width) || c.tune.count(tune_key(width, ts))) continue;
+    const uint32_t nt = width / ts.bn, grid = shape_grid(c, ts);
+    const uint32_t rows = ((grid + nt - 1) / nt) * ts.bm;
+    const uint64_t tiles = tiles_of(ts, width, rows);
+    GemmHdr h{1, (uint32_t)tiles, rows, 0};
+    GemmGroup g{(uint64_t)(meta + 4096), rows, 0, 0, 0};
+    HIPX(hipMemcpyAsync(meta, &h, sizeof h, hipMemcpyHostToDevice, s));
+    HIPX(hipMemcpyAsync(meta + 16, &g, sizeof g, hipMemcpyHostToDevice, s));
     HIPX(hipStreamSynchronize(s));
     LayerArgs la{};
     la.a_base = a;
@@ -451,22 +509,16 @@ std::string tuned_kernel(Ctx& c, uint32_t width, uint32_t rows, uint32_t groups)
     la.N = la.K = width;
     la.flags = kRelu;
     hipFunction_t k = mod->get(ts.name);
-    const uint32_t grid = std::max<uint32_t>(8, (uint32_t)c.cus * ts.occupancy / 8 * 8);
-    auto run = [&] {
-      launch_kernel(k, grid, ts.threads, s, (const GemmHdr*)meta, (const GemmGroup*)(meta + 16), la);
-    };
+    auto run = [&] { launch_kernel(k, grid, ts.threads, s, (const GemmHdr*)meta, (const GemmGroup*)(meta + 16), la); };
     run();
-    const int reps = 5;
+    const int reps = 4;
     HIPX(hipEventRecord(e0, s));
     for (int r = 0; r < reps; r++) run();
     HIPX(hipEventRecord(e1, s));
     HIPX(hipEventSynchronize(e1));
     float ms = 0;
     HIPX(hipEventElapsedTime(&ms, e0, e1));
-    if (ms / reps < best_ms) {
-      best_ms = ms / reps;
-      best = ts.name;
-    }
+    c.tune[tune_key(width, ts)] = TuneEntry{ts.name, (double)ms / reps / (double)waves_of(ts, grid, tiles)};
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -474,8 +526,71 @@ std::string tuned_kernel(Ctx& c, uint32_t width, uint32_t rows, uint32_t groups)
   c.cache.put(a);
   c.cache.put(o);
   c.cache.put(meta);
-  c.tune[key] = TuneEntry{best, best_ms};
   tune_save(c);
+}
+
+// Gap between two dependent kernels of one stream, charged to a split plan.
+constexpr double kLaunchGapMs = 0.004;
+
+// Cheapest plan for groups of `m` rows: one shape over all tiles, or a
+// large shape over every group's row tiles except the ragged last tiles of
+// the groups in `split`, which a thin shape covers in a second launch.
+// Candidate splits move the k smallest ragged tiles, k = 1, 2, ...
+MlpPlan plan_mlp(Ctx& c, uint32_t W, const std::vector<uint32_t>& m) {
+  MlpPlan best;
+  best.split.assign(m.size(), 0);
+  if (!c.force_tile.empty()) {
+    const size_t plus = c.force_tile.find('+');
+    best.main = &shape_of(c.force_tile.substr(0, plus));
+    if (plus != std::string::npos) {
+      best.tail = &shape_of(c.force_tile.substr(plus + 1));
+      for (size_t g = 0; g < m.size(); g++) best.split[g] = m[g] % best.main->bm != 0;
+    }
+    for (const TileShape* t : {best.main, best.tail})
+      if (t && !fits(*t, W)) fail(SAGE_EINVAL, "tile %s does not fit width %u", t->name, W);
+    return best;
+  }
+  tune_width(c, W);
+  auto wave = [&](const TileShape& ts) { return c.tune.at(tune_key(W, ts)).ms; };
+  double best_cost = 1e300;
+  std::vector<std::pair<uint32_t, size_t>> parts;  // (ragged rows, group)
+  for (const auto& ts : kShapes) {
+    if (!fits(ts, W)) continue;
+    const uint32_t grid = shape_grid(c, ts);
+    uint64_t tiles = 0;
+    parts.clear();
+    for (size_t g = 0; g < m.size(); g++) {
+      tiles += tiles_of(ts, W, m[g]);
+      if (m[g] % ts.bm) parts.push_back({m[g] % ts.bm, g});
+    }
+    const double cost = waves_of(ts, grid, tiles) * wave(ts);
+    if (cost < best_cost) {
+      best_cost = cost;
+      best.main = &ts;
+      best.tail = nullptr;
+    }
+    if (ts.bm < 128 || parts.empty()) continue;
+    std::sort(parts.begin(), parts.end());
+    const uint64_t per_part = W / ts.bn;
+    for (const auto& tt : kShapes) {
+      if (!fits(tt, W) || tt.bm >= ts.bm || !tt.ranged) continue;
+      const uint32_t tgrid = shape_grid(c, tt);
+      uint64_t ttiles = 0;
+      for (size_t k = 1; k <= parts.size() && k <= 64; k++) {
+        ttiles += tiles_of(tt, W, parts[k - 1].first);
+        const uint64_t main_tiles = tiles - k * per_part;
+        const double sc = waves_of(ts, grid, main_tiles) * wave(ts) + waves_of(tt, tgrid, ttiles) * wave(tt) +
+                          kLaunchGapMs;
+        if (sc < best_cost) {
+          best_cost = sc;
+          best.main = &ts;
+          best.tail = &tt;
+          std::fill(best.split.begin(), best.split.end(), 0);
+          for (size_t i = 0; i < k; i++) best.split[parts[i].second] = 1;
+        }
+      }
+    }
+  }
   return best;
 }
 

@@ -325,13 +325,14 @@ struct Ctx {
   std::map<void*, size_t> pinned;            // sage_host_alloc ranges
   uint64_t* h_stage = nullptr;               // pinned staging for block-table uploads
   size_t h_stage_cap = 0;
-  std::map<std::string, TuneEntry> tune;     // "width:rows:groups" bucket -> best kernel
+  std::map<std::string, TuneEntry> tune;     // "width:shape" -> time of one full wave of tiles (ms)
   // counters
   uint64_t logical = 0, h2d = 0, reloads = 0, registrations = 0, invocations = 0, mismatches = 0;
   double t_register = 0, t_code = 0, t_fp_wait = 0, t_dedup = 0, t_verify = 0, t_setup = 0, t_invoke = 0;
   Serve* serve = nullptr;                    // running serving loop, if any
   Worker worker;                             // code branch of fn_register
   std::string force_tile;                    // SAGE_TILE: fixed GEMM tile shape (tests)
+  std::string last_launch;                   // kernels and tiles of the last MLP launch
   bool test_fp_const = false;                // force every fingerprint equal (collision test)
   uint64_t test_fp_value = 0;
 
@@ -370,7 +371,6 @@ int launch_stencil_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, in
 void finish_flight(Ctx& c, int flight);
 void flights_init(Ctx& c);
 void flights_destroy(Ctx& c);
-std::string tuned_kernel(Ctx& c, uint32_t width, uint32_t rows, uint32_t groups);
 void tune_load(Ctx& c);
 
 uint64_t setup_internal(Ctx& c, uint64_t fn, uint32_t batch);

@@ -629,4 +629,15 @@ sage_status sage_timing_reset(sage_ctx* p) {
   });
 }
 
+sage_status sage_last_launch(sage_ctx* p, char* out, size_t cap) {
+  return guard([&] {
+    Ctx& c = ctx_of(p);
+    if (!out) fail(SAGE_EINVAL, "null output");
+    std::lock_guard<std::recursive_mutex> lk(c.mu);
+    if (c.last_launch.empty()) fail(SAGE_ENOTFOUND, "no MLP launch yet");
+    if (c.last_launch.size() + 1 > cap) fail(SAGE_EINVAL, "need %zu bytes", c.last_launch.size() + 1);
+    std::memcpy(out, c.last_launch.c_str(), c.last_launch.size() + 1);
+  });
+}
+
 }  // extern "C"

@@ -124,6 +124,7 @@ _sigs = {
     "sage_timing_enable": (C.c_int, [_P, C.c_int]),
     "sage_timing_get": (C.c_int, [_P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]),
     "sage_timing_reset": (C.c_int, [_P]),
+    "sage_last_launch": (C.c_int, [_P, C.c_char_p, C.c_size_t]),
     "sage_selftest_setup_overlap": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_int,
                                               C.POINTER(C.c_double)]),
     "sage_serve_start": (C.c_int, [_P, C.c_uint32]),
@@ -334,6 +335,12 @@ def sage_timing_get(ctx: int, kernel: str):
 
 def sage_timing_reset(ctx: int) -> None:
     _check(_lib.sage_timing_reset(ctx), "sage_timing_reset")
+
+
+def sage_last_launch(ctx: int) -> str:
+    buf = C.create_string_buffer(512)
+    _check(_lib.sage_last_launch(ctx, buf, 512), "sage_last_launch")
+    return buf.value.decode()
 
 
 def sage_selftest_setup_overlap(load_ms: float, host_ms: float, copy_ms: float, serial: bool) -> float:

@@ -91,13 +91,24 @@ def test_bf16_shared_equals_private_and_eager(sage_ctx_factory, torch_cuda):
 TILES = ["ggemm_bf16_16x64", "ggemm_bf16_32x64", "ggemm_bf16_32x128", "ggemm_bf16_64x128",
          "ggemm_bf16_128x128", "ggemm_bf16_256x128", "ggemm_bf16_128x256", "ggemm2_bf16_256x256",
          "ggemm2_bf16_256x128", "ggemm2_bf16_128x256", "ggemm4_bf16_256x256", "ggemm3_bf16_256x256",
-         "ggemm3_bf16_256x128", "ggemm5_bf16_256x128"]
+         "ggemm3_bf16_256x128", "ggemm5_bf16_256x128", "ggemm5_bf16_256x256",
+         "ggemm3s5_bf16_256x256", "ggemm3w16_bf16_256x256", "ggemm3w16s5_bf16_256x256",
+         "ggemm3_bf16_16x64", "ggemm3_bf16_32x64", "ggemm3_bf16_64x64", "ggemm3_bf16_128x64",
+         "ggemm6_bf16_256x256", "ggemm6s5_bf16_256x256", "ggemm6_bf16_256x128",
+         "ggemm3g4_bf16_16x64", "ggemm3g4_bf16_32x64", "ggemm3g4_bf16_64x64", "ggemm3g4_bf16_128x64",
+         "ggemm3g2_bf16_256x256", "ggemm3t_bf16_16x16", "ggemm3t_bf16_16x32", "ggemm3t_bf16_32x32",
+         # a large shape over full row tiles + a thin shape over the ragged last ones
+         "ggemm3_bf16_256x256+ggemm3_bf16_64x64", "ggemm3w16_bf16_256x256+ggemm3_bf16_16x64",
+         "ggemm5_bf16_256x128+ggemm3_bf16_32x64", "ggemm6_bf16_256x256+ggemm3_bf16_64x64",
+         "ggemm6_bf16_256x256+ggemm3g4_bf16_16x64", "ggemm6_bf16_256x256+ggemm3t_bf16_16x32"]
 
 
 def test_bf16_every_tile_shape_same_bits(sage_ctx_factory, torch_cuda, monkeypatch):
     """Every tile shape (forced, autotuner bypassed) walks K in the same order
     with the same MFMA: all give identical bits, and match the oracle; more
-    than 256 rows in a group exercise several m-tiles of the largest tiles."""
+    than 256 rows in a group exercise several m-tiles of the largest tiles.
+    "main+tail" forces a split launch: the ragged last row tile of every
+    group runs in a second, thin-tile launch of each layer."""
     from paper_2404_14691_amd import sage as S
     layers, width = 2, 512
     batches = [300, 5, 70, 1]
@@ -113,6 +124,9 @@ def test_bf16_every_tile_shape_same_bits(sage_ctx_factory, torch_cuda, monkeypat
         ys = [np.zeros((b, width), dtype=np.float32) for b in batches]
         S.fn_invoke_batch(ctx, invs, xs, ys)
         S.fn_release_batch(ctx, invs)
+        plan = S.sage_last_launch(ctx)
+        assert plan.split("+")[0].split(":")[0] == tile.split("+")[0], plan
+        assert ("+" in plan) == ("+" in tile), plan
         if first is None:
             first = ys
             for i, (x, y) in enumerate(zip(xs, ys)):
