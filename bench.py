@@ -309,6 +309,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-kernels", action="store_true", help="skip the standalone 4 GiB kernel bandwidth runs")
     ap.add_argument("--no-host-link", action="store_true", help="skip the host-memory registration runs")
+    ap.add_argument("--only-shared", action="store_true",
+                    help="time the shared+batched steps only (for counter runs); no plain path or extras")
     ap.add_argument("--workload", default="sharing",
                     help="sharing (default) | batching | stencil | mlp_f32 | serving")
     args = ap.parse_args()
@@ -342,8 +344,9 @@ def main():
         for i in range(args.warmup):
             shared_step(S, ctx, wl)
             log(f"warmup step {i} done")
-        plain_step(S, pctx, wl)
-        log("plain warmup done")
+        if not args.only_shared:
+            plain_step(S, pctx, wl)
+            log("plain warmup done")
         # ---- timed: shared + batched, with per-kernel device timing
         S.sage_timing_reset(ctx)
         S.sage_timing_enable(ctx, True)
@@ -360,10 +363,13 @@ def main():
         f_ms, f_n = S.sage_timing_get(ctx, "fp64k")
         b_ms, b_n = S.sage_timing_get(ctx, "blkcopy")
         # ---- plain
-        p_elapsed, p_res = timed(torch, lambda: plain_step(S, pctx, wl), args.plain_steps)
-        setup_plain = [x for r in p_res for x in r]
-        log(f"plain timed: {p_elapsed * 1e3 / args.plain_steps:.2f} ms/step")
-        standalone = None if args.no_kernels else kernel_bandwidth(S, ctx, torch)
+        if args.only_shared:
+            p_elapsed, setup_plain = None, []
+        else:
+            p_elapsed, p_res = timed(torch, lambda: plain_step(S, pctx, wl), args.plain_steps)
+            setup_plain = [x for r in p_res for x in r]
+            log(f"plain timed: {p_elapsed * 1e3 / args.plain_steps:.2f} ms/step")
+        standalone = None if (args.no_kernels or args.only_shared) else kernel_bandwidth(S, ctx, torch)
         if standalone:
             log(f"standalone kernels: {standalone}")
     finally:
@@ -373,7 +379,7 @@ def main():
     n_req = len(wl.requests)
     ms_step = elapsed / args.steps * 1e3
     value = n_req * args.steps / elapsed
-    plain_value = n_req * args.plain_steps / p_elapsed
+    plain_value = n_req * args.plain_steps / p_elapsed if p_elapsed else None
     flops_launch = 2.0 * wl.rows * wl.width * wl.width
     gemm_avg_ms = g_ms / max(g_n, 1)
     achieved = flops_launch / (gemm_avg_ms * 1e-3) / 1e12
@@ -399,10 +405,11 @@ def main():
             "requests_per_step": n_req, "rows_per_step": wl.rows},
         "setup_ms": {
             "shared": {"p50": round(percentile(setup_shared, 50), 4), "p99": round(percentile(setup_shared, 99), 3)},
-            "plain": {"p50": round(percentile(setup_plain, 50), 4), "p99": round(percentile(setup_plain, 99), 3)}},
+            "plain": {"p50": round(percentile(setup_plain, 50), 4),
+                      "p99": round(percentile(setup_plain, 99), 3)} if setup_plain else None},
         "plain": {"value": round(plain_value, 2), "ms_per_step": round(p_elapsed / args.plain_steps * 1e3, 3),
-                  "steps": args.plain_steps},
-        "speedup_vs_plain": round(value / plain_value, 2),
+                  "steps": args.plain_steps} if plain_value else None,
+        "speedup_vs_plain": round(value / plain_value, 2) if plain_value else None,
         "pool": {"logical_bytes": stats["logical_bytes"], "unique_bytes": stats["unique_bytes"],
                  "shared_bytes": stats["shared_bytes"], "private_bytes": stats["private_bytes"]},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -420,11 +427,11 @@ def main():
         "kernels_standalone_4GiB": standalone,
         "host_ms_per_step": host,
     }
-    if not args.no_host_link:
+    if not args.no_host_link and not args.only_shared:
         log("host-link registration runs ...")
         line["host_link_not_headline"] = host_link(S, torch, wl)
         log(f"host link: {line['host_link_not_headline']}")
-    if not args.no_cpu:
+    if not args.no_cpu and not args.only_shared:
         log("cpu baseline (oracle) ...")
         line["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(line), flush=True)
