@@ -167,15 +167,19 @@ void sage_host_free(sage_ctx* ctx, void* p);
  * already in the pool join that slot (verified byte for byte); the others are
  * copied into new slots.  With share=0 only the function record is made and
  * the data is copied privately at each fn_setup.
- * Returns when the data is in place.  Blobs must be SAGE_RO and match the
- * kind's layout (see sage_fn_desc); sources stay borrowed until
- * fn_unregister.  Errors: EINVAL (layout), ENOMEM (pool full of referenced
- * blocks; the function is not registered), EIO (code object), EHIP. */
+ * Returns when every block is classified (joined or new); copies of new
+ * blocks may still be in flight on the library's control stream, ordered
+ * before every later pool access and before any body of the function.
+ * Blobs must be SAGE_RO and match the kind's layout (see sage_fn_desc);
+ * sources stay borrowed until fn_unregister.  Errors: EINVAL (layout),
+ * ENOMEM (pool full of referenced blocks; the function is not registered),
+ * EIO (code object), EHIP. */
 sage_status fn_register(sage_ctx* ctx, const sage_fn_desc* desc, const sage_blob* blobs,
                         size_t n_blobs, sage_fn* out);
 
 /* Drop a function.  EBUSY while it has live setups.  Blocks no other
- * registered function uses leave the pool. */
+ * registered function uses leave the pool.  Returns after every copy that
+ * reads the function's sources has finished: the caller may free them. */
 sage_status fn_unregister(sage_ctx* ctx, sage_fn fn);
 
 /* Make one invocation of `fn` with `batch` rows (MLP) or fields (stencil)

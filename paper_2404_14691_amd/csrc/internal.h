@@ -272,9 +272,12 @@ struct Ring {
   size_t slots = 0, chunk = 0;
   std::vector<uint8_t*> host, dev;
   std::vector<uint64_t*> dfp, hfp;
-  std::vector<BlkOp*> dops, hops;
+  std::vector<BlkOp*> dops, hops;       // VERIFY (and synchronous) operations
   std::vector<uint32_t*> dres, hres;
-  std::vector<hipEvent_t> ev;
+  std::vector<BlkOp*> dops_c, hops_c;   // COPY operations left in flight on the control stream
+  std::vector<uint32_t*> dres_c;
+  std::vector<hipEvent_t> ev;           // fingerprints (then VERIFY results) of the slot's chunk
+  std::vector<hipEvent_t> ev_c;         // the slot's last in-flight COPY
   std::vector<size_t> cap;  // blocks the fp/op/result buffers of each slot hold
   size_t ops_cap = 0;
 };
@@ -324,6 +327,7 @@ struct Ctx {
   uint64_t next_id = 1;
   std::map<void*, size_t> pinned;            // sage_host_alloc ranges
   uint64_t* h_stage = nullptr;               // pinned staging for block-table uploads
+  hipEvent_t stage_ev = nullptr;             // last upload from h_stage (on ctl)
   size_t h_stage_cap = 0;
   std::map<std::string, TuneEntry> tune;     // "width:shape" -> time of one full wave of tiles (ms)
   // counters

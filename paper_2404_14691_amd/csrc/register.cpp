@@ -24,7 +24,7 @@ void ring_init(Ctx& c) {
     uint64_t *dfp = nullptr, *hfp = nullptr;
     BlkOp *dops = nullptr, *hops = nullptr;
     uint32_t *dres = nullptr, *hres = nullptr;
-    hipEvent_t ev;
+    hipEvent_t ev, ev_c;
     HIPX(hipHostMalloc((void**)&h, R.chunk, hipHostMallocDefault));
     HIPX(hipMalloc((void**)&d, R.chunk));
     HIPX(hipMalloc((void**)&dfp, nblk * 8));
@@ -34,6 +34,7 @@ void ring_init(Ctx& c) {
     HIPX(hipMalloc((void**)&dres, nblk * 4));
     HIPX(hipHostMalloc((void**)&hres, nblk * 4, hipHostMallocDefault));
     HIPX(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    HIPX(hipEventCreateWithFlags(&ev_c, hipEventDisableTiming));
     R.host.push_back(h);
     R.dev.push_back(d);
     R.dfp.push_back(dfp);
@@ -43,6 +44,13 @@ void ring_init(Ctx& c) {
     R.dres.push_back(dres);
     R.hres.push_back(hres);
     R.ev.push_back(ev);
+    R.ev_c.push_back(ev_c);
+    R.dops_c.push_back(nullptr);
+    R.hops_c.push_back(nullptr);
+    R.dres_c.push_back(nullptr);
+    HIPX(hipMalloc((void**)&R.dops_c.back(), nblk * sizeof(BlkOp)));
+    HIPX(hipHostMalloc((void**)&R.hops_c.back(), nblk * sizeof(BlkOp), hipHostMallocDefault));
+    HIPX(hipMalloc((void**)&R.dres_c.back(), nblk * 4));
   }
 }
 
@@ -58,6 +66,10 @@ void ring_destroy(Ctx& c) {
     (void)hipFree(R.dres[i]);
     (void)hipHostFree(R.hres[i]);
     (void)hipEventDestroy(R.ev[i]);
+    (void)hipEventDestroy(R.ev_c[i]);
+    (void)hipFree(R.dops_c[i]);
+    (void)hipHostFree(R.hops_c[i]);
+    (void)hipFree(R.dres_c[i]);
   }
   R = Ring{};
 }
@@ -67,6 +79,12 @@ void ring_destroy(Ctx& c) {
 static void ring_reserve(Ctx& c, int slot, size_t nblk) {
   Ring& R = c.ring;
   if (R.cap[slot] >= nblk) return;
+  HIPX(hipEventSynchronize(R.ev_c[slot]));  // an in-flight COPY may still read the old op buffers
+  (void)hipFree(R.dops_c[slot]);
+  (void)hipHostFree(R.hops_c[slot]);
+  (void)hipFree(R.dres_c[slot]);
+  R.dops_c[slot] = R.hops_c[slot] = nullptr;
+  R.dres_c[slot] = nullptr;
   (void)hipFree(R.dfp[slot]);
   (void)hipHostFree(R.hfp[slot]);
   (void)hipFree(R.dops[slot]);
@@ -83,6 +101,9 @@ static void ring_reserve(Ctx& c, int slot, size_t nblk) {
   HIPX(hipHostMalloc((void**)&R.hops[slot], nblk * sizeof(BlkOp), hipHostMallocDefault));
   HIPX(hipMalloc((void**)&R.dres[slot], nblk * 4));
   HIPX(hipHostMalloc((void**)&R.hres[slot], nblk * 4, hipHostMallocDefault));
+  HIPX(hipMalloc((void**)&R.dops_c[slot], nblk * sizeof(BlkOp)));
+  HIPX(hipHostMalloc((void**)&R.hops_c[slot], nblk * sizeof(BlkOp), hipHostMallocDefault));
+  HIPX(hipMalloc((void**)&R.dres_c[slot], nblk * 4));
   R.cap[slot] = nblk;
 }
 
@@ -185,6 +206,14 @@ struct Chunk {
 // fingerprint whose bytes verify equal, or becomes a new class copied into
 // a fresh slot.  Fingerprints are only an index; equality is decided by
 // the VERIFY kernel, so a collision costs a slot, never a wrong byte.
+//
+// Pool writes are ordered on the control stream: a chunk's VERIFY launch
+// runs there and is waited for; its COPY launch follows and is left in
+// flight, overlapping the next chunk's (or registration's) host work.
+// Everything that reads pool slots later is ordered behind it: VERIFYs and
+// reloads on the same stream, bodies through the function's ready event
+// (recorded on the control stream), a ring slot's next fill through the
+// slot's copy event.
 void register_shared(Ctx& c, Fn& f) {
   Pool& P = c.pool;
   Ring& R = c.ring;
@@ -224,6 +253,7 @@ void register_shared(Ctx& c, Fn& f) {
     if (src.dev) {
       ch.data = src.p + ch.off;
     } else {
+      HIPX(hipStreamWaitEvent(s, R.ev_c[ch.slot], 0));  // the slot's last COPY has read its data
       const uint8_t* hsrc = src.p + ch.off;
       if (!src.pinned) {
         fill_parallel(c, R.host[ch.slot], hsrc, ch.bytes);
@@ -241,13 +271,15 @@ void register_shared(Ctx& c, Fn& f) {
 
   auto process = [&](Chunk& ch) {
     const int slot = ch.slot;
-    hipStream_t s = stream_of(slot);
+    hipStream_t s = c.ctl;
     double t0 = now_ms();
     HIPX(hipEventSynchronize(R.ev[slot]));
+    HIPX(hipEventSynchronize(R.ev_c[slot]));  // the slot's previous COPY has read its op buffer
     double t1 = now_ms();
     c.t_fp_wait += t1 - t0;
     BlkOp* ops = R.hops[slot];
-    uint32_t nops = 0;
+    BlkOp* cops = R.hops_c[slot];
+    uint32_t nops = 0, ncops = 0;
     struct Pend {
       uint32_t i, cand, op;
     };
@@ -271,7 +303,7 @@ void register_shared(Ctx& c, Fn& f) {
       chunk_new.push_back(cl);
       P.cls[cl].mark = mark;
       f.cls[gb] = cl;
-      ops[nops++] = BlkOp{(uint64_t)(ch.data + (uint64_t)i * kBlock), (uint64_t)P.addr(slotid), len, 0};
+      cops[ncops++] = BlkOp{(uint64_t)(ch.data + (uint64_t)i * kBlock), (uint64_t)P.addr(slotid), len, 0};
     };
     // first candidate after `after` (or the first one) with the block's length
     auto next_cand = [&](uint64_t fp, uint32_t len, uint32_t after) -> uint32_t {
@@ -303,7 +335,8 @@ void register_shared(Ctx& c, Fn& f) {
       HIPX(launch_blkcopy(R.dops[slot], nops, R.dres[slot], c.max_groups_copy(), s));
       c.timer.stop(tok, s);
       HIPX(hipMemcpyAsync(R.hres[slot], R.dres[slot], nops * 4, hipMemcpyDeviceToHost, s));
-      HIPX(hipStreamSynchronize(s));
+      HIPX(hipEventRecord(R.ev[slot], s));
+      HIPX(hipEventSynchronize(R.ev[slot]));
       t1 = now_ms();
       c.t_verify += t1 - tv;
       std::vector<uint32_t> res(R.hres[slot], R.hres[slot] + nops);
@@ -326,6 +359,14 @@ void register_shared(Ctx& c, Fn& f) {
       }
       pend.swap(again);
     }
+    if (ncops > 0) {
+      // new classes: copy into their slots, left in flight on the control stream
+      HIPX(hipMemcpyAsync(R.dops_c[slot], cops, ncops * sizeof(BlkOp), hipMemcpyHostToDevice, s));
+      const int tok = c.timer.start("blkcopy", s, 1);
+      HIPX(launch_blkcopy(R.dops_c[slot], ncops, R.dres_c[slot], c.max_groups_copy(), s));
+      c.timer.stop(tok, s);
+      HIPX(hipEventRecord(R.ev_c[slot], s));
+    }
     for (uint32_t cl : chunk_new) P.cls[cl].pending = nullptr;
     c.t_dedup += now_ms() - t1;
   };
@@ -345,6 +386,7 @@ void register_shared(Ctx& c, Fn& f) {
     }
   } catch (...) {
     for (hipStream_t s : c.streams) (void)hipStreamSynchronize(s);
+    (void)hipStreamSynchronize(c.ctl);
     for (uint32_t cl : created) P.drop_class(cl);
     throw;
   }
@@ -410,7 +452,8 @@ void reload_classes(Ctx& c, Fn& f, const std::vector<uint32_t>& missing) {
   for (uint32_t cl : f.distinct) P.cls[cl].mark = mark;
   auto protect = [&](uint32_t cl) { return P.cls[cl].mark == mark; };
   const size_t per_slot = R.chunk / kBlock;
-  hipStream_t s = c.streams[0];
+  hipStream_t s = c.ctl;  // behind in-flight registration copies
+  HIPX(hipEventSynchronize(R.ev_c[0]));  // slot 0's last COPY has read its staging and op buffers
   size_t i = 0;
   while (i < missing.size()) {
     BlkOp* ops = R.hops[0];
@@ -451,6 +494,7 @@ void refresh_table(Ctx& c, Fn& f) {
   std::vector<uint64_t> t(f.n_blocks);
   for (uint32_t b = 0; b < f.n_blocks; b++) t[b] = (uint64_t)c.pool.addr(c.pool.cls[f.cls[b]].slot);
   if (t != f.h_table) {
+    HIPX(hipEventSynchronize(c.stage_ev));  // the previous upload has read the staging buffer
     if (c.h_stage_cap < t.size()) {
       if (c.h_stage) HIPX(hipHostFree(c.h_stage));
       c.h_stage = nullptr;
@@ -460,7 +504,8 @@ void refresh_table(Ctx& c, Fn& f) {
     }
     std::memcpy(c.h_stage, t.data(), t.size() * 8);
     HIPX(hipMemcpyAsync(f.d_table, c.h_stage, t.size() * 8, hipMemcpyHostToDevice, c.ctl));
-    HIPX(hipStreamSynchronize(c.ctl));
+    HIPX(hipEventRecord(c.stage_ev, c.ctl));
+    HIPX(hipEventRecord(f.ready, c.ctl));  // bodies of f wait for the new table
     f.h_table.swap(t);
   }
   f.table_epoch = c.pool.epoch;

@@ -214,6 +214,7 @@ sage_status sage_open(int device, const sage_config* cfg, sage_ctx** out) {
     HIPX(hipGetDeviceProperties(&prop, device));
     c.cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     HIPX(hipStreamCreateWithFlags(&c.ctl, hipStreamNonBlocking));
+    HIPX(hipEventCreateWithFlags(&c.stage_ev, hipEventDisableTiming));
     for (uint32_t i = 0; i < c.cfg.streams; i++) {
       hipStream_t s;
       HIPX(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
@@ -248,10 +249,8 @@ sage_status sage_close(sage_ctx* p) {
       (void)hipSetDevice(c.device);
       (void)hipDeviceSynchronize();
       flights_destroy(c);
-      for (auto& kv : c.fns) {
-        (void)hipFree(kv.second->d_table);
+      for (auto& kv : c.fns)
         if (kv.second->ready) (void)hipEventDestroy(kv.second->ready);
-      }
       c.fns.clear();
       c.invs.clear();
       c.cache.release_all();
@@ -263,6 +262,7 @@ sage_status sage_close(sage_ctx* p) {
       c.pinned.clear();
       if (c.h_stage) (void)hipHostFree(c.h_stage);
       c.h_stage = nullptr;
+      if (c.stage_ev) (void)hipEventDestroy(c.stage_ev);
       c.timer.destroy();
       for (hipStream_t s : c.streams) (void)hipStreamDestroy(s);
       (void)hipStreamDestroy(c.ctl);
@@ -318,15 +318,13 @@ sage_status fn_register(sage_ctx* p, const sage_fn_desc* desc, const sage_blob* 
     f->n_blocks = first;
     HIPX(hipEventCreateWithFlags(&f->ready, hipEventDisableTiming));
     Fn& F = *f;
-    // code branch: module + block table; data branch: the blobs
+    // the block table comes from the device cache (no hipMalloc/hipFree per function)
+    if (c.cfg.share) F.d_table = (uint64_t*)c.cache.get(std::max<size_t>(8, (size_t)F.n_blocks * 8));
+    // code branch: module; data branch: the blobs
     double t_code = 0;
     auto code = [&] {
       const double t0 = now_ms();
       F.mod = load_module(c, F.d.kind);
-      if (c.cfg.share) {
-        HIPX(hipSetDevice(c.device));
-        HIPX(hipMalloc((void**)&F.d_table, std::max<size_t>(8, (size_t)F.n_blocks * 8)));
-      }
       t_code = now_ms() - t0;
     };
     auto data = [&] {
@@ -337,7 +335,8 @@ sage_status fn_register(sage_ctx* p, const sage_fn_desc* desc, const sage_blob* 
       if (c.cfg.share) refresh_table(c, F);
       HIPX(hipEventRecord(F.ready, c.ctl));
     } catch (...) {
-      if (F.d_table) (void)hipFree(F.d_table);
+      (void)hipStreamSynchronize(c.ctl);
+      if (F.d_table) c.cache.put(F.d_table);
       (void)hipEventDestroy(F.ready);
       throw;
     }
@@ -362,7 +361,9 @@ sage_status fn_unregister(sage_ctx* p, sage_fn id) {
     for (uint32_t cl : f.distinct)
       if (P.cls[cl].members == 0) P.drop_class(cl);
     c.logical -= f.ro_bytes;
-    (void)hipFree(f.d_table);
+    // copies from f's sources may still be in flight; the caller may free them on return
+    HIPX(hipEventSynchronize(f.ready));
+    if (f.d_table) c.cache.put(f.d_table);
     (void)hipEventDestroy(f.ready);
     c.fns.erase(id);
   });
@@ -572,6 +573,7 @@ sage_status sage_read_slot(sage_ctx* p, uint32_t slot, void* host) {
     bool found = false;
     for (const Class& k : c.pool.cls) found |= k.alive && k.slot == slot;
     if (!found) fail(SAGE_ENOTFOUND, "slot %u holds no class", slot);
+    HIPX(hipStreamSynchronize(c.ctl));  // pool writes are ordered on the control stream
     HIPX(hipMemcpy(host, c.pool.addr(slot), kBlock, hipMemcpyDeviceToHost));
   });
 }
