@@ -272,31 +272,38 @@ def host_link(S, torch, wl):
     return out
 
 
-def cpu_baseline(wl, n_inv=8, seed=0):
-    """The oracle on the host: one function's fingerprints + dedup map and
-    `n_inv` of its invocations in float64; extrapolated to one step."""
+def cpu_baseline(wl, inv_per_fn=32):
+    """The oracle on the host: fingerprints and the cross-function dedup map
+    of all functions' blobs, then `inv_per_fn` invocations of each function
+    in float64; scaled to one step of the workload."""
     from oracle import dedup as OD
     from oracle import fingerprint as OF
     from oracle import mlp as OM
     t0 = time.perf_counter()
-    OF.fp64k_blob(wl.host_blobs[0])
-    OD.partition_dict([wl.host_blobs[0]], 65536)
+    for blob in wl.host_blobs:
+        OF.fp64k_blob(blob)
+    OD.partition_dict(wl.host_blobs, 65536)
     t_reg = time.perf_counter() - t0
-    W = OM.bf16_to_f64(wl.host_blobs[0]).reshape(wl.layers, wl.width, wl.width)
-    reqs = [r for r in wl.requests if r[0] == 0][:n_inv]
-    t0 = time.perf_counter()
-    for _, b, r in reqs:
-        OM.mlp_forward(OM.bf16_to_f64(wl.x_host[r:r + b]), W)
-    t_inv = (time.perf_counter() - t0) / len(reqs)
-    step_s = wl.n_fns * t_reg + len(wl.requests) * t_inv
+    t_inv, n_inv = 0.0, 0
+    for f, blob in enumerate(wl.host_blobs):
+        W = OM.bf16_to_f64(blob).reshape(wl.layers, wl.width, wl.width)
+        reqs = [r for r in wl.requests if r[0] == f][:inv_per_fn]
+        t0 = time.perf_counter()
+        for _, b, r in reqs:
+            OM.mlp_forward(OM.bf16_to_f64(wl.x_host[r:r + b]), W)
+        t_inv += time.perf_counter() - t0
+        n_inv += len(reqs)
+        del W
+    step_s = t_reg + len(wl.requests) * t_inv / n_inv
     try:
         from threadpoolctl import threadpool_info
         cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
         cores = os.cpu_count() or 1
     return {"value": len(wl.requests) / step_s, "unit": "invocations/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"fingerprint + dedup map of 1 of {wl.n_fns} functions (256 MiB) and {len(reqs)} of its "
-                      f"invocations in float64 numpy; step time = {wl.n_fns} x registration + "
+            "sample": f"fingerprints + cross-function dedup map of all {wl.n_fns} functions (4 x 256 MiB) and "
+                      f"{n_inv} of the {len(wl.requests)} invocations ({inv_per_fn} per function) in float64 "
+                      f"numpy, {t_reg + t_inv:.1f} s measured; step = registrations + "
                       f"{len(wl.requests)} x mean invocation ({step_s:.1f} s)"}
 
 

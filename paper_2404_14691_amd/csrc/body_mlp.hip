@@ -645,7 +645,7 @@ __device__ __forceinline__ void phase_sync() {
   __builtin_amdgcn_sched_barrier(0);
 }
 
-template <int BM, int BN, int WM, int WN, int S>
+template <int BM, int BN, int WM, int WN, int S, bool PRIO = false, bool LOADS_FIRST = false>
 __device__ __forceinline__ void ggemm6(const GemmHdr* __restrict__ hdr, const GemmGroup* __restrict__ groups,
                                        const LayerArgs la, uint8_t* lds) {
   constexpr int NWN = BN / WN, NWM = BM / WM;
@@ -726,6 +726,7 @@ __device__ __forceinline__ void ggemm6(const GemmHdr* __restrict__ hdr, const Ge
     const uint32_t chunk = lane >> 4;
     for (uint32_t kt = 0; kt < KT; kt++) {
       // memory phase
+      if (LOADS_FIRST && kt + S - 1 < KT) issue(kt + S - 1);
       const uint8_t* st = lds + (kt % S) * STAGE;
       bf16x8 af[FM], bfr[FN];
 #pragma unroll
@@ -734,7 +735,7 @@ __device__ __forceinline__ void ggemm6(const GemmHdr* __restrict__ hdr, const Ge
 #pragma unroll
       for (int jj = 0; jj < FN; jj++)
         bfr[jj] = *reinterpret_cast<const bf16x8*>(st + A_STAGE + swz3(wn * WN + jj * 16 + (lane & 15), chunk));
-      if (kt + S - 1 < KT) issue(kt + S - 1);
+      if (!LOADS_FIRST && kt + S - 1 < KT) issue(kt + S - 1);
       if (kt + 1 < KT) {
         const uint32_t later = (KT - 2 - kt) < (uint32_t)(S - 2) ? (KT - 2 - kt) : (uint32_t)(S - 2);
         wait_stages<LPS, S - 2>(later);  // this wave's loads of slice kt + 1 landed
@@ -742,11 +743,13 @@ __device__ __forceinline__ void ggemm6(const GemmHdr* __restrict__ hdr, const Ge
       __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): fragments in registers, slice kt free
       phase_sync();
       // matrix phase
+      if (PRIO) __builtin_amdgcn_s_setprio(1);
 #pragma unroll
       for (int i = 0; i < FM; i++)
 #pragma unroll
         for (int jj = 0; jj < FN; jj++)
           acc[i][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[jj], acc[i][jj], 0, 0, 0);
+      if (PRIO) __builtin_amdgcn_s_setprio(0);
       phase_sync();
     }
     if (!lag) phase_sync();  // both groups leave the tile after the same number of barriers
@@ -849,15 +852,20 @@ SAGE_GGEMM3G(ggemm3t_bf16_16x32, 16, 32, 16, 32, 16, 4)
 SAGE_GGEMM3G(ggemm3t_bf16_32x32, 32, 32, 16, 32, 16, 4)
 
 // ping-pong over the direct-to-LDS ring
-#define SAGE_GGEMM6(NAME, BM, BN, WM, WN, S)                                                          \
+#define SAGE_GGEMM6(NAME, BM, BN, WM, WN, S, PRIO, LF)                                                \
   extern "C" __global__ __launch_bounds__(512, 1) void NAME(                                           \
       const GemmHdr* __restrict__ hdr, const GemmGroup* __restrict__ groups, LayerArgs la) {           \
     __shared__ __attribute__((aligned(1024))) uint8_t lds[S * (BM + BN) * kRow3];                      \
-    ggemm6<BM, BN, WM, WN, S>(hdr, groups, la, lds);                                                   \
+    ggemm6<BM, BN, WM, WN, S, PRIO, LF>(hdr, groups, la, lds);                                         \
   }
-SAGE_GGEMM6(ggemm6_bf16_256x256, 256, 256, 128, 64, 4)
-SAGE_GGEMM6(ggemm6s5_bf16_256x256, 256, 256, 128, 64, 5)
-SAGE_GGEMM6(ggemm6_bf16_256x128, 256, 128, 64, 64, 4)
+SAGE_GGEMM6(ggemm6_bf16_256x256, 256, 256, 128, 64, 4, false, false)
+SAGE_GGEMM6(ggemm6s5_bf16_256x256, 256, 256, 128, 64, 5, false, false)
+SAGE_GGEMM6(ggemm6_bf16_256x128, 256, 128, 64, 64, 4, false, false)
+// the matrix-phase wave at raised issue priority; global loads issued first
+SAGE_GGEMM6(ggemm6p_bf16_256x256, 256, 256, 128, 64, 4, true, false)
+SAGE_GGEMM6(ggemm6l_bf16_256x256, 256, 256, 128, 64, 4, false, true)
+SAGE_GGEMM6(ggemm6pl_bf16_256x256, 256, 256, 128, 64, 4, true, true)
+SAGE_GGEMM6(ggemm6s3_bf16_256x256, 256, 256, 128, 64, 3, false, false)
 
 // direct-to-LDS ring + fragment double-buffering
 #define SAGE_GGEMM5(BM, BN, WM, WN, S)                                                                \

@@ -154,7 +154,8 @@ class Pool {
   uint32_t lru_front() const { return lru_head_; }
   uint32_t chain_head(uint64_t fp) const { return index_.find(fp); }
   uint32_t new_mark() { return ++mark_; }
-  bool by_seq(uint32_t a, uint32_t b) const { return cls[a].seq < cls[b].seq; }
+  // Sort class ids by creation order (LSD radix on the sequence numbers).
+  void sort_by_seq(std::vector<uint32_t>& ids) const;
 
   std::vector<Class> cls;
   uint64_t budget = 0, used_ = 0, evictions = 0, epoch = 0, live_classes = 0;

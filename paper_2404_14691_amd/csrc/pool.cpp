@@ -203,4 +203,21 @@ void Pool::drop_class(uint32_t c) {
   free_cls_.push_back(c);
 }
 
+void Pool::sort_by_seq(std::vector<uint32_t>& ids) const {
+  std::vector<std::pair<uint64_t, uint32_t>> a(ids.size()), b(ids.size());
+  uint64_t mx = 0;
+  for (size_t i = 0; i < ids.size(); i++) {
+    a[i] = {cls[ids[i]].seq, ids[i]};
+    mx = std::max(mx, a[i].first);
+  }
+  for (unsigned shift = 0; shift < 64 && (mx >> shift) != 0; shift += 8) {
+    size_t cnt[257] = {0};
+    for (const auto& e : a) cnt[((e.first >> shift) & 255) + 1]++;
+    for (int k = 0; k < 256; k++) cnt[k + 1] += cnt[k];
+    for (const auto& e : a) b[cnt[(e.first >> shift) & 255]++] = e;
+    a.swap(b);
+  }
+  for (size_t i = 0; i < ids.size(); i++) ids[i] = a[i].second;
+}
+
 }  // namespace sage

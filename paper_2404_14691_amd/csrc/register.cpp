@@ -399,7 +399,7 @@ void register_shared(Ctx& c, Fn& f) {
       P.cls[cl].mark = dmark;
       f.distinct.push_back(cl);
     }
-  std::sort(f.distinct.begin(), f.distinct.end(), [&](uint32_t a, uint32_t b) { return P.by_seq(a, b); });
+  P.sort_by_seq(f.distinct);
   for (uint32_t cl : f.distinct)
     if (P.cls[cl].active == 0) P.lru_back(cl);
   c.h2d += f.ro_bytes;

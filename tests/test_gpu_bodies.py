@@ -94,7 +94,8 @@ TILES = ["ggemm_bf16_16x64", "ggemm_bf16_32x64", "ggemm_bf16_32x128", "ggemm_bf1
          "ggemm3_bf16_256x128", "ggemm5_bf16_256x128", "ggemm5_bf16_256x256",
          "ggemm3s5_bf16_256x256", "ggemm3w16_bf16_256x256", "ggemm3w16s5_bf16_256x256",
          "ggemm3_bf16_16x64", "ggemm3_bf16_32x64", "ggemm3_bf16_64x64", "ggemm3_bf16_128x64",
-         "ggemm6_bf16_256x256", "ggemm6s5_bf16_256x256", "ggemm6_bf16_256x128",
+         "ggemm6_bf16_256x256", "ggemm6s5_bf16_256x256", "ggemm6_bf16_256x128", "ggemm6p_bf16_256x256",
+         "ggemm6l_bf16_256x256", "ggemm6pl_bf16_256x256", "ggemm6s3_bf16_256x256",
          "ggemm3g4_bf16_16x64", "ggemm3g4_bf16_32x64", "ggemm3g4_bf16_64x64", "ggemm3g4_bf16_128x64",
          "ggemm3g2_bf16_256x256", "ggemm3t_bf16_16x16", "ggemm3t_bf16_16x32", "ggemm3t_bf16_32x32",
          # a large shape over full row tiles + a thin shape over the ragged last ones
