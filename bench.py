@@ -300,7 +300,14 @@ def cpu_baseline(wl, inv_per_fn=32):
         cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
         cores = os.cpu_count() or 1
+    cpu = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": len(wl.requests) / step_s, "unit": "invocations/s", "cores": int(cores), "kind": "oracle",
+            "nproc": os.cpu_count(), "cpu_model": cpu, "blas_threads": int(cores),
             "sample": f"fingerprints + cross-function dedup map of all {wl.n_fns} functions (4 x 256 MiB) and "
                       f"{n_inv} of the {len(wl.requests)} invocations ({inv_per_fn} per function) in float64 "
                       f"numpy, {t_reg + t_inv:.1f} s measured; step = registrations + "

@@ -101,7 +101,8 @@ TILES = ["ggemm_bf16_16x64", "ggemm_bf16_32x64", "ggemm_bf16_32x128", "ggemm_bf1
          # a large shape over full row tiles + a thin shape over the ragged last ones
          "ggemm3_bf16_256x256+ggemm3_bf16_64x64", "ggemm3w16_bf16_256x256+ggemm3_bf16_16x64",
          "ggemm5_bf16_256x128+ggemm3_bf16_32x64", "ggemm6_bf16_256x256+ggemm3_bf16_64x64",
-         "ggemm6_bf16_256x256+ggemm3g4_bf16_16x64", "ggemm6_bf16_256x256+ggemm3t_bf16_16x32"]
+         "ggemm6_bf16_256x256+ggemm3g4_bf16_16x64", "ggemm6_bf16_256x256+ggemm3t_bf16_16x32",
+         "ggemm6p_bf16_256x256+ggemm3t_bf16_32x32"]
 
 
 def test_bf16_every_tile_shape_same_bits(sage_ctx_factory, torch_cuda, monkeypatch):
