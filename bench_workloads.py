@@ -334,4 +334,80 @@ def serving(S, torch, log, rates=(200, 500, 1000, 2000), duration=3.0, budget_fr
                  "bf16", rates=results)
 
 
-WORKLOADS = {"batching": batching, "stencil": stencil, "mlp_f32": mlp_f32, "serving": serving}
+# ---------------------------------------------------------------- exit stages
+def exit_stages(S, torch, log, interval_ms=300.0, reps=3, batch=8):
+    """Table 4 analogue: setup + invoke latency of one BF16 MLP (8 x 4096^2,
+    256 MiB in pageable host memory) in each multi-stage exit stage and cold
+    (a new context: code object, registration and all).  The stage is applied
+    (sage_tick) before each timed call, as the paper's exit runs in the
+    background."""
+    from paper_2404_14691_amd import synth
+    W, L = 4096, 8
+    w = synth.shared_mlp_bf16_functions(n_fns=1, layers=L, width=W, share_frac=0.0, seed=5)
+    blob = w.blobs[0]
+    desc = S.mlp_desc(S.SAGE_MLP_BF16, L, W)
+    x = synth.bf16_inputs(batch, W, 5, 0)
+    y = np.zeros((batch, W), dtype=np.float32)
+    keys = ("t_module_ms", "t_reload_ms", "t_setup_ms", "t_invoke_ms")
+
+    def one(ctx, fn):
+        st0 = S.sage_get_stats(ctx)
+        t0 = time.perf_counter()
+        inv = S.fn_setup(ctx, fn, batch)
+        S.fn_invoke(ctx, inv, x, y)
+        S.fn_release(ctx, inv)
+        e2e = (time.perf_counter() - t0) * 1e3
+        st1 = S.sage_get_stats(ctx)
+        return e2e, {k: st1[k] - st0[k] for k in keys}, time.monotonic()
+
+    def cfg(serial=0):
+        c = S.sage_config_default()
+        c.pool_budget_bytes = 2 << 30
+        c.exit_stage_ms = interval_ms
+        c.serial_setup = serial
+        return c
+
+    rows = {k: [] for k in ("stage1", "stage2", "stage3", "stage4", "cold", "cold_serial")}
+    parts = {k: [] for k in rows}
+    def cold(serial):
+        t0 = time.perf_counter()
+        c = S.sage_open(0, cfg(serial))
+        f = S.fn_register(c, desc, [S.make_blob(blob)])
+        inv = S.fn_setup(c, f, batch)
+        S.fn_invoke(c, inv, x, y)
+        S.fn_release(c, inv)
+        return (time.perf_counter() - t0) * 1e3, c, f
+
+    for r in range(reps):
+        ms, c2, f2 = cold(1)
+        rows["cold_serial"].append(ms)
+        S.fn_unregister(c2, f2)
+        S.sage_close(c2)
+        ms, ctx, fn = cold(0)  # this context and function stay for the warm stages
+        rows["cold"].append(ms)
+        _, _, t_rel = one(ctx, fn)
+        for k, idle in (("stage1", 0.3), ("stage2", 1.3), ("stage3", 2.3), ("stage4", 3.3)):
+            dt = t_rel + idle * interval_ms / 1e3 - time.monotonic()
+            if dt > 0:
+                time.sleep(dt)
+            S.sage_tick(ctx)
+            e2e, br, t_rel = one(ctx, fn)
+            rows[k].append(e2e)
+            parts[k].append(br)
+        S.fn_unregister(ctx, fn)
+        S.sage_close(ctx)
+        log(f"exit stages rep {r}: " + ", ".join(f"{k} {v[-1]:.2f} ms" for k, v in rows.items()))
+    med = {k: float(np.median(v)) for k, v in rows.items()}
+    breakdown = {k: {kk: round(float(np.median([p[kk] for p in parts[k]])), 3) for kk in keys}
+                 for k in ("stage1", "stage2", "stage3", "stage4")}
+    gain = float(np.mean([med["cold"] / med[k] for k in ("stage1", "stage2", "stage3", "stage4")]))
+    return _line("setup+invoke latency per multi-stage exit stage vs cold (Table 4 analogue), 1 MI355X", gain,
+                 "x mean speedup of stages 1-4 over cold", reps, 0, med["stage1"],
+                 {"workload": "exit stages: 1 BF16 MLP 8 x 4096^2 (256 MiB, pageable host source), batch 8, host "
+                              f"I/O, stage interval {interval_ms:.0f} ms; cold = new context + code object + "
+                              "registration + first invocation"},
+                 "bf16", e2e_ms={k: round(v, 3) for k, v in med.items()}, breakdown_ms=breakdown)
+
+
+WORKLOADS = {"batching": batching, "stencil": stencil, "mlp_f32": mlp_f32, "serving": serving,
+             "exit_stages": exit_stages}

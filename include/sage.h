@@ -112,6 +112,14 @@ typedef struct {
   uint32_t serial_setup;     /* 1: load code and move data one after the other (A/B switch) */
   size_t pool_budget_bytes;  /* pool capacity; 0 = half of free device memory at open */
   const char* tune_cache;    /* autotuner cache file, or NULL for in-memory only */
+  /* Multi-stage exit (section "Multi-stage Resource Exit"), interval T in ms
+   * (0 = off: unreferenced blocks stay in HBM until evicted, code objects stay
+   * loaded).  A block unreferenced for T moves to a pinned host cache; a code
+   * object none of whose functions was set up or released for 2 T is
+   * unloaded; a host copy unreferenced for 3 T is dropped (the function's
+   * source remains).  Later setups reload from where the bytes are. */
+  double exit_stage_ms;
+  size_t host_cache_bytes;   /* host-cache budget for demoted blocks; 0 = no limit */
 } sage_config;
 
 typedef struct {
@@ -140,6 +148,14 @@ typedef struct {
   double t_verify_ms;       /* data branch: COPY/VERIFY launches and their results */
   double t_setup_ms;        /* fn_setup calls (admission, reloads, references) */
   double t_invoke_ms;       /* fn_invoke / fn_invoke_batch calls */
+  /* multi-stage exit */
+  uint64_t host_cached_bytes; /* pinned host bytes holding demoted blocks */
+  uint64_t demotions;       /* classes moved from HBM to the host cache */
+  uint64_t host_reloads;    /* classes reloaded from the host cache */
+  uint64_t module_loads;    /* code objects loaded (first load included) */
+  uint64_t module_unloads;  /* code objects unloaded by the multi-stage exit */
+  double t_module_ms;       /* host wall time in code-object loads */
+  double t_reload_ms;       /* host wall time in fn_setup reloads of missing blocks */
 } sage_stats;
 
 /* ----------------------------------------------------------------- context */
@@ -181,6 +197,10 @@ sage_status fn_register(sage_ctx* ctx, const sage_fn_desc* desc, const sage_blob
  * registered function uses leave the pool.  Returns after every copy that
  * reads the function's sources has finished: the caller may free them. */
 sage_status fn_unregister(sage_ctx* ctx, sage_fn fn);
+
+/* Apply the multi-stage exit now (it is also applied at the start of
+ * fn_register, fn_setup and sage_get_stats, and by the serving loop). */
+sage_status sage_tick(sage_ctx* ctx);
 
 /* Make one invocation of `fn` with `batch` rows (MLP) or fields (stencil)
  * runnable; the analogue of SageLoadToGPU() (section "Programming of

@@ -31,7 +31,7 @@ def hipcc() -> str:
 # packed FP32 instructions are disabled for every device compile
 DEVICE_FLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17",
                 "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-HOST_SOURCES = ["sage_api.cpp", "register.cpp", "exec.cpp", "pool.cpp", "util.cpp", "serve.cpp"]
+HOST_SOURCES = ["sage_api.cpp", "register.cpp", "exec.cpp", "pool.cpp", "util.cpp", "serve.cpp", "exit.cpp"]
 
 
 def _run(cmd):

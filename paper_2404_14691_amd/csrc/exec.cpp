@@ -110,6 +110,13 @@ static void drop_graphs(Flight& F) {
   F.graphs.clear();
 }
 
+void flights_drop_graphs(Ctx& c) {
+  for (size_t i = 0; i < c.flights.size(); i++) {
+    finish_flight(c, (int)i);
+    drop_graphs(c.flights[i]);
+  }
+}
+
 void flights_destroy(Ctx& c) {
   for (Flight& F : c.flights) {
     (void)hipStreamSynchronize(F.s);

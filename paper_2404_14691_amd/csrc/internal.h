@@ -115,6 +115,17 @@ struct Class {
   bool in_lru = false;
   bool indexed = false;
   const uint8_t* pending = nullptr;  // device bytes of its first block while its chunk is in flight
+  double idle_since = 0;      // when it last became unreferenced (host ms)
+  uint32_t hbuf = kNone;      // host-cache buffer holding its bytes after demotion, or kNone
+  uint32_t hoff = 0;          // block index inside that buffer
+  uint64_t hgen = 0;          // demotion number of its current host copy
+};
+
+// Pinned host buffer of the host cache: blocks demoted together.
+struct HostBuf {
+  uint8_t* p = nullptr;
+  uint32_t blocks = 0;
+  uint32_t live = 0;  // classes still holding a block of it
 };
 
 // Open-addressing map fingerprint -> first class of its chain.
@@ -146,7 +157,7 @@ class Pool {
   void free_slot(uint32_t s) { free_.push_back(s); used_--; }
   uint32_t new_class(uint64_t fp, uint32_t len);
   void drop_class(uint32_t c);          // dead class: slot freed, index entry removed, storage recycled
-  void evict(uint32_t c);
+  void evict(uint32_t c, bool demotion = false);  // demotion: counted as such, not as an eviction
   void index_add(uint32_t c);           // append to the end of its fingerprint chain
   void index_remove(uint32_t c);
   void lru_back(uint32_t c);
@@ -156,9 +167,16 @@ class Pool {
   uint32_t new_mark() { return ++mark_; }
   // Sort class ids by creation order (LSD radix on the sequence numbers).
   void sort_by_seq(std::vector<uint32_t>& ids) const;
+  // Host cache: a new buffer for `blocks` demoted blocks (kNone if the
+  // budget or the allocation fails), and dropping one class's host copy.
+  uint32_t host_buffer(uint32_t blocks, uint64_t budget_bytes);
+  void host_release(uint32_t c);
 
   std::vector<Class> cls;
   uint64_t budget = 0, used_ = 0, evictions = 0, epoch = 0, live_classes = 0;
+  std::vector<HostBuf> hbufs;
+  std::deque<std::pair<uint32_t, uint64_t>> host_lru;  // (class, demotion number), in demotion order
+  uint64_t host_bytes = 0, demotions = 0;
 
  private:
   bool grow_arena();
@@ -166,6 +184,7 @@ class Pool {
   size_t seg_slots_ = 16384;
   std::vector<uint32_t> free_;
   std::vector<uint32_t> free_cls_;
+  std::vector<uint32_t> free_hbufs_;
   FpIndex index_;
   uint32_t lru_head_ = kNone, lru_tail_ = kNone;
   uint32_t mark_ = 0;
@@ -189,9 +208,15 @@ uint32_t Pool::alloc_slot(const Protect& protect) {
 }
 
 // --------------------------------------------------------------- modules
+// A code object.  The record lives as long as the context; the loaded
+// module may be unloaded by the multi-stage exit and is loaded again by the
+// next setup that needs it.
 struct Module {
   hipModule_t mod = nullptr;
   std::map<std::string, hipFunction_t> fn;
+  std::string path;
+  int key = 0;
+  double last_use = 0;  // host ms of the last setup or release of one of its functions
   hipFunction_t get(const char* name);
 };
 
@@ -329,11 +354,16 @@ struct Ctx {
   std::map<void*, size_t> pinned;            // sage_host_alloc ranges
   uint64_t* h_stage = nullptr;               // pinned staging for block-table uploads
   hipEvent_t stage_ev = nullptr;             // last upload from h_stage (on ctl)
+  hipEvent_t ctl_ev = nullptr;               // marks the control stream for other streams to wait on
   size_t h_stage_cap = 0;
   std::map<std::string, TuneEntry> tune;     // "width:shape" -> time of one full wave of tiles (ms)
   // counters
   uint64_t logical = 0, h2d = 0, reloads = 0, registrations = 0, invocations = 0, mismatches = 0;
   double t_register = 0, t_code = 0, t_fp_wait = 0, t_dedup = 0, t_verify = 0, t_setup = 0, t_invoke = 0;
+  uint64_t host_reloads = 0, module_unloads = 0;
+  double t_reload = 0;
+  uint64_t module_loads = 0;                 // under module_mu
+  double t_module = 0;                       // under module_mu
   Serve* serve = nullptr;                    // running serving loop, if any
   Worker worker;                             // code branch of fn_register
   std::string force_tile;                    // SAGE_TILE: fixed GEMM tile shape (tests)
@@ -356,7 +386,10 @@ void fill_parallel(Ctx& c, uint8_t* dst, const uint8_t* src, size_t n);
 void run_two_branches(const std::function<void()>& code, const std::function<void()>& data, bool serial,
                       Worker* w = nullptr);
 
-Module* load_module(Ctx& c, int kind);
+Module* load_module(Ctx& c, int kind);     // loads (again) if not loaded
+void unload_module(Ctx& c, Module& m);
+void advance_exit(Ctx& c);                 // multi-stage exit of idle data and code
+void flights_drop_graphs(Ctx& c);          // finish every flight and drop its captured graphs
 void register_shared(Ctx& c, Fn& f);
 void copy_private(Ctx& c, Fn& f, uint8_t* dst, hipStream_t s);
 void reload_classes(Ctx& c, Fn& f, const std::vector<uint32_t>& missing);

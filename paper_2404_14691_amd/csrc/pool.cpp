@@ -82,6 +82,12 @@ void Pool::init(uint64_t budget_slots, size_t seg_slots) {
 
 void Pool::destroy() {
   for (uint8_t* s : segs_) (void)hipFree(s);
+  for (HostBuf& h : hbufs)
+    if (h.p) (void)hipHostFree(h.p);
+  hbufs.clear();
+  free_hbufs_.clear();
+  host_lru.clear();
+  host_bytes = 0;
   segs_.clear();
   free_.clear();
   free_cls_.clear();
@@ -174,9 +180,10 @@ void Pool::lru_back(uint32_t c) {
   else lru_head_ = c;
   lru_tail_ = c;
   k.in_lru = true;
+  k.idle_since = now_ms();
 }
 
-void Pool::evict(uint32_t c) {
+void Pool::evict(uint32_t c, bool demotion) {
   Class& k = cls[c];
   lru_remove(c);
   index_remove(c);
@@ -184,7 +191,8 @@ void Pool::evict(uint32_t c) {
     free_slot(k.slot);
     k.slot = kNone;
   }
-  evictions++;
+  if (demotion) demotions++;
+  else evictions++;
   epoch++;
 }
 
@@ -197,10 +205,46 @@ void Pool::drop_class(uint32_t c) {
     free_slot(k.slot);
     k.slot = kNone;
   }
+  host_release(c);
   k.alive = false;
   k.pending = nullptr;
   live_classes--;
   free_cls_.push_back(c);
+}
+
+uint32_t Pool::host_buffer(uint32_t blocks, uint64_t budget_bytes) {
+  const uint64_t bytes = (uint64_t)blocks * kBlock;
+  if (budget_bytes && host_bytes + bytes > budget_bytes) return kNone;
+  uint8_t* p = nullptr;
+  if (hipHostMalloc((void**)&p, bytes, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return kNone;
+  }
+  uint32_t h;
+  if (!free_hbufs_.empty()) {
+    h = free_hbufs_.back();
+    free_hbufs_.pop_back();
+  } else {
+    hbufs.emplace_back();
+    h = (uint32_t)hbufs.size() - 1;
+  }
+  hbufs[h] = HostBuf{p, blocks, 0};
+  host_bytes += bytes;
+  return h;
+}
+
+void Pool::host_release(uint32_t c) {
+  Class& k = cls[c];
+  if (k.hbuf == kNone) return;
+  HostBuf& h = hbufs[k.hbuf];
+  if (--h.live == 0) {
+    (void)hipHostFree(h.p);
+    host_bytes -= (uint64_t)h.blocks * kBlock;
+    h = HostBuf{};
+    free_hbufs_.push_back(k.hbuf);
+  }
+  k.hbuf = kNone;
+  k.hoff = 0;
 }
 
 void Pool::sort_by_seq(std::vector<uint32_t>& ids) const {

@@ -139,6 +139,7 @@ static std::string lib_dir() {
 hipFunction_t Module::get(const char* name) {
   auto it = fn.find(name);
   if (it != fn.end()) return it->second;
+  if (!mod) fail(SAGE_ESTATE, "code object %s is not loaded", path.c_str());
   hipFunction_t f = nullptr;
   const hipError_t e = hipModuleGetFunction(&f, mod, name);
   if (e != hipSuccess) {
@@ -154,15 +155,21 @@ hipFunction_t Module::get(const char* name) {
 Module* load_module(Ctx& c, int kind) {
   std::lock_guard<std::mutex> lk(c.module_mu);
   const int key = kind == SAGE_STENCIL7_F32 ? SAGE_STENCIL7_F32 : SAGE_MLP_BF16;
-  auto it = c.modules.find(key);
-  if (it != c.modules.end()) return it->second.get();
+  std::unique_ptr<Module>& slot = c.modules[key];
+  if (!slot) {
+    slot = std::make_unique<Module>();
+    slot->key = key;
+    slot->path = lib_dir() + (key == SAGE_STENCIL7_F32 ? "/sage_stencil.hsaco" : "/sage_mlp.hsaco");
+  }
+  Module* m = slot.get();
+  if (m->mod) return m;
+  const double t0 = now_ms();
   HIPX(hipSetDevice(c.device));
-  const std::string path = lib_dir() + (key == SAGE_STENCIL7_F32 ? "/sage_stencil.hsaco" : "/sage_mlp.hsaco");
-  auto m = std::make_unique<Module>();
-  const hipError_t e = hipModuleLoad(&m->mod, path.c_str());
+  const hipError_t e = hipModuleLoad(&m->mod, m->path.c_str());
   if (e != hipSuccess) {
     (void)hipGetLastError();
-    fail(SAGE_EIO, "hipModuleLoad(%s): %s", path.c_str(), hipGetErrorString(e));
+    m->mod = nullptr;
+    fail(SAGE_EIO, "hipModuleLoad(%s): %s", m->path.c_str(), hipGetErrorString(e));
   }
   if (key == SAGE_STENCIL7_F32) {
     m->get("stencil7_sweep2");
@@ -170,9 +177,10 @@ Module* load_module(Ctx& c, int kind) {
     m->get("mlp_f32_layer");
     m->get("ggemm_bf16_128x128");
   }
-  Module* raw = m.get();
-  c.modules[key] = std::move(m);
-  return raw;
+  m->last_use = now_ms();
+  c.module_loads++;
+  c.t_module += now_ms() - t0;
+  return m;
 }
 
 // --------------------------------------------------------------- blocks
@@ -439,11 +447,13 @@ void copy_private(Ctx& c, Fn& f, uint8_t* dst, hipStream_t s) {
 }
 
 // ------------------------------------------------------------ reloads
-// Bring evicted classes of `f` back: each class is copied from the source
-// block of `f` that first referenced it (the source is read-only and was
-// verified equal at registration).  Slots must already be available.
+// Bring evicted classes of `f` back: a demoted class from its host-cache
+// copy, any other from the source block of `f` that first referenced it (the
+// source is read-only and was verified equal at registration).  Pinned host
+// bytes reach the device staging buffer in one DMA per contiguous run.
 void reload_classes(Ctx& c, Fn& f, const std::vector<uint32_t>& missing) {
   if (missing.empty()) return;
+  const double t_start = now_ms();
   Pool& P = c.pool;
   Ring& R = c.ring;
   std::unordered_map<uint32_t, uint32_t> first;
@@ -451,41 +461,79 @@ void reload_classes(Ctx& c, Fn& f, const std::vector<uint32_t>& missing) {
   const uint32_t mark = P.new_mark();
   for (uint32_t cl : f.distinct) P.cls[cl].mark = mark;
   auto protect = [&](uint32_t cl) { return P.cls[cl].mark == mark; };
-  const size_t per_slot = R.chunk / kBlock;
-  hipStream_t s = c.ctl;  // behind in-flight registration copies
-  HIPX(hipEventSynchronize(R.ev_c[0]));  // slot 0's last COPY has read its staging and op buffers
-  size_t i = 0;
+  // Batches go round the staging ring on the copy streams, so staging of one
+  // overlaps the copies of the others.  Every stream first waits for the
+  // control stream: a freed slot may still be the target of a registration
+  // copy in flight there.
+  HIPX(hipEventRecord(c.ctl_ev, c.ctl));
+  for (size_t k = 0; k < R.slots; k++) HIPX(hipEventSynchronize(R.ev_c[k]));
+  for (hipStream_t cs : c.streams) HIPX(hipStreamWaitEvent(cs, c.ctl_ev, 0));
+  size_t i = 0, batch = 0;
+  std::vector<uint32_t> from_host;
   while (i < missing.size()) {
-    BlkOp* ops = R.hops[0];
+    const int slot = (int)(batch % R.slots);
+    hipStream_t s = c.streams[slot % c.streams.size()];
+    if (batch >= R.slots) HIPX(hipEventSynchronize(R.ev[slot]));  // the slot's previous batch is done
+    batch++;
+    const size_t per_slot = std::min<size_t>(R.chunk / kBlock, R.cap[slot]);
+    BlkOp* ops = R.hops[slot];
     uint32_t nops = 0;
     size_t staged = 0;
+    // runs of contiguous pinned host blocks reach the staging buffer in one DMA each
+    const uint8_t* run_src = nullptr;
+    size_t run_at = 0, run_n = 0;
+    auto flush_run = [&] {
+      if (run_n)
+        HIPX(hipMemcpyAsync(R.dev[slot] + run_at * kBlock, run_src, run_n * kBlock, hipMemcpyHostToDevice, s));
+      run_n = 0;
+    };
     while (i < missing.size() && nops < per_slot) {
       const uint32_t cl = missing[i++];
-      const uint32_t b = first.at(cl);
-      bool dev = false;
-      const uint8_t* src = f.block_src(b, &dev);
-      const uint32_t len = P.cls[cl].len;
+      Class& k = P.cls[cl];
+      const uint32_t len = k.len;
       const uint32_t slotid = P.alloc_slot(protect);
       if (slotid == kNone) fail(SAGE_ENOMEM, "pool full during reload");
-      P.cls[cl].slot = slotid;
+      k.slot = slotid;
       P.index_add(cl);
-      if (dev) {
-        ops[nops++] = BlkOp{(uint64_t)src, (uint64_t)P.addr(slotid), len, 0};
+      bool dev = false;
+      const uint8_t* hsrc = nullptr;  // pinned host bytes to stage, if any
+      if (k.hbuf != kNone) {
+        // the bytes wait in the pinned host cache (second or third stage)
+        hsrc = P.hbufs[k.hbuf].p + (uint64_t)k.hoff * kBlock;
+        from_host.push_back(cl);
+        c.host_reloads++;
       } else {
-        std::memcpy(R.host[0] + staged * kBlock, src, len);
-        ops[nops++] = BlkOp{(uint64_t)(R.dev[0] + staged * kBlock), (uint64_t)P.addr(slotid), len, 0};
+        const uint8_t* src = f.block_src(first.at(cl), &dev);
+        if (dev) {
+          ops[nops++] = BlkOp{(uint64_t)src, (uint64_t)P.addr(slotid), len, 0};
+        } else {
+          std::memcpy(R.host[slot] + staged * kBlock, src, len);
+          hsrc = R.host[slot] + staged * kBlock;
+        }
+      }
+      if (hsrc) {
+        if (!(run_n && hsrc == run_src + run_n * kBlock)) {
+          flush_run();
+          run_src = hsrc;
+          run_at = staged;
+        }
+        run_n++;
+        ops[nops++] = BlkOp{(uint64_t)(R.dev[slot] + staged * kBlock), (uint64_t)P.addr(slotid), len, 0};
         staged++;
       }
       c.h2d += len;
       c.reloads++;
     }
-    if (staged) HIPX(hipMemcpyAsync(R.dev[0], R.host[0], staged * kBlock, hipMemcpyHostToDevice, s));
-    HIPX(hipMemcpyAsync(R.dops[0], ops, nops * sizeof(BlkOp), hipMemcpyHostToDevice, s));
+    flush_run();
+    HIPX(hipMemcpyAsync(R.dops[slot], ops, nops * sizeof(BlkOp), hipMemcpyHostToDevice, s));
     const int tok = c.timer.start("blkcopy", s, 1);
-    HIPX(launch_blkcopy(R.dops[0], nops, R.dres[0], c.max_groups_copy(), s));
+    HIPX(launch_blkcopy(R.dops[slot], nops, R.dres[slot], c.max_groups_copy(), s));
     c.timer.stop(tok, s);
-    HIPX(hipStreamSynchronize(s));
+    HIPX(hipEventRecord(R.ev[slot], s));
   }
+  for (hipStream_t cs : c.streams) HIPX(hipStreamSynchronize(cs));
+  for (uint32_t cl : from_host) P.host_release(cl);  // back in HBM: the host copy goes
+  c.t_reload += now_ms() - t_start;
 }
 
 // Rebuild the device block table of `f` when any of its classes moved.

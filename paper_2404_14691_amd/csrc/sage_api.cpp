@@ -88,7 +88,11 @@ namespace sage {
 uint64_t setup_internal(Ctx& c, uint64_t id, uint32_t batch) {
   if (batch < 1) fail(SAGE_EINVAL, "batch must be >= 1");
   HIPX(hipSetDevice(c.device));
+  advance_exit(c);
   Fn& f = fn_of(c, id);
+  // after the third exit stage the code object is loaded again, beside the data
+  auto code = [&] { load_module(c, f.d.kind); };
+  const bool need_code = f.mod && !f.mod->mod;
   auto v = std::make_unique<Inv>();
   v->id = c.next_id++;
   v->fn = &f;
@@ -114,7 +118,10 @@ uint64_t setup_internal(Ctx& c, uint64_t id, uint32_t batch) {
                (unsigned long long)(free_slots + victims.size()));
         for (uint32_t cl : victims) P.evict(cl);
       }
-      reload_classes(c, f, missing);
+      if (need_code) run_two_branches(code, [&] { reload_classes(c, f, missing); }, c.cfg.serial_setup != 0, &c.worker);
+      else reload_classes(c, f, missing);
+    } else if (need_code) {
+      code();
     }
     refresh_table(c, f);
     f.resident_epoch = P.epoch;
@@ -122,6 +129,7 @@ uint64_t setup_internal(Ctx& c, uint64_t id, uint32_t batch) {
       for (uint32_t cl : f.distinct)
         if (P.cls[cl].active++ == 0) P.lru_remove(cl);
   } else {
+    if (need_code) code();
     // private copy of the read-only data for this invocation
     const size_t bytes = (size_t)f.n_blocks * kBlock;
     v->priv = c.cache.get(bytes);
@@ -139,6 +147,7 @@ uint64_t setup_internal(Ctx& c, uint64_t id, uint32_t batch) {
   }
   v->live = true;
   f.live++;
+  if (f.mod) f.mod->last_use = now_ms();
   const uint64_t out = v->id;
   c.invs[v->id] = std::move(v);
   return out;
@@ -159,6 +168,7 @@ void release_internal(Ctx& c, uint64_t id) {
   free_inv_buffers(c, v);
   v.live = false;
   f.live--;
+  if (f.live == 0 && f.mod) f.mod->last_use = now_ms();
   c.invs.erase(id);
 }
 
@@ -206,6 +216,7 @@ sage_status sage_open(int device, const sage_config* cfg, sage_ctx** out) {
     else sage_config_default(&c.cfg);
     if (c.cfg.ring_slots < 1 || c.cfg.chunk_bytes < kBlock || c.cfg.chunk_bytes % kBlock || c.cfg.streams < 1)
       fail(SAGE_EINVAL, "ring_slots >= 1, streams >= 1, chunk_bytes a multiple of 64 KiB");
+    if (!(c.cfg.exit_stage_ms >= 0)) fail(SAGE_EINVAL, "exit_stage_ms must be >= 0");
     int ndev = 0;
     HIPX(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) fail(SAGE_EINVAL, "device %d not present (%d devices)", device, ndev);
@@ -215,6 +226,7 @@ sage_status sage_open(int device, const sage_config* cfg, sage_ctx** out) {
     c.cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     HIPX(hipStreamCreateWithFlags(&c.ctl, hipStreamNonBlocking));
     HIPX(hipEventCreateWithFlags(&c.stage_ev, hipEventDisableTiming));
+    HIPX(hipEventCreateWithFlags(&c.ctl_ev, hipEventDisableTiming));
     for (uint32_t i = 0; i < c.cfg.streams; i++) {
       hipStream_t s;
       HIPX(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
@@ -256,13 +268,15 @@ sage_status sage_close(sage_ctx* p) {
       c.cache.release_all();
       c.pool.destroy();
       ring_destroy(c);
-      for (auto& kv : c.modules) (void)hipModuleUnload(kv.second->mod);
+      for (auto& kv : c.modules)
+        if (kv.second->mod) (void)hipModuleUnload(kv.second->mod);
       c.modules.clear();
       for (auto& kv : c.pinned) (void)hipHostFree(kv.first);
       c.pinned.clear();
       if (c.h_stage) (void)hipHostFree(c.h_stage);
       c.h_stage = nullptr;
       if (c.stage_ev) (void)hipEventDestroy(c.stage_ev);
+      if (c.ctl_ev) (void)hipEventDestroy(c.ctl_ev);
       c.timer.destroy();
       for (hipStream_t s : c.streams) (void)hipStreamDestroy(s);
       (void)hipStreamDestroy(c.ctl);
@@ -303,6 +317,7 @@ sage_status fn_register(sage_ctx* p, const sage_fn_desc* desc, const sage_blob* 
     const double t_start = now_ms();
     HIPX(hipSetDevice(c.device));
     validate(*desc, blobs, n_blobs);
+    advance_exit(c);
     auto f = std::make_unique<Fn>();
     f->id = c.next_id++;
     f->d = *desc;
@@ -484,6 +499,8 @@ sage_status sage_get_stats(sage_ctx* p, sage_stats* out) {
     Ctx& c = ctx_of(p);
     if (!out) fail(SAGE_EINVAL, "null output");
     std::lock_guard<std::recursive_mutex> lk(c.mu);
+    HIPX(hipSetDevice(c.device));
+    advance_exit(c);
     std::memset(out, 0, sizeof *out);
     const Pool& P = c.pool;
     for (const Class& k : P.cls) {
@@ -515,6 +532,16 @@ sage_status sage_get_stats(sage_ctx* p, sage_stats* out) {
     out->t_verify_ms = c.t_verify;
     out->t_setup_ms = c.t_setup;
     out->t_invoke_ms = c.t_invoke;
+    out->host_cached_bytes = P.host_bytes;
+    out->demotions = P.demotions;
+    out->host_reloads = c.host_reloads;
+    out->module_unloads = c.module_unloads;
+    out->t_reload_ms = c.t_reload;
+    {
+      std::lock_guard<std::mutex> mk(c.module_mu);
+      out->module_loads = c.module_loads;
+      out->t_module_ms = c.t_module;
+    }
   });
 }
 
@@ -628,6 +655,15 @@ sage_status sage_timing_reset(sage_ctx* p) {
     Ctx& c = ctx_of(p);
     std::lock_guard<std::recursive_mutex> lk(c.mu);
     c.timer.reset();
+  });
+}
+
+sage_status sage_tick(sage_ctx* p) {
+  return guard([&] {
+    Ctx& c = ctx_of(p);
+    std::lock_guard<std::recursive_mutex> lk(c.mu);
+    HIPX(hipSetDevice(c.device));
+    advance_exit(c);
   });
 }
 

@@ -56,7 +56,7 @@ class sage_config(C.Structure):
     _fields_ = [("ring_slots", C.c_size_t), ("chunk_bytes", C.c_size_t), ("streams", C.c_uint32),
                 ("fill_threads", C.c_uint32), ("inflight_groups", C.c_uint32), ("share", C.c_uint32),
                 ("batch", C.c_uint32), ("serial_setup", C.c_uint32), ("pool_budget_bytes", C.c_size_t),
-                ("tune_cache", C.c_char_p)]
+                ("tune_cache", C.c_char_p), ("exit_stage_ms", C.c_double), ("host_cache_bytes", C.c_size_t)]
 
 
 class sage_stats(C.Structure):
@@ -65,7 +65,10 @@ class sage_stats(C.Structure):
         "resident_slots", "budget_slots", "classes", "h2d_bytes", "refcount_sum", "live_setups",
         "evictions", "reloads", "registrations", "invocations", "verify_mismatches", "workspace_bytes")] + \
         [(n, C.c_double) for n in ("t_register_ms", "t_code_ms", "t_fp_wait_ms", "t_dedup_ms", "t_verify_ms",
-                                   "t_setup_ms", "t_invoke_ms")]
+                                   "t_setup_ms", "t_invoke_ms")] + \
+        [(n, C.c_uint64) for n in ("host_cached_bytes", "demotions", "host_reloads", "module_loads",
+                                   "module_unloads")] + \
+        [(n, C.c_double) for n in ("t_module_ms", "t_reload_ms")]
 
     def as_dict(self) -> dict:
         return {n: (int(getattr(self, n)) if t is C.c_uint64 else float(getattr(self, n)))
@@ -125,6 +128,7 @@ _sigs = {
     "sage_timing_get": (C.c_int, [_P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]),
     "sage_timing_reset": (C.c_int, [_P]),
     "sage_last_launch": (C.c_int, [_P, C.c_char_p, C.c_size_t]),
+    "sage_tick": (C.c_int, [_P]),
     "sage_selftest_setup_overlap": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_int,
                                               C.POINTER(C.c_double)]),
     "sage_serve_start": (C.c_int, [_P, C.c_uint32]),
@@ -335,6 +339,10 @@ def sage_timing_get(ctx: int, kernel: str):
 
 def sage_timing_reset(ctx: int) -> None:
     _check(_lib.sage_timing_reset(ctx), "sage_timing_reset")
+
+
+def sage_tick(ctx: int) -> None:
+    _check(_lib.sage_tick(ctx), "sage_tick")
 
 
 def sage_last_launch(ctx: int) -> str:
