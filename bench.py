@@ -272,10 +272,11 @@ def host_link(S, torch, wl):
     return out
 
 
-def cpu_baseline(wl, inv_per_fn=32):
+def cpu_baseline(wl, min_s=10.0, max_inv=1024):
     """The oracle on the host: fingerprints and the cross-function dedup map
-    of all functions' blobs, then `inv_per_fn` invocations of each function
-    in float64; scaled to one step of the workload."""
+    of all functions' blobs, then invocations of the workload's requests in
+    order (each function's weights converted once) until at least `min_s`
+    seconds of invocation time and 64 invocations; scaled to one step."""
     from oracle import dedup as OD
     from oracle import fingerprint as OF
     from oracle import mlp as OM
@@ -284,16 +285,15 @@ def cpu_baseline(wl, inv_per_fn=32):
         OF.fp64k_blob(blob)
     OD.partition_dict(wl.host_blobs, 65536)
     t_reg = time.perf_counter() - t0
+    Ws = [OM.bf16_to_f64(b).reshape(wl.layers, wl.width, wl.width) for b in wl.host_blobs]
     t_inv, n_inv = 0.0, 0
-    for f, blob in enumerate(wl.host_blobs):
-        W = OM.bf16_to_f64(blob).reshape(wl.layers, wl.width, wl.width)
-        reqs = [r for r in wl.requests if r[0] == f][:inv_per_fn]
+    while n_inv < max_inv and (t_inv < min_s or n_inv < 64):
+        f, b, r = wl.requests[n_inv % len(wl.requests)]
         t0 = time.perf_counter()
-        for _, b, r in reqs:
-            OM.mlp_forward(OM.bf16_to_f64(wl.x_host[r:r + b]), W)
+        OM.mlp_forward(OM.bf16_to_f64(wl.x_host[r:r + b]), Ws[f])
         t_inv += time.perf_counter() - t0
-        n_inv += len(reqs)
-        del W
+        n_inv += 1
+    del Ws
     step_s = t_reg + len(wl.requests) * t_inv / n_inv
     try:
         from threadpoolctl import threadpool_info
@@ -308,17 +308,17 @@ def cpu_baseline(wl, inv_per_fn=32):
         pass
     return {"value": len(wl.requests) / step_s, "unit": "invocations/s", "cores": int(cores), "kind": "oracle",
             "nproc": os.cpu_count(), "cpu_model": cpu, "blas_threads": int(cores),
-            "sample": f"fingerprints + cross-function dedup map of all {wl.n_fns} functions (4 x 256 MiB) and "
-                      f"{n_inv} of the {len(wl.requests)} invocations ({inv_per_fn} per function) in float64 "
-                      f"numpy, {t_reg + t_inv:.1f} s measured; step = registrations + "
-                      f"{len(wl.requests)} x mean invocation ({step_s:.1f} s)"}
+            "sample": f"fingerprints + cross-function dedup map of all {wl.n_fns} functions (4 x 256 MiB, "
+                      f"{t_reg:.1f} s) and {n_inv} invocations of the workload's requests in order "
+                      f"({t_inv:.1f} s) in float64 numpy; step = registrations + {len(wl.requests)} x mean "
+                      f"invocation ({step_s:.1f} s)"}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-kernels", action="store_true", help="skip the standalone 4 GiB kernel bandwidth runs")

@@ -329,7 +329,7 @@ sage_status sage_timing_enable(sage_ctx* ctx, int on);
 sage_status sage_timing_get(sage_ctx* ctx, const char* kernel, double* total_ms, uint64_t* launches);
 sage_status sage_timing_reset(sage_ctx* ctx);
 /* Describe the last MLP body launch of this context as text, e.g.
- * "ggemm6_bf16_256x256:256+ggemm3g4_bf16_64x64:128" (kernel:tiles per layer;
+ * "ggemm6p_bf16_256x256:256+ggemm3t_bf16_32x32:384" (kernel:tiles per layer;
  * a second term is the thin-tile launch over split-off ragged row tiles).
  * Writes at most cap bytes including the terminating NUL; EINVAL if the
  * text does not fit, ENOTFOUND before the first MLP launch. */

@@ -2,14 +2,20 @@
 // (sage_mlp.hsaco) that fn_register loads with hipModuleLoad while the
 // function's weights are moving to the device.
 //
-//   ggemm_bf16_<BM>x<BN>: one layer of a grouped BF16 MLP,
-//       C[r, n] = act(sum_k A[r, k] * W[n, k]) for every row r of every group,
-//       A and W BF16, FP32 accumulation with v_mfma_f32_16x16x32_bf16.
-//       Persistent: each workgroup walks tiles blockIdx.x, +gridDim.x, ...
-//       over a tile list spanning all groups (ragged rows per group).
-//       W rows are found through the function's 64 KiB block table.
-//   mlp_f32_layer: the same layer in FP32 on the vector ALUs for small
-//       batches (one wave per two output columns, fixed reduction order).
+// One layer of a grouped BF16 MLP,
+//     C[r, n] = act(sum_k A[r, k] * W[n, k]) for every row r of every group,
+// A and W BF16, FP32 accumulation with v_mfma_f32_16x16x32_bf16, is one
+// persistent kernel over a tile list that spans all groups (ragged rows per
+// group); W rows are found through the function's 64 KiB block table.
+// Tile-shape families (the launch planner picks among them):
+//   ggemm_bf16_<BM>x<BN>   register-staged double-buffered LDS tiles;
+//   ggemm2_bf16_<BM>x<BN>  the same, 8 waves, XCD-aware tile ranges;
+//   ggemm3*_bf16_<BM>x<BN> direct-to-LDS loads into a ring of K slices,
+//                          thin tiles for a few rows;
+//   ggemm6*_bf16_<BM>x<BN> 8-wave ping-pong over the same ring, the main
+//                          shape of large grouped launches.
+// mlp_f32_layer is the same layer in FP32 on the vector ALUs for small
+// batches (one wave per two output columns, fixed reduction order).
 //
 // Every tile shape walks K in the same order with the same MFMA, so an
 // output element's bits do not depend on the tile shape, on its row
@@ -482,154 +488,6 @@ __device__ __forceinline__ void ggemm3(const GemmHdr* __restrict__ hdr, const Ge
 }
 
 // ---------------------------------------------------------------------------
-// As ggemm3, plus register double-buffering of the MFMA fragments: the LDS
-// reads of stage kt + 1 are issued before the MFMAs of stage kt, so LDS
-// latency hides under matrix work.  Stage j's LDS buffer is refilled (stage
-// j + S) only after every wave's reads of stage j completed (lgkmcnt(0)
-// before the barrier that precedes the refill).
-template <int BM, int BN, int WM, int WN, int S>
-__device__ __forceinline__ void ggemm5(const GemmHdr* __restrict__ hdr, const GemmGroup* __restrict__ groups,
-                                       const LayerArgs la, uint8_t* lds) {
-  constexpr int NWN = BN / WN, NWM = BM / WM;
-  constexpr int NW = NWN * NWM, NT = 64 * NW;
-  constexpr int FM = WM / 16, FN = WN / 16;
-  constexpr uint32_t A_STAGE = BM * kRow3, B_STAGE = BN * kRow3, STAGE = A_STAGE + B_STAGE;
-  constexpr int A_INS = BM / 16 / NW, B_INS = BN / 16 / NW;
-  static_assert(A_INS * 16 * NW == BM && B_INS * 16 * NW == BN, "rows split evenly over waves");
-  constexpr int LPS = A_INS + B_INS;
-  constexpr uint32_t SC = 4;
-  typedef __attribute__((address_space(3))) void lds_void;
-  (void)NT;
-
-  const uint32_t t = threadIdx.x, lane = t & 63;
-  const uint32_t wave = __builtin_amdgcn_readfirstlane(t >> 6);
-  const uint32_t wm = wave / NWN, wn = wave % NWN;
-  const uint32_t N = la.N, K = la.K;
-  const uint32_t total = hdr->total_tiles, G = hdr->n_groups;
-  const bool out_f32 = la.flags & kOutF32, relu = la.flags & kRelu;
-  const uint32_t KT = K / 32;
-  const uint32_t n_tiles = N / BN;
-  const uint32_t lrow = lane >> 2, lslot = lane & 3;
-
-  const uint32_t xcd = blockIdx.x % kXcds, j = blockIdx.x / kXcds, per_xcd = gridDim.x / kXcds;
-  if (j >= per_xcd) return;
-  const uint32_t r0 = (uint32_t)(((uint64_t)total * xcd) / kXcds);
-  const uint32_t r1 = (uint32_t)(((uint64_t)total * (xcd + 1)) / kXcds);
-
-  for (uint32_t tile = r0 + j; tile < r1; tile += per_xcd) {
-    const GemmGroup gr = groups[find_group(groups, G, tile)];
-    const uint32_t m_tiles = (gr.m + BM - 1) / BM;
-    uint32_t mt, nt;
-    tile_coords(tile - gr.tile_start, m_tiles, n_tiles, SC, &mt, &nt);
-    const uint32_t m0 = mt * BM, n0 = nt * BN;
-    const uint64_t* wtab = reinterpret_cast<const uint64_t*>(gr.wtab);
-
-    const uint8_t* ap[A_INS];
-    const uint8_t* bp[B_INS];
-#pragma unroll
-    for (int q = 0; q < A_INS; q++) {
-      const uint32_t row = (wave * A_INS + q) * 16 + lrow;
-      uint32_t r = m0 + row;
-      r = r < gr.m ? r : gr.m - 1;
-      ap[q] = a_row(la, gr.row0 + r, 2) + (lslot ^ ((row >> 1) & 3)) * 16;
-    }
-#pragma unroll
-    for (int q = 0; q < B_INS; q++) {
-      const uint32_t row = (wave * B_INS + q) * 16 + lrow;
-      const uint64_t off = la.w_off + (uint64_t)(n0 + row) * K * 2;
-      bp[q] = reinterpret_cast<const uint8_t*>(wtab[off >> kBlockShift]) + (off & (kBlock - 1)) +
-              (lslot ^ ((row >> 1) & 3)) * 16;
-    }
-    auto issue = [&](uint32_t kt) __attribute__((always_inline)) {
-      uint8_t* st = lds + (kt % S) * STAGE;
-#pragma unroll
-      for (int q = 0; q < A_INS; q++)
-        __builtin_amdgcn_global_load_lds((const void*)(ap[q] + kt * kRow3),
-                                         (lds_void*)(st + (wave * A_INS + q) * 1024), 16, 0, 0);
-#pragma unroll
-      for (int q = 0; q < B_INS; q++)
-        __builtin_amdgcn_global_load_lds((const void*)(bp[q] + kt * kRow3),
-                                         (lds_void*)(st + A_STAGE + (wave * B_INS + q) * 1024), 16, 0, 0);
-    };
-    const uint32_t chunk = lane >> 4;
-    auto read_frags = [&](uint32_t kt, bf16x8 (&af)[FM], bf16x8 (&bf)[FN]) __attribute__((always_inline)) {
-      const uint8_t* st = lds + (kt % S) * STAGE;
-#pragma unroll
-      for (int i = 0; i < FM; i++)
-        af[i] = *reinterpret_cast<const bf16x8*>(st + swz3(wm * WM + i * 16 + (lane & 15), chunk));
-#pragma unroll
-      for (int jj = 0; jj < FN; jj++)
-        bf[jj] = *reinterpret_cast<const bf16x8*>(st + A_STAGE + swz3(wn * WN + jj * 16 + (lane & 15), chunk));
-    };
-
-    f32x4 acc[FM][FN];
-#pragma unroll
-    for (int i = 0; i < FM; i++)
-#pragma unroll
-      for (int jj = 0; jj < FN; jj++) acc[i][jj] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-#pragma unroll
-    for (int s0 = 0; s0 < S; s0++)
-      if ((uint32_t)s0 < KT) issue(s0);
-    {
-      const uint32_t later = (KT - 1) < (uint32_t)(S - 1) ? (KT - 1) : (uint32_t)(S - 1);
-      wait_stages<LPS, S - 1>(later);
-    }
-    __builtin_amdgcn_s_barrier();
-    bf16x8 fa[FM], fb[FN], ga[FM], gb[FN];
-    read_frags(0, fa, fb);
-    auto mfma_all = [&](const bf16x8 (&a)[FM], const bf16x8 (&b)[FN]) __attribute__((always_inline)) {
-#pragma unroll
-      for (int i = 0; i < FM; i++)
-#pragma unroll
-        for (int jj = 0; jj < FN; jj++)
-          acc[i][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[jj], acc[i][jj], 0, 0, 0);
-    };
-    // two K-steps per trip with the fragment buffers swapped by name, so no
-    // register copies and no control-flow merge sits between reads and MFMAs
-    uint32_t kt = 0;
-    auto step = [&](bf16x8 (&ca)[FM], bf16x8 (&cb)[FN], bf16x8 (&na)[FM], bf16x8 (&nb)[FN])
-        __attribute__((always_inline)) {
-      const uint32_t later = (KT - 2 - kt) < (uint32_t)(S - 2) ? (KT - 2 - kt) : (uint32_t)(S - 2);
-      wait_stages<LPS, S - 2>(later);
-      __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): this wave's reads of stage kt are done
-      __builtin_amdgcn_s_barrier();
-      if (kt + S < KT) issue(kt + S);
-      read_frags(kt + 1, na, nb);
-      mfma_all(ca, cb);
-      kt++;
-    };
-    // KT is even and >= 2: K is a multiple of BN (>= 128), checked by the host
-    while (kt + 2 < KT) {
-      step(fa, fb, ga, gb);
-      step(ga, gb, fa, fb);
-    }
-    step(fa, fb, ga, gb);
-    mfma_all(ga, gb);
-    __syncthreads();  // the next tile's first loads overwrite stages still being read
-
-#pragma unroll
-    for (int i = 0; i < FM; i++) {
-#pragma unroll
-      for (int q = 0; q < 4; q++) {
-        const uint32_t r = m0 + wm * WM + i * 16 + 4 * (lane >> 4) + q;
-        if (r < gr.m) {
-          uint8_t* crow = c_row(la, gr.row0 + r, out_f32 ? 4 : 2);
-#pragma unroll
-          for (int jj = 0; jj < FN; jj++) {
-            const uint32_t col = n0 + wn * WN + jj * 16 + (lane & 15);
-            float v = acc[i][jj][q];
-            if (relu) v = v > 0.f ? v : 0.f;
-            if (out_f32) reinterpret_cast<float*>(crow)[col] = v;
-            else reinterpret_cast<__bf16*>(crow)[col] = (__bf16)v;
-          }
-        }
-      }
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
 // Ping-pong schedule over the ggemm3 ring: eight waves in two groups of four
 // (waves w and w + 4 share a SIMD).  Every wave alternates a memory phase
 // (LDS reads of one K-slice's fragments, global loads of a later slice) and
@@ -645,7 +503,7 @@ __device__ __forceinline__ void phase_sync() {
   __builtin_amdgcn_sched_barrier(0);
 }
 
-template <int BM, int BN, int WM, int WN, int S, bool PRIO = false, bool LOADS_FIRST = false>
+template <int BM, int BN, int WM, int WN, int S, bool PRIO = false>
 __device__ __forceinline__ void ggemm6(const GemmHdr* __restrict__ hdr, const GemmGroup* __restrict__ groups,
                                        const LayerArgs la, uint8_t* lds) {
   constexpr int NWN = BN / WN, NWM = BM / WM;
@@ -726,7 +584,6 @@ __device__ __forceinline__ void ggemm6(const GemmHdr* __restrict__ hdr, const Ge
     const uint32_t chunk = lane >> 4;
     for (uint32_t kt = 0; kt < KT; kt++) {
       // memory phase
-      if (LOADS_FIRST && kt + S - 1 < KT) issue(kt + S - 1);
       const uint8_t* st = lds + (kt % S) * STAGE;
       bf16x8 af[FM], bfr[FN];
 #pragma unroll
@@ -735,7 +592,7 @@ __device__ __forceinline__ void ggemm6(const GemmHdr* __restrict__ hdr, const Ge
 #pragma unroll
       for (int jj = 0; jj < FN; jj++)
         bfr[jj] = *reinterpret_cast<const bf16x8*>(st + A_STAGE + swz3(wn * WN + jj * 16 + (lane & 15), chunk));
-      if (!LOADS_FIRST && kt + S - 1 < KT) issue(kt + S - 1);
+      if (kt + S - 1 < KT) issue(kt + S - 1);
       if (kt + 1 < KT) {
         const uint32_t later = (KT - 2 - kt) < (uint32_t)(S - 2) ? (KT - 2 - kt) : (uint32_t)(S - 2);
         wait_stages<LPS, S - 2>(later);  // this wave's loads of slice kt + 1 landed
@@ -784,13 +641,9 @@ __device__ __forceinline__ void ggemm6(const GemmHdr* __restrict__ hdr, const Ge
     ggemm_bf16<BM, BN, WM, WN>(hdr, groups, la, lds);                                                  \
   }
 
-SAGE_GGEMM(16, 64, 16, 16, 2)
-SAGE_GGEMM(32, 64, 16, 32, 2)
 SAGE_GGEMM(32, 128, 32, 32, 2)
 SAGE_GGEMM(64, 128, 32, 64, 2)
 SAGE_GGEMM(128, 128, 64, 64, 2)
-SAGE_GGEMM(256, 128, 128, 64, 1)
-SAGE_GGEMM(128, 256, 64, 128, 1)
 
 // large tiles, 8 waves, XCD-aware tile ranges
 #define SAGE_GGEMM2(BM, BN, WM, WN)                                                                   \
@@ -800,17 +653,7 @@ SAGE_GGEMM(128, 256, 64, 128, 1)
     ggemm2<BM, BN, WM, WN>(hdr, groups, la, lds);                                                      \
   }
 
-SAGE_GGEMM2(256, 256, 128, 64)
-SAGE_GGEMM2(256, 128, 128, 32)
 SAGE_GGEMM2(128, 256, 64, 64)
-// 4 waves of 128 x 128: fewer LDS reads per MFMA (accumulators in AGPRs)
-#define SAGE_GGEMM2W(BM, BN, WM, WN)                                                                  \
-  extern "C" __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN), 1) void ggemm4_bf16_##BM##x##BN(  \
-      const GemmHdr* __restrict__ hdr, const GemmGroup* __restrict__ groups, LayerArgs la) {           \
-    __shared__ __attribute__((aligned(16))) uint8_t lds[2 * (BM + BN) * kRowBytes];                    \
-    ggemm2<BM, BN, WM, WN>(hdr, groups, la, lds);                                                      \
-  }
-SAGE_GGEMM2W(256, 256, 128, 128)
 
 // direct-to-LDS, S-stage ring
 #define SAGE_GGEMM3G(NAME, BM, BN, WM, WN, S, G)                                                      \
@@ -820,24 +663,14 @@ SAGE_GGEMM2W(256, 256, 128, 128)
     ggemm3<BM, BN, WM, WN, S, G>(hdr, groups, la, lds);                                                \
   }
 #define SAGE_GGEMM3(NAME, BM, BN, WM, WN, S) SAGE_GGEMM3G(NAME, BM, BN, WM, WN, S, 1)
-SAGE_GGEMM3(ggemm3_bf16_256x256, 256, 256, 128, 64, 4)
-SAGE_GGEMM3(ggemm3_bf16_256x128, 256, 128, 128, 32, 4)
-SAGE_GGEMM3(ggemm3s5_bf16_256x256, 256, 256, 128, 64, 5)      // five stages: all 160 KiB of LDS
-SAGE_GGEMM3(ggemm3w16_bf16_256x256, 256, 256, 64, 64, 4)      // 16 waves of 64 x 64
-SAGE_GGEMM3(ggemm3w16s5_bf16_256x256, 256, 256, 64, 64, 5)
-// thin tiles with an eight-stage ring: few rows (small batches, and the
+// thin tiles with an eight-stage ring: a few rows (small batches, and the
 // ragged last row tiles split off a large-tile launch) are bound by the
 // latency of the K walk, which the deep ring hides
-SAGE_GGEMM3(ggemm3_bf16_16x64, 16, 64, 16, 64, 8)
-SAGE_GGEMM3(ggemm3_bf16_32x64, 32, 64, 16, 64, 8)
-SAGE_GGEMM3(ggemm3_bf16_64x64, 64, 64, 32, 32, 8)
 SAGE_GGEMM3(ggemm3_bf16_128x64, 128, 64, 32, 64, 8)
 // sixteen-slice rings consumed four slices per barrier (K a multiple of 128)
 SAGE_GGEMM3G(ggemm3g4_bf16_16x64, 16, 64, 16, 64, 16, 4)
 SAGE_GGEMM3G(ggemm3g4_bf16_32x64, 32, 64, 16, 64, 16, 4)
 SAGE_GGEMM3G(ggemm3g4_bf16_64x64, 64, 64, 32, 32, 16, 4)
-SAGE_GGEMM3G(ggemm3g4_bf16_128x64, 128, 64, 32, 64, 12, 4)
-SAGE_GGEMM3G(ggemm3g2_bf16_256x256, 256, 256, 128, 64, 4, 2)
 // narrow thin tiles: a few rows still spread W over 128..256 workgroups
 // (16 x 16 with its register use capped at two waves per SIMD)
 #define SAGE_GGEMM3T(NAME, BM, BN, WM, WN, S, G, WPE)                                                 \
@@ -852,30 +685,15 @@ SAGE_GGEMM3G(ggemm3t_bf16_16x32, 16, 32, 16, 32, 16, 4)
 SAGE_GGEMM3G(ggemm3t_bf16_32x32, 32, 32, 16, 32, 16, 4)
 
 // ping-pong over the direct-to-LDS ring
-#define SAGE_GGEMM6(NAME, BM, BN, WM, WN, S, PRIO, LF)                                                \
+#define SAGE_GGEMM6(NAME, BM, BN, WM, WN, S, PRIO)                                                    \
   extern "C" __global__ __launch_bounds__(512, 1) void NAME(                                           \
       const GemmHdr* __restrict__ hdr, const GemmGroup* __restrict__ groups, LayerArgs la) {           \
     __shared__ __attribute__((aligned(1024))) uint8_t lds[S * (BM + BN) * kRow3];                      \
-    ggemm6<BM, BN, WM, WN, S, PRIO, LF>(hdr, groups, la, lds);                                         \
+    ggemm6<BM, BN, WM, WN, S, PRIO>(hdr, groups, la, lds);                                             \
   }
-SAGE_GGEMM6(ggemm6_bf16_256x256, 256, 256, 128, 64, 4, false, false)
-SAGE_GGEMM6(ggemm6s5_bf16_256x256, 256, 256, 128, 64, 5, false, false)
-SAGE_GGEMM6(ggemm6_bf16_256x128, 256, 128, 64, 64, 4, false, false)
-// the matrix-phase wave at raised issue priority; global loads issued first
-SAGE_GGEMM6(ggemm6p_bf16_256x256, 256, 256, 128, 64, 4, true, false)
-SAGE_GGEMM6(ggemm6l_bf16_256x256, 256, 256, 128, 64, 4, false, true)
-SAGE_GGEMM6(ggemm6pl_bf16_256x256, 256, 256, 128, 64, 4, true, true)
-SAGE_GGEMM6(ggemm6s3_bf16_256x256, 256, 256, 128, 64, 3, false, false)
-
-// direct-to-LDS ring + fragment double-buffering
-#define SAGE_GGEMM5(BM, BN, WM, WN, S)                                                                \
-  extern "C" __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN), 1) void ggemm5_bf16_##BM##x##BN(  \
-      const GemmHdr* __restrict__ hdr, const GemmGroup* __restrict__ groups, LayerArgs la) {           \
-    __shared__ __attribute__((aligned(1024))) uint8_t lds[S * (BM + BN) * kRow3];                      \
-    ggemm5<BM, BN, WM, WN, S>(hdr, groups, la, lds);                                                   \
-  }
-SAGE_GGEMM5(256, 128, 128, 32, 4)
-SAGE_GGEMM5(256, 256, 128, 128, 4)
+// the matrix-phase wave at raised issue priority
+SAGE_GGEMM6(ggemm6p_bf16_256x256, 256, 256, 128, 64, 4, true)
+SAGE_GGEMM6(ggemm6_bf16_256x128, 256, 128, 64, 64, 4, false)
 
 // ---------------------------------------------------------------- FP32 MLP
 // Tiles: (group, block of 8 output columns); wave w of the workgroup owns

@@ -36,43 +36,16 @@ struct TileShape {
   uint32_t kalign = 64;  // K must be a multiple of this
 };
 static const TileShape kShapes[] = {
-    {"ggemm_bf16_16x64", 16, 64, 2, 256, false},      {"ggemm_bf16_32x64", 32, 64, 2, 256, false},
-    {"ggemm_bf16_32x128", 32, 128, 2, 256, false},    {"ggemm_bf16_64x128", 64, 128, 2, 256, false},
-    {"ggemm_bf16_128x128", 128, 128, 2, 256, false},  {"ggemm_bf16_256x128", 256, 128, 1, 256, false},
-    {"ggemm_bf16_128x256", 128, 256, 1, 256, false},  {"ggemm2_bf16_256x256", 256, 256, 1, 512, true},
-    {"ggemm2_bf16_256x128", 256, 128, 1, 512, true},  {"ggemm2_bf16_128x256", 128, 256, 1, 512, true},
-    {"ggemm4_bf16_256x256", 256, 256, 1, 256, true},  {"ggemm3_bf16_256x256", 256, 256, 1, 512, true},
-    {"ggemm3_bf16_256x128", 256, 128, 1, 512, true},  {"ggemm5_bf16_256x128", 256, 128, 1, 512, true},
-    {"ggemm5_bf16_256x256", 256, 256, 1, 256, true},  {"ggemm3s5_bf16_256x256", 256, 256, 1, 512, true},
-    {"ggemm3w16_bf16_256x256", 256, 256, 1, 1024, true}, {"ggemm3w16s5_bf16_256x256", 256, 256, 1, 1024, true},
-    {"ggemm3_bf16_16x64", 16, 64, 4, 64, true},       {"ggemm3_bf16_32x64", 32, 64, 3, 128, true},
-    {"ggemm3_bf16_64x64", 64, 64, 2, 256, true},      {"ggemm3_bf16_128x64", 128, 64, 1, 256, true},
-    {"ggemm6_bf16_256x256", 256, 256, 1, 512, true},  {"ggemm6s5_bf16_256x256", 256, 256, 1, 512, true},
-    {"ggemm6_bf16_256x128", 256, 128, 1, 512, true},
-    {"ggemm6p_bf16_256x256", 256, 256, 1, 512, true},  {"ggemm6l_bf16_256x256", 256, 256, 1, 512, true},
-    {"ggemm6pl_bf16_256x256", 256, 256, 1, 512, true}, {"ggemm6s3_bf16_256x256", 256, 256, 1, 512, true},
-    {"ggemm3g4_bf16_16x64", 16, 64, 2, 64, true, 128},  {"ggemm3g4_bf16_32x64", 32, 64, 1, 128, true, 128},
-    {"ggemm3g4_bf16_64x64", 64, 64, 1, 256, true, 128}, {"ggemm3g4_bf16_128x64", 128, 64, 1, 256, true, 128},
-    {"ggemm3g2_bf16_256x256", 256, 256, 1, 512, true},
-    {"ggemm3t_bf16_16x16", 16, 16, 4, 64, true, 128},   {"ggemm3t_bf16_16x32", 16, 32, 3, 64, true, 128},
-    {"ggemm3t_bf16_32x32", 32, 32, 2, 128, true, 128},
+    {"ggemm6p_bf16_256x256", 256, 256, 1, 512, true},  {"ggemm6_bf16_256x128", 256, 128, 1, 512, true},
+    {"ggemm2_bf16_128x256", 128, 256, 1, 512, true},   {"ggemm_bf16_128x128", 128, 128, 2, 256, false},
+    {"ggemm3_bf16_128x64", 128, 64, 1, 256, true},     {"ggemm_bf16_64x128", 64, 128, 2, 256, false},
+    {"ggemm_bf16_32x128", 32, 128, 2, 256, false},     {"ggemm3g4_bf16_64x64", 64, 64, 1, 256, true, 128},
+    {"ggemm3g4_bf16_32x64", 32, 64, 1, 128, true, 128}, {"ggemm3g4_bf16_16x64", 16, 64, 2, 64, true, 128},
+    {"ggemm3t_bf16_32x32", 32, 32, 2, 128, true, 128},  {"ggemm3t_bf16_16x32", 16, 32, 3, 64, true, 128},
+    {"ggemm3t_bf16_16x16", 16, 16, 4, 64, true, 128},
 };
 
 static bool fits(const TileShape& ts, uint32_t W) { return W % ts.bn == 0 && W % ts.kalign == 0; }
-
-// Shapes the planner chooses from: the fastest measured variant of each tile
-// size.  The others stay available by name (SAGE_TILE) for tests and
-// comparison; leaving near-equal variants out keeps plans reproducible.
-static const char* const kPlanned[] = {
-    "ggemm6p_bf16_256x256", "ggemm6_bf16_256x128", "ggemm2_bf16_128x256", "ggemm_bf16_128x128",
-    "ggemm3_bf16_128x64",   "ggemm_bf16_64x128",   "ggemm_bf16_32x128",   "ggemm3g4_bf16_64x64",
-    "ggemm3g4_bf16_32x64",  "ggemm3g4_bf16_16x64", "ggemm3t_bf16_32x32",  "ggemm3t_bf16_16x32",
-    "ggemm3t_bf16_16x16"};
-static bool planned(const TileShape& ts) {
-  for (const char* n : kPlanned)
-    if (std::strcmp(n, ts.name) == 0) return true;
-  return false;
-}
 
 static const TileShape& shape_of(const std::string& name) {
   for (const auto& s : kShapes)
@@ -490,12 +463,12 @@ static std::string tune_key(uint32_t width, const TileShape& ts) {
 static void tune_width(Ctx& c, uint32_t width) {
   bool all = true;
   for (const auto& ts : kShapes)
-    if (planned(ts) && fits(ts, width)) all &= c.tune.count(tune_key(width, ts)) > 0;
+    if (fits(ts, width)) all &= c.tune.count(tune_key(width, ts)) > 0;
   if (all) return;
   Module* mod = load_module(c, SAGE_MLP_BF16);
   uint32_t max_rows = 0;
   for (const auto& ts : kShapes) {
-    if (!planned(ts) || !fits(ts, width)) continue;
+    if (!fits(ts, width)) continue;
     const uint32_t nt = width / ts.bn, grid = shape_grid(c, ts);
     max_rows = std::max(max_rows, ((grid + nt - 1) / nt) * ts.bm);
   }
@@ -517,7 +490,7 @@ static void tune_width(Ctx& c, uint32_t width) {
   HIPX(hipEventCreate(&e0));
   HIPX(hipEventCreate(&e1));
   for (const auto& ts : kShapes) {
-    if (!planned(ts) || !fits(ts, width) || c.tune.count(tune_key(width, ts))) continue;
+    if (!fits(ts, width) || c.tune.count(tune_key(width, ts))) continue;
     const uint32_t nt = width / ts.bn, grid = shape_grid(c, ts);
     const uint32_t rows = ((grid + nt - 1) / nt) * ts.bm;
     const uint64_t tiles = tiles_of(ts, width, rows);
@@ -578,7 +551,7 @@ MlpPlan plan_mlp(Ctx& c, uint32_t W, const std::vector<uint32_t>& m) {
   double best_cost = 1e300;
   std::vector<std::pair<uint32_t, size_t>> parts;  // (ragged rows, group)
   for (const auto& ts : kShapes) {
-    if (!planned(ts) || !fits(ts, W)) continue;
+    if (!fits(ts, W)) continue;
     const uint32_t grid = shape_grid(c, ts);
     uint64_t tiles = 0;
     parts.clear();
@@ -596,7 +569,7 @@ MlpPlan plan_mlp(Ctx& c, uint32_t W, const std::vector<uint32_t>& m) {
     std::sort(parts.begin(), parts.end());
     const uint64_t per_part = W / ts.bn;
     for (const auto& tt : kShapes) {
-      if (!planned(tt) || !fits(tt, W) || tt.bm >= ts.bm || !tt.ranged) continue;
+      if (!fits(tt, W) || tt.bm >= ts.bm || !tt.ranged) continue;
       const uint32_t tgrid = shape_grid(c, tt);
       uint64_t ttiles = 0;
       for (size_t k = 1; k <= parts.size() && k <= 64; k++) {

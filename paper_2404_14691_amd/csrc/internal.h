@@ -160,7 +160,7 @@ class Pool {
   void evict(uint32_t c, bool demotion = false);  // demotion: counted as such, not as an eviction
   void index_add(uint32_t c);           // append to the end of its fingerprint chain
   void index_remove(uint32_t c);
-  void lru_back(uint32_t c);
+  void lru_back(uint32_t c, double now);  // now: when it became unreferenced (host ms)
   void lru_remove(uint32_t c);
   uint32_t lru_front() const { return lru_head_; }
   uint32_t chain_head(uint64_t fp) const { return index_.find(fp); }

@@ -171,7 +171,7 @@ void Pool::lru_remove(uint32_t c) {
   k.in_lru = false;
 }
 
-void Pool::lru_back(uint32_t c) {
+void Pool::lru_back(uint32_t c, double now) {
   lru_remove(c);
   Class& k = cls[c];
   k.lru_prev = lru_tail_;
@@ -180,7 +180,7 @@ void Pool::lru_back(uint32_t c) {
   else lru_head_ = c;
   lru_tail_ = c;
   k.in_lru = true;
-  k.idle_since = now_ms();
+  k.idle_since = now;
 }
 
 void Pool::evict(uint32_t c, bool demotion) {

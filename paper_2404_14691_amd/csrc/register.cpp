@@ -408,8 +408,9 @@ void register_shared(Ctx& c, Fn& f) {
       f.distinct.push_back(cl);
     }
   P.sort_by_seq(f.distinct);
+  const double now = now_ms();
   for (uint32_t cl : f.distinct)
-    if (P.cls[cl].active == 0) P.lru_back(cl);
+    if (P.cls[cl].active == 0) P.lru_back(cl, now);
   c.h2d += f.ro_bytes;
 }
 

@@ -147,7 +147,7 @@ uint64_t setup_internal(Ctx& c, uint64_t id, uint32_t batch) {
   }
   v->live = true;
   f.live++;
-  if (f.mod) f.mod->last_use = now_ms();
+  if (f.mod && c.cfg.exit_stage_ms > 0) f.mod->last_use = now_ms();
   const uint64_t out = v->id;
   c.invs[v->id] = std::move(v);
   return out;
@@ -159,16 +159,17 @@ void release_internal(Ctx& c, uint64_t id) {
   if (f.live <= 0) fail(SAGE_ESTATE, "reference count underflow");
   if (c.cfg.share && f.live == 1) {
     Pool& P = c.pool;
+    const double now = now_ms();
     for (uint32_t cl : f.distinct) {  // increasing class order
       Class& k = P.cls[cl];
       if (k.active == 0) fail(SAGE_ESTATE, "reference count underflow");
-      if (--k.active == 0) P.lru_back(cl);
+      if (--k.active == 0) P.lru_back(cl, now);
     }
   }
   free_inv_buffers(c, v);
   v.live = false;
   f.live--;
-  if (f.live == 0 && f.mod) f.mod->last_use = now_ms();
+  if (f.live == 0 && f.mod && c.cfg.exit_stage_ms > 0) f.mod->last_use = now_ms();
   c.invs.erase(id);
 }
 
