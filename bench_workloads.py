@@ -409,5 +409,69 @@ def exit_stages(S, torch, log, interval_ms=300.0, reps=3, batch=8):
                  "bf16", e2e_ms={k: round(v, 3) for k, v in med.items()}, breakdown_ms=breakdown)
 
 
+# ---------------------------------------------------------------- RW-only function
+def rw_only(S, torch, log, reps=3, n_inv=8, nx=512, ny=512, nz=320, sweeps=20, coef=0.5):
+    """A function with no read-only data (the paper's lbm: Table 2, 0 MB
+    read-only, 330 MB writable; "cannot benefit" from memory sharing): the
+    relaxation kind over a 512 x 512 x 320 FP32 field (335 MB) passed from
+    pageable host memory, 20 sweeps, result back to host memory.  Shared and
+    plain contexts do the same work; a cold run opens a new context (code
+    object and all) per invocation."""
+    from paper_2404_14691_amd import synth
+    shape = (nz, ny, nx)
+    desc = S.relax_desc(nx, ny, nz, sweeps, coef)
+    u = synth.stencil_field(0, 0, seed=7, shape=shape)
+    out = np.empty_like(u)
+    res = {}
+
+    def warm(share):
+        cfg = S.sage_config_default()
+        cfg.share = share
+        ctx = S.sage_open(0, cfg)
+        try:
+            fn = S.fn_register(ctx, desc, [])
+            inv = S.fn_setup(ctx, fn, 1)
+            S.fn_invoke(ctx, inv, u, out)  # warm-up: first launch of the kind
+            S.fn_release(ctx, inv)
+            ms = []
+            for _ in range(n_inv):
+                t0 = time.perf_counter()
+                inv = S.fn_setup(ctx, fn, 1)
+                S.fn_invoke(ctx, inv, u, out)
+                S.fn_release(ctx, inv)
+                ms.append((time.perf_counter() - t0) * 1e3)
+            S.fn_unregister(ctx, fn)
+            return float(np.median(ms))
+        finally:
+            S.sage_close(ctx)
+
+    def cold():
+        t0 = time.perf_counter()
+        ctx = S.sage_open(0, S.sage_config_default())
+        fn = S.fn_register(ctx, desc, [])
+        inv = S.fn_setup(ctx, fn, 1)
+        S.fn_invoke(ctx, inv, u, out)
+        S.fn_release(ctx, inv)
+        ms = (time.perf_counter() - t0) * 1e3
+        S.fn_unregister(ctx, fn)
+        S.sage_close(ctx)
+        return ms
+
+    runs = {"shared": [], "plain": [], "cold": []}
+    for r in range(reps):
+        runs["shared"].append(warm(1))
+        runs["plain"].append(warm(0))
+        runs["cold"].append(cold())
+        log(f"rw_only rep {r}: " + ", ".join(f"{k} {v[-1]:.1f} ms" for k, v in runs.items()))
+    med = {k: float(np.median(v)) for k, v in runs.items()}
+    value = 1e3 / med["shared"]
+    return _line("invocations/sec of a function without read-only data, shared vs plain, 1 MI355X", value,
+                 "invocations/s", reps, 1, med["shared"],
+                 {"workload": f"rw_only: relaxation {nx}x{ny}x{nz} FP32 ({nx * ny * nz * 4 / 1e6:.0f} MB writable, no "
+                              f"read-only data), {sweeps} sweeps, field from and to pageable host memory"},
+                 "f32", invocation_ms=med, speedup_vs_plain=round(med["plain"] / med["shared"], 3),
+                 warm_vs_cold=round(med["cold"] / med["shared"], 3))
+
+
 WORKLOADS = {"batching": batching, "stencil": stencil, "mlp_f32": mlp_f32, "serving": serving,
-             "exit_stages": exit_stages}
+             "exit_stages": exit_stages, "rw_only": rw_only}

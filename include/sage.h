@@ -82,7 +82,8 @@ typedef struct {
 typedef enum {
   SAGE_MLP_F32 = 1,     /* ReLU MLP, FP32 weights/activations */
   SAGE_MLP_BF16 = 2,    /* ReLU MLP, BF16 weights/activations, FP32 accumulate, FP32 output */
-  SAGE_STENCIL7_F32 = 3 /* 7-point Jacobi relaxation with a read-only coefficient grid */
+  SAGE_STENCIL7_F32 = 3, /* 7-point Jacobi relaxation with a read-only coefficient grid */
+  SAGE_RELAX7_F32 = 4    /* the same sweep with one constant coefficient: no read-only data */
 } sage_kind;
 
 /* MLP: one RO blob, weights [layers][width][width] ([out][in]) row-major,
@@ -94,11 +95,16 @@ typedef enum {
  *   nx*4 <= 65536, all extents >= 3.  Input u0 [batch][nz][ny][nx] FP32,
  *   output u after `sweeps` Jacobi sweeps:
  *   u'_p = u_p + c_p * (avg of 6 face neighbours - u_p) on interior cells,
- *   boundary cells unchanged. */
+ *   boundary cells unchanged.
+ * RELAX7: no read-only blob (n_blobs = 0); all of its data is the writable
+ *   field of each invocation, like the paper's lbm (Table 2: no read-only
+ *   bytes, 330 MB writable).  The STENCIL7 sweep with c_p = coef, nx a
+ *   multiple of 4, all extents >= 3. */
 typedef struct {
   uint32_t kind; /* sage_kind */
   uint32_t layers, width;
   uint32_t nx, ny, nz, sweeps;
+  float coef;    /* RELAX7 only */
 } sage_fn_desc;
 
 typedef struct {

@@ -5,7 +5,8 @@
 //       u'_p = u_p + c_p * ((sum of 6 face neighbours) / 6 - u_p) inside,
 //       u'_p = u_p on the boundary,
 //   with the read-only coefficient grid c reached through its 64 KiB block
-//   table (nx * 4 divides 65536, so an x-row of c never crosses a block).
+//   table (nx * 4 divides 65536, so an x-row of c never crosses a block), or,
+//   for the relaxation kind without read-only data, one constant c.
 //
 // A workgroup is 64 x-cells by 4 y-rows and marches kStencilTZ planes along
 // z, carrying the z-1 / z / z+1 values in registers; x and y neighbours come
@@ -129,7 +130,8 @@ extern "C" __global__ __launch_bounds__(1024) void stencil7_sweep2(StencilArgs s
       f32x4 out = uc;
       if (!z_edge && y != 0 && y != ny - 1) {
         const uint64_t coff = ((uint64_t)z * ny + y) * nx * 4 + (uint64_t)x * 4;  // byte offset of c(x, y, z)
-        const f32x4 c = *reinterpret_cast<const f32x4*>(sa.ctab[coff >> kBlockShift] + (coff & (kBlock - 1)));
+        const f32x4 c = sa.ctab ? *reinterpret_cast<const f32x4*>(sa.ctab[coff >> kBlockShift] + (coff & (kBlock - 1)))
+                                : f32x4{sa.coef, sa.coef, sa.coef, sa.coef};
         const float nb[4][2] = {{left, uc.y}, {uc.x, uc.z}, {uc.y, uc.w}, {uc.z, right}};
 #pragma unroll
         for (int e = 0; e < 4; e++) {

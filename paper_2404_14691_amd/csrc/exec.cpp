@@ -15,16 +15,17 @@ size_t in_elem_size(const sage_fn_desc& d) { return d.kind == SAGE_MLP_BF16 ? 2 
 
 uint64_t ro_bytes_for(const sage_fn_desc& d) {
   if (d.kind == SAGE_STENCIL7_F32) return (uint64_t)d.nx * d.ny * d.nz * 4;
+  if (d.kind == SAGE_RELAX7_F32) return 0;
   return (uint64_t)d.layers * d.width * d.width * in_elem_size(d);
 }
 
 size_t in_bytes_for(const sage_fn_desc& d, uint32_t batch) {
-  if (d.kind == SAGE_STENCIL7_F32) return (size_t)batch * d.nx * d.ny * d.nz * 4;
+  if (is_grid(d.kind)) return (size_t)batch * d.nx * d.ny * d.nz * 4;
   return (size_t)batch * d.width * in_elem_size(d);
 }
 
 size_t out_bytes_for(const sage_fn_desc& d, uint32_t batch) {
-  if (d.kind == SAGE_STENCIL7_F32) return (size_t)batch * d.nx * d.ny * d.nz * 4;
+  if (is_grid(d.kind)) return (size_t)batch * d.nx * d.ny * d.nz * 4;
   return (size_t)batch * d.width * 4;
 }
 
@@ -379,13 +380,15 @@ int launch_stencil_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, in
       fidx++;
     }
   }
-  const uint64_t* ctab = calls[0].inv->table();
+  // the coefficient grid's block table, or none: one constant coefficient
+  const uint64_t* ctab = d.kind == SAGE_STENCIL7_F32 ? calls[0].inv->table() : nullptr;
   if (S == 0) {
     for (auto& p : io_fields) HIPX(hipMemcpyAsync(p.second, p.first, fbytes, hipMemcpyDeviceToDevice, s));
   } else {
     HIPX(hipMemcpyAsync(F.d_meta, F.h_meta, (size_t)S * 2 * nf * 8, hipMemcpyHostToDevice, s));
     StencilArgs sa{};
     sa.ctab = ctab;
+    sa.coef = d.coef;
     sa.nx = d.nx;
     sa.ny = d.ny;
     sa.nz = d.nz;

@@ -43,6 +43,9 @@ const std::string& last_error();
 void hip_check(hipError_t e, const char* what, const char* file, int line);
 #define HIPX(call) ::sage::hip_check((call), #call, __FILE__, __LINE__)
 
+// Kinds whose body is the grid sweep (read-only coefficient grid or none).
+inline bool is_grid(uint32_t kind) { return kind == SAGE_STENCIL7_F32 || kind == SAGE_RELAX7_F32; }
+
 // Run `body` and translate an Error / std::exception into a status.
 sage_status guard(const std::function<void()>& body);
 

@@ -59,13 +59,14 @@ constexpr uint32_t kOutF32 = 2u;
 
 // ---------------------------------------------------------------- stencil
 struct StencilArgs {
-  const uint64_t* ctab;   // coefficient blocks
+  const uint64_t* ctab;   // coefficient blocks, or null: every cell uses `coef`
   const uint64_t* src;    // per field: device address of the sweep's input
   const uint64_t* dst;    // per field: device address of the sweep's output
   uint32_t nx, ny, nz;
   uint32_t n_fields;
   uint32_t tiles_x, tiles_y, tiles_z;  // spatial tiles per axis
   uint32_t spatial_tiles;              // tiles_x * tiles_y * tiles_z
+  float coef;
 };
 
 constexpr int kStencilTX = 64;  // stencil7_sweep: cells along x per workgroup row

@@ -154,7 +154,7 @@ hipFunction_t Module::get(const char* name) {
 // functions and invocations (section "Context Memory Sharing").
 Module* load_module(Ctx& c, int kind) {
   std::lock_guard<std::mutex> lk(c.module_mu);
-  const int key = kind == SAGE_STENCIL7_F32 ? SAGE_STENCIL7_F32 : SAGE_MLP_BF16;
+  const int key = is_grid(kind) ? SAGE_STENCIL7_F32 : SAGE_MLP_BF16;
   std::unique_ptr<Module>& slot = c.modules[key];
   if (!slot) {
     slot = std::make_unique<Module>();

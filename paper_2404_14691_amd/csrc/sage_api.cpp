@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <tuple>
 #include <cstdlib>
+#include <cmath>
 #include <cstring>
 #include <unordered_set>
 
@@ -54,6 +55,11 @@ void validate(const sage_fn_desc& d, const sage_blob* blobs, size_t n) {
   } else if (d.kind == SAGE_STENCIL7_F32) {
     if (!pow2(d.nx) || (uint64_t)d.nx * 4 > kBlock || d.nx < 4 || d.ny < 3 || d.nz < 3)
       fail(SAGE_EINVAL, "stencil needs a power-of-two nx with nx*4 <= 65536 and extents >= 3");
+  } else if (d.kind == SAGE_RELAX7_F32) {
+    if (d.nx % 4 || d.nx < 4 || d.ny < 3 || d.nz < 3 || !std::isfinite(d.coef))
+      fail(SAGE_EINVAL, "relaxation needs nx a multiple of 4, extents >= 3 and a finite coefficient");
+    if (n != 0) fail(SAGE_EINVAL, "this kind has no read-only data: register it with no blobs");
+    return;
   } else {
     fail(SAGE_EINVAL, "unknown function kind %u", d.kind);
   }
@@ -138,7 +144,7 @@ uint64_t setup_internal(Ctx& c, uint64_t id, uint32_t batch) {
       copy_private(c, f, (uint8_t*)v->priv, c.ctl);
       std::vector<uint64_t> t(f.n_blocks);
       for (uint32_t b = 0; b < f.n_blocks; b++) t[b] = (uint64_t)((uint8_t*)v->priv + (uint64_t)b * kBlock);
-      HIPX(hipMemcpyAsync(v->priv_table, t.data(), t.size() * 8, hipMemcpyHostToDevice, c.ctl));
+      if (!t.empty()) HIPX(hipMemcpyAsync(v->priv_table, t.data(), t.size() * 8, hipMemcpyHostToDevice, c.ctl));
       HIPX(hipStreamSynchronize(c.ctl));
     } catch (...) {
       free_inv_buffers(c, *v);
@@ -440,7 +446,7 @@ static void run_calls(Ctx& c, const std::vector<Call>& calls, uint32_t io) {
   std::vector<Key> keys;
   for (const Call& cl : calls) {
     const sage_fn_desc& d = cl.inv->fn->d;
-    const Key k = d.kind == SAGE_STENCIL7_F32 ? Key{d.kind, 0u, 0u, (const void*)cl.inv->table()}
+    const Key k = is_grid(d.kind) ? Key{d.kind, 0u, 0u, (const void*)cl.inv->table()}
                                               : Key{d.kind, d.width, d.layers, nullptr};
     size_t i = 0;
     while (i < keys.size() && keys[i] != k) i++;
@@ -452,7 +458,7 @@ static void run_calls(Ctx& c, const std::vector<Call>& calls, uint32_t io) {
   }
   std::vector<int> used;
   for (auto& part : parts) {
-    const int fl = part[0].inv->fn->d.kind == SAGE_STENCIL7_F32 ? launch_stencil_group(c, part, io)
+    const int fl = is_grid(part[0].inv->fn->d.kind) ? launch_stencil_group(c, part, io)
                                                                   : launch_mlp_group(c, part, io);
     used.push_back(fl);
   }

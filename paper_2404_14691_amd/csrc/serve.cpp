@@ -52,7 +52,7 @@ static bool same_shape(Ctx& c, const Req& a, const Req& b) {
   const sage_fn_desc& x = find_fn(c, a.fn).d;
   const sage_fn_desc& y = find_fn(c, b.fn).d;
   if (x.kind != y.kind) return false;
-  if (x.kind == SAGE_STENCIL7_F32) return a.fn == b.fn;
+  if (is_grid(x.kind)) return a.fn == b.fn;
   return x.width == y.width && x.layers == y.layers;
 }
 
@@ -161,7 +161,7 @@ static void serve_loop(Ctx& c, Serve& S) {
         }
         if (group.empty()) break;
         const uint32_t io = group[0]->io;
-        const bool stencil = find_fn(c, group[0]->fn).d.kind == SAGE_STENCIL7_F32;
+        const bool stencil = is_grid(find_fn(c, group[0]->fn).d.kind);
         const sage_status st = guard([&] {
           if (stencil) launch_stencil_group(c, calls, io, fl);
           else launch_mlp_group(c, calls, io, fl);

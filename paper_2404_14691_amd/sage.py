@@ -28,7 +28,7 @@ STATUS_NAMES = ["SAGE_OK", "SAGE_EINVAL", "SAGE_ENOMEM", "SAGE_EBUSY", "SAGE_ENO
                 "SAGE_ESTATE", "SAGE_EHIP", "SAGE_EIO"]
 SAGE_RO, SAGE_RW = 0, 1
 SAGE_SRC_HOST, SAGE_SRC_DEVICE = 0, 1
-SAGE_MLP_F32, SAGE_MLP_BF16, SAGE_STENCIL7_F32 = 1, 2, 3
+SAGE_MLP_F32, SAGE_MLP_BF16, SAGE_STENCIL7_F32, SAGE_RELAX7_F32 = 1, 2, 3, 4
 SAGE_IO_DEVICE_IN, SAGE_IO_DEVICE_OUT = 1, 2
 SAGE_OP_COPY, SAGE_OP_VERIFY = 0, 1
 BLOCK = 65536
@@ -49,7 +49,8 @@ class sage_blob(C.Structure):
 
 class sage_fn_desc(C.Structure):
     _fields_ = [("kind", C.c_uint32), ("layers", C.c_uint32), ("width", C.c_uint32),
-                ("nx", C.c_uint32), ("ny", C.c_uint32), ("nz", C.c_uint32), ("sweeps", C.c_uint32)]
+                ("nx", C.c_uint32), ("ny", C.c_uint32), ("nz", C.c_uint32), ("sweeps", C.c_uint32),
+                ("coef", C.c_float)]
 
 
 class sage_config(C.Structure):
@@ -399,3 +400,7 @@ def mlp_desc(kind: int, layers: int, width: int) -> sage_fn_desc:
 
 def stencil_desc(nx: int, ny: int, nz: int, sweeps: int) -> sage_fn_desc:
     return sage_fn_desc(kind=SAGE_STENCIL7_F32, nx=nx, ny=ny, nz=nz, sweeps=sweeps)
+
+
+def relax_desc(nx: int, ny: int, nz: int, sweeps: int, coef: float) -> sage_fn_desc:
+    return sage_fn_desc(kind=SAGE_RELAX7_F32, nx=nx, ny=ny, nz=nz, sweeps=sweeps, coef=coef)
