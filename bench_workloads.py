@@ -204,7 +204,7 @@ def stencil(S, torch, log, steps=2, warmup=1, n=512, n_inv=32, sweeps=20):
                  "f32", plain={"value": round(n_inv / pel, 3), "ms_per_step": round(pel * 1e3, 2)},
                  speedup_vs_plain=round(value / (n_inv / pel), 2),
                  roofline={"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "stencil7_sweep",
+                           "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "stencil7_sweep2",
                            "avg_launch_ms": round(avg, 4), "bytes_per_launch": alg})
 
 

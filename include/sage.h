@@ -349,6 +349,15 @@ sage_status sage_last_launch(sage_ctx* ctx, char* out, size_t cap);
 sage_status sage_selftest_setup_overlap(double load_ms, double host_ms, double copy_ms, int serial,
                                         double* measured_ms);
 
+/* Host-only check of the BF16 launch planner: the plan for a layer of width
+ * `width` over groups of rows[0..n_groups) on `cus` CUs, given each listed
+ * tile shape's time for one full wave of tiles (shapes not listed are not
+ * considered), written to `out` as "main:tiles[+tail:tiles] cost_ms".
+ * EINVAL for an unknown shape name, no fitting shape, or a short buffer.
+ * Needs no GPU. */
+sage_status sage_selftest_plan(uint32_t width, const uint32_t* rows, size_t n_groups, const char* const* shapes,
+                               const double* wave_ms, size_t n_shapes, uint32_t cus, char* out, size_t cap);
+
 #if defined(__GNUC__)
 #pragma GCC visibility pop
 #endif

@@ -67,6 +67,7 @@ struct MlpPlan {
   const TileShape* main = nullptr;
   const TileShape* tail = nullptr;   // thin shape of the split-off ragged row tiles
   std::vector<uint8_t> split;        // per group: its ragged last row tile runs in the tail launch
+  double cost_ms = 0;                // predicted layer time
 };
 uint32_t shape_grid(const Ctx& c, const TileShape& ts);
 MlpPlan plan_mlp(Ctx& c, uint32_t W, const std::vector<uint32_t>& m);
@@ -531,31 +532,25 @@ static void tune_width(Ctx& c, uint32_t width) {
 // Gap between two dependent kernels of one stream, charged to a split plan.
 constexpr double kLaunchGapMs = 0.004;
 
-// Cheapest plan for groups of `m` rows: one shape over all tiles, or a
-// large shape over every group's row tiles except the ragged last tiles of
-// the groups in `split`, which a thin shape covers in a second launch.
-// Candidate splits move the k smallest ragged tiles, k = 1, 2, ...
-MlpPlan plan_mlp(Ctx& c, uint32_t W, const std::vector<uint32_t>& m) {
+// Cheapest plan for groups of `m` rows under full-wave times `tune`
+// ("width:shape" -> ms; shapes without an entry are not considered): one
+// shape over all tiles, or a large shape over every group's row tiles except
+// the ragged last tiles of the groups in `split`, which a thin shape covers
+// in a second launch.  Candidate splits move the k smallest ragged tiles.
+static MlpPlan plan_from(const std::map<std::string, TuneEntry>& tune, uint32_t cus, uint32_t W,
+                         const std::vector<uint32_t>& m) {
   MlpPlan best;
   best.split.assign(m.size(), 0);
-  if (!c.force_tile.empty()) {
-    const size_t plus = c.force_tile.find('+');
-    best.main = &shape_of(c.force_tile.substr(0, plus));
-    if (plus != std::string::npos) {
-      best.tail = &shape_of(c.force_tile.substr(plus + 1));
-      for (size_t g = 0; g < m.size(); g++) best.split[g] = m[g] % best.main->bm != 0;
-    }
-    for (const TileShape* t : {best.main, best.tail})
-      if (t && !fits(*t, W)) fail(SAGE_EINVAL, "tile %s does not fit width %u", t->name, W);
-    return best;
-  }
-  tune_width(c, W);
-  auto wave = [&](const TileShape& ts) { return c.tune.at(tune_key(W, ts)).ms; };
+  auto grid_of = [&](const TileShape& ts) { return std::max<uint32_t>(8, cus * ts.occupancy / 8 * 8); };
+  auto wave = [&](const TileShape& ts) -> double {
+    auto it = tune.find(tune_key(W, ts));
+    return it == tune.end() ? -1.0 : it->second.ms;
+  };
   double best_cost = 1e300;
   std::vector<std::pair<uint32_t, size_t>> parts;  // (ragged rows, group)
   for (const auto& ts : kShapes) {
-    if (!fits(ts, W)) continue;
-    const uint32_t grid = shape_grid(c, ts);
+    if (!fits(ts, W) || wave(ts) < 0) continue;
+    const uint32_t grid = grid_of(ts);
     uint64_t tiles = 0;
     parts.clear();
     for (size_t g = 0; g < m.size(); g++) {
@@ -567,13 +562,14 @@ MlpPlan plan_mlp(Ctx& c, uint32_t W, const std::vector<uint32_t>& m) {
       best_cost = cost;
       best.main = &ts;
       best.tail = nullptr;
+      std::fill(best.split.begin(), best.split.end(), 0);
     }
     if (ts.bm < 128 || parts.empty()) continue;
     std::sort(parts.begin(), parts.end());
     const uint64_t per_part = W / ts.bn;
     for (const auto& tt : kShapes) {
-      if (!fits(tt, W) || tt.bm >= ts.bm || !tt.ranged) continue;
-      const uint32_t tgrid = shape_grid(c, tt);
+      if (!fits(tt, W) || wave(tt) < 0 || tt.bm >= ts.bm || !tt.ranged) continue;
+      const uint32_t tgrid = grid_of(tt);
       uint64_t ttiles = 0;
       for (size_t k = 1; k <= parts.size() && k <= 64; k++) {
         ttiles += tiles_of(tt, W, parts[k - 1].first);
@@ -591,7 +587,51 @@ MlpPlan plan_mlp(Ctx& c, uint32_t W, const std::vector<uint32_t>& m) {
     }
   }
   if (!best.main) fail(SAGE_EINVAL, "no tile shape fits width %u", W);
+  best.cost_ms = best_cost;
   return best;
+}
+
+MlpPlan plan_mlp(Ctx& c, uint32_t W, const std::vector<uint32_t>& m) {
+  MlpPlan best;
+  best.split.assign(m.size(), 0);
+  if (!c.force_tile.empty()) {
+    const size_t plus = c.force_tile.find('+');
+    best.main = &shape_of(c.force_tile.substr(0, plus));
+    if (plus != std::string::npos) {
+      best.tail = &shape_of(c.force_tile.substr(plus + 1));
+      for (size_t g = 0; g < m.size(); g++) best.split[g] = m[g] % best.main->bm != 0;
+    }
+    for (const TileShape* t : {best.main, best.tail})
+      if (t && !fits(*t, W)) fail(SAGE_EINVAL, "tile %s does not fit width %u", t->name, W);
+    return best;
+  }
+  tune_width(c, W);
+  return plan_from(c.tune, (uint32_t)c.cus, W, m);
+}
+
+// "main:tiles[+tail:tiles] cost_ms" of the plan for `m` under `tune`.
+std::string plan_describe(const std::map<std::string, TuneEntry>& tune, uint32_t cus, uint32_t W,
+                          const std::vector<uint32_t>& m) {
+  const MlpPlan p = plan_from(tune, cus, W, m);
+  uint64_t tiles = 0, ttiles = 0;
+  for (size_t g = 0; g < m.size(); g++) {
+    const uint32_t part = p.tail && p.split[g] ? m[g] % p.main->bm : 0;
+    tiles += tiles_of(*p.main, W, m[g] - part);
+    if (part) ttiles += tiles_of(*p.tail, W, part);
+  }
+  std::string s = std::string(p.main->name) + ":" + std::to_string(tiles);
+  if (ttiles) s += std::string("+") + p.tail->name + ":" + std::to_string(ttiles);
+  char buf[64];
+  std::snprintf(buf, sizeof buf, " %.6f", p.cost_ms);
+  return s + buf;
+}
+
+std::string tune_key_for(uint32_t width, const std::string& shape) { return std::to_string(width) + ":" + shape; }
+
+bool tile_shape_known(const std::string& name) {
+  for (const auto& s : kShapes)
+    if (name == s.name) return true;
+  return false;
 }
 
 }  // namespace sage

@@ -413,6 +413,12 @@ void finish_flight(Ctx& c, int flight);
 void flights_init(Ctx& c);
 void flights_destroy(Ctx& c);
 void tune_load(Ctx& c);
+// Launch plan of a BF16 layer for groups of `rows` under full-wave times
+// `tune` on `cus` CUs, as text (host logic only; for self tests).
+std::string plan_describe(const std::map<std::string, TuneEntry>& tune, uint32_t cus, uint32_t W,
+                          const std::vector<uint32_t>& rows);
+std::string tune_key_for(uint32_t width, const std::string& shape);
+bool tile_shape_known(const std::string& name);
 
 uint64_t setup_internal(Ctx& c, uint64_t fn, uint32_t batch);
 void release_internal(Ctx& c, uint64_t inv);

@@ -69,9 +69,7 @@ struct StencilArgs {
   float coef;
 };
 
-constexpr int kStencilTX = 64;  // stencil7_sweep: cells along x per workgroup row
-constexpr int kStencilTY = 4;   // rows along y per workgroup
-constexpr int kStencilTZ = 32;  // planes along z each workgroup marches
-constexpr int kStencil2TX = 256, kStencil2TY = 16, kStencil2TZ = 64;  // stencil7_sweep2 tile
+// stencil7_sweep2 tile: cells along x, rows along y, planes along z marched
+constexpr int kStencil2TX = 256, kStencil2TY = 16, kStencil2TZ = 64;
 
 }  // namespace sage

@@ -665,6 +665,23 @@ sage_status sage_timing_reset(sage_ctx* p) {
   });
 }
 
+sage_status sage_selftest_plan(uint32_t width, const uint32_t* rows, size_t n_groups, const char* const* shapes,
+                               const double* wave_ms, size_t n_shapes, uint32_t cus, char* out, size_t cap) {
+  return guard([&] {
+    if (!rows || !out || (n_shapes && (!shapes || !wave_ms)) || !n_groups || !cus)
+      fail(SAGE_EINVAL, "null argument or empty input");
+    std::map<std::string, TuneEntry> tune;
+    for (size_t i = 0; i < n_shapes; i++) {
+      if (!shapes[i]) fail(SAGE_EINVAL, "null shape name");
+      if (!tile_shape_known(shapes[i])) fail(SAGE_EINVAL, "unknown tile shape %s", shapes[i]);
+      tune[tune_key_for(width, shapes[i])] = TuneEntry{shapes[i], wave_ms[i]};
+    }
+    const std::string s = plan_describe(tune, cus, width, std::vector<uint32_t>(rows, rows + n_groups));
+    if (s.size() + 1 > cap) fail(SAGE_EINVAL, "need %zu bytes", s.size() + 1);
+    std::memcpy(out, s.c_str(), s.size() + 1);
+  });
+}
+
 sage_status sage_tick(sage_ctx* p) {
   return guard([&] {
     Ctx& c = ctx_of(p);

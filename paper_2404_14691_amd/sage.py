@@ -130,6 +130,8 @@ _sigs = {
     "sage_timing_reset": (C.c_int, [_P]),
     "sage_last_launch": (C.c_int, [_P, C.c_char_p, C.c_size_t]),
     "sage_tick": (C.c_int, [_P]),
+    "sage_selftest_plan": (C.c_int, [C.c_uint32, C.POINTER(C.c_uint32), C.c_size_t, C.POINTER(C.c_char_p),
+                                     C.POINTER(C.c_double), C.c_size_t, C.c_uint32, C.c_char_p, C.c_size_t]),
     "sage_selftest_setup_overlap": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_int,
                                               C.POINTER(C.c_double)]),
     "sage_serve_start": (C.c_int, [_P, C.c_uint32]),
@@ -340,6 +342,19 @@ def sage_timing_get(ctx: int, kernel: str):
 
 def sage_timing_reset(ctx: int) -> None:
     _check(_lib.sage_timing_reset(ctx), "sage_timing_reset")
+
+
+def sage_selftest_plan(width: int, rows, wave_ms: dict, cus: int = 256):
+    """(plan text, predicted ms) of the BF16 launch planner for groups of
+    `rows` under full-wave times `wave_ms` {shape: ms}; host only."""
+    names = list(wave_ms)
+    r = (C.c_uint32 * len(rows))(*rows)
+    sh = (C.c_char_p * len(names))(*[n.encode() for n in names])
+    ms = (C.c_double * len(names))(*[wave_ms[n] for n in names])
+    buf = C.create_string_buffer(512)
+    _check(_lib.sage_selftest_plan(width, r, len(rows), sh, ms, len(names), cus, buf, 512), "sage_selftest_plan")
+    plan, cost = buf.value.decode().rsplit(" ", 1)
+    return plan, float(cost)
 
 
 def sage_tick(ctx: int) -> None:
