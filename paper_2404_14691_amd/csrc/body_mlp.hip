@@ -488,10 +488,11 @@ __device__ __forceinline__ void ggemm3(const GemmHdr* __restrict__ hdr, const Ge
 }
 
 // ---------------------------------------------------------------------------
-// Ping-pong schedule over the ggemm3 ring: eight waves in two groups of four
-// (waves w and w + 4 share a SIMD).  Every wave alternates a memory phase
-// (LDS reads of one K-slice's fragments, global loads of a later slice) and
-// a matrix phase (that slice's MFMAs), each ended by a workgroup barrier;
+// Ping-pong schedule over the ggemm3 ring: the waves form two groups of
+// equal size (waves w and w + NW / 2 share a SIMD; 8 waves: groups of four).
+// Every wave alternates a memory phase (LDS reads of one K-slice's
+// fragments, global loads of a later slice) and a matrix phase (that slice's
+// MFMAs), each ended by a workgroup barrier;
 // the second group starts one barrier late, so while one wave of a SIMD
 // multiplies, its partner fetches.  Ring safety: a slice's buffer is
 // refilled S - 1 slices later, after both groups' reads of it completed
@@ -508,7 +509,7 @@ __device__ __forceinline__ void ggemm6(const GemmHdr* __restrict__ hdr, const Ge
                                        const LayerArgs la, uint8_t* lds) {
   constexpr int NWN = BN / WN, NWM = BM / WM;
   constexpr int NW = NWN * NWM;
-  static_assert(NW == 8, "two groups of four waves");
+  static_assert(NW % 8 == 0, "two groups, each with the same number of waves on every SIMD");
   constexpr int FM = WM / 16, FN = WN / 16;
   constexpr uint32_t A_STAGE = BM * kRow3, B_STAGE = BN * kRow3, STAGE = A_STAGE + B_STAGE;
   constexpr int A_INS = BM / 16 / NW, B_INS = BN / 16 / NW;
@@ -520,7 +521,7 @@ __device__ __forceinline__ void ggemm6(const GemmHdr* __restrict__ hdr, const Ge
   const uint32_t t = threadIdx.x, lane = t & 63;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(t >> 6);
   const uint32_t wm = wave / NWN, wn = wave % NWN;
-  const bool lag = wave >= 4;
+  const bool lag = wave >= NW / 2;  // waves w and w + NW / 2 share a SIMD
   const uint32_t N = la.N, K = la.K;
   const uint32_t total = hdr->total_tiles, G = hdr->n_groups;
   const bool out_f32 = la.flags & kOutF32, relu = la.flags & kRelu;
@@ -686,7 +687,7 @@ SAGE_GGEMM3G(ggemm3t_bf16_32x32, 32, 32, 16, 32, 16, 4)
 
 // ping-pong over the direct-to-LDS ring
 #define SAGE_GGEMM6(NAME, BM, BN, WM, WN, S, PRIO)                                                    \
-  extern "C" __global__ __launch_bounds__(512, 1) void NAME(                                           \
+  extern "C" __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN), 1) void NAME(                    \
       const GemmHdr* __restrict__ hdr, const GemmGroup* __restrict__ groups, LayerArgs la) {           \
     __shared__ __attribute__((aligned(1024))) uint8_t lds[S * (BM + BN) * kRow3];                      \
     ggemm6<BM, BN, WM, WN, S, PRIO>(hdr, groups, la, lds);                                             \
