@@ -1,0 +1,90 @@
+"""The C ABI's contract on the GPU: argument and state errors return the
+documented status and change nothing; empty work is a no-op."""
+import torch  # noqa: F401  (imported at collection: the first import on a fresh box is slow)
+import numpy as np
+import pytest
+
+from paper_2404_14691_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _status(fn, *a):
+    from paper_2404_14691_amd import sage as S
+    with pytest.raises(S.SageError) as e:
+        fn(*a)
+    return e.value.status
+
+
+def test_open_rejects_bad_configs(torch_cuda):
+    from paper_2404_14691_amd import sage as S
+    cfg = S.sage_config_default()
+    cfg.chunk_bytes = 65536 + 1
+    assert _status(S.sage_open, 0, cfg) == S.SAGE_EINVAL
+    cfg = S.sage_config_default()
+    cfg.exit_stage_ms = -1.0
+    assert _status(S.sage_open, 0, cfg) == S.SAGE_EINVAL
+    assert _status(S.sage_open, 64, S.sage_config_default()) == S.SAGE_EINVAL
+
+
+def test_setup_and_invoke_argument_errors(sage_ctx_factory, torch_cuda):
+    from paper_2404_14691_amd import sage as S
+    torch = torch_cuda
+    ctx = sage_ctx_factory()
+    w = synth.shared_mlp_bf16_functions(n_fns=1, layers=2, width=256, share_frac=0.0, seed=31)
+    fn = S.fn_register(ctx, S.mlp_desc(S.SAGE_MLP_BF16, 2, 256), [S.make_blob(w.blobs[0])])
+    assert _status(S.sage_last_launch, ctx) == S.SAGE_ENOTFOUND
+    assert _status(S.fn_setup, ctx, fn, 0) == S.SAGE_EINVAL
+    inv = S.fn_setup(ctx, fn, 4)
+    x = synth.bf16_inputs(4, 256, 31, 0)
+    y = np.zeros((4, 256), dtype=np.float32)
+    # wrong byte counts
+    assert _status(S.fn_invoke, ctx, inv, x[:3], y) == S.SAGE_EINVAL
+    assert _status(S.fn_invoke, ctx, inv, x, y[:, :128].copy()) == S.SAGE_EINVAL
+    # the same invocation twice in one batch
+    assert _status(S.fn_invoke_batch, ctx, [inv, inv], [x, x], [y, y]) == S.SAGE_EINVAL
+    # device buffers must be 16-byte aligned
+    dx = torch.zeros(4 * 256 + 8, dtype=torch.int16, device="cuda")
+    dy = torch.zeros(4 * 256, dtype=torch.float32, device="cuda")
+    io = S.SAGE_IO_DEVICE_IN | S.SAGE_IO_DEVICE_OUT
+    assert _status(S.fn_invoke, ctx, inv, (dx.data_ptr() + 2, 4 * 256 * 2), (dy.data_ptr(), 4 * 256 * 4),
+                   io) == S.SAGE_EINVAL
+    # an empty batch is a no-op; the invocation still runs afterwards
+    S.fn_invoke_batch(ctx, [], [], [])
+    S.fn_invoke(ctx, inv, x, y)
+    assert np.isfinite(y).all() and np.abs(y).sum() > 0
+    assert S.sage_last_launch(ctx).endswith(tuple("0123456789"))
+    # a live function cannot be dropped; a released invocation cannot be used
+    assert _status(S.fn_unregister, ctx, fn) == S.SAGE_EBUSY
+    S.fn_release(ctx, inv)
+    assert _status(S.fn_invoke, ctx, inv, x, y) == S.SAGE_ESTATE
+    assert _status(S.fn_release, ctx, inv) == S.SAGE_ESTATE
+    S.fn_unregister(ctx, fn)
+    assert _status(S.fn_setup, ctx, fn, 1) == S.SAGE_ENOTFOUND
+
+
+def test_failed_calls_change_no_counter(sage_ctx_factory, torch_cuda):
+    from paper_2404_14691_amd import sage as S
+    ctx = sage_ctx_factory()
+    w = synth.shared_mlp_bf16_functions(n_fns=1, layers=2, width=256, share_frac=0.0, seed=32)
+    fn = S.fn_register(ctx, S.mlp_desc(S.SAGE_MLP_BF16, 2, 256), [S.make_blob(w.blobs[0])])
+    before = S.sage_get_stats(ctx)
+    for bad in (lambda: S.fn_setup(ctx, fn, 0),
+                lambda: S.fn_register(ctx, S.mlp_desc(S.SAGE_MLP_BF16, 3, 256), [S.make_blob(w.blobs[0])]),
+                lambda: S.sage_read_slot(ctx, 10 ** 6)):
+        with pytest.raises(S.SageError):
+            bad()
+    after = S.sage_get_stats(ctx)
+    assert {k: v for k, v in after.items() if not k.startswith("t_")} == \
+           {k: v for k, v in before.items() if not k.startswith("t_")}
+
+
+def test_zero_length_kernels_are_no_ops(sage_ctx_factory, torch_cuda):
+    from paper_2404_14691_amd import sage as S
+    torch = torch_cuda
+    ctx = sage_ctx_factory()
+    out = torch.full((1,), 7, dtype=torch.int64, device="cuda")
+    S.sage_fingerprint(ctx, out.data_ptr(), 0, out.data_ptr())
+    S.sage_blkcopy(ctx, out.data_ptr(), 0, out.data_ptr())
+    torch.cuda.synchronize()
+    assert int(out.item()) == 7
