@@ -326,7 +326,7 @@ def main():
     ap.add_argument("--only-shared", action="store_true",
                     help="time the shared+batched steps only (for counter runs); no plain path or extras")
     ap.add_argument("--workload", default="sharing",
-                    help="sharing (default) | batching | stencil | mlp_f32 | serving | exit_stages | rw_only")
+                    help="sharing (default) | batching | stencil | mlp_f32 | serving | exit_stages | rw_only | progressive")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (this path has no "

@@ -473,5 +473,89 @@ def rw_only(S, torch, log, reps=3, n_inv=8, nx=512, ny=512, nz=320, sweeps=20, c
                  warm_vs_cold=round(med["cold"] / med["shared"], 3))
 
 
+# ---------------------------------------------------------------- progressive setup
+def progressive(S, torch, log, reps=5, batches=(8, 2048), interval_ms=250.0):
+    """Per-kernel readiness: setup + invoke latency of one BF16 MLP
+    (8 x 4096^2, 256 MiB) whose blocks must all come back, with the whole
+    reload inside fn_setup (off) or with layer l's launch waiting only for
+    layer l's copies (on).  Sources: the function's device memory, the pinned
+    host cache (second exit stage) and its pageable host memory.  Device-side
+    inputs and outputs; outputs of both modes are compared bit for bit."""
+    from paper_2404_14691_amd import synth
+    W, L = 4096, 8
+    fn_bytes = L * W * W * 2
+    w = synth.shared_mlp_bf16_functions(n_fns=2, layers=L, width=W, share_frac=0.0, seed=8)
+    dblobs = [torch.from_numpy(b.view(np.int16)).cuda() for b in w.blobs]
+    desc = S.mlp_desc(S.SAGE_MLP_BF16, L, W)
+    io = S.SAGE_IO_DEVICE_IN | S.SAGE_IO_DEVICE_OUT
+    maxb = max(batches)
+    x = torch.from_numpy(synth.bf16_inputs(maxb, W, 8, 0).view(np.int16)).cuda()
+    outs = {}
+
+    def run(ctx, fn, b, y):
+        t0 = time.perf_counter()
+        inv = S.fn_setup(ctx, fn, b)
+        S.fn_invoke(ctx, inv, (x.data_ptr(), b * W * 2), (y.data_ptr(), b * W * 4), io)
+        S.fn_release(ctx, inv)
+        return (time.perf_counter() - t0) * 1e3
+
+    def case(source, prog, b):
+        cfg = S.sage_config_default()
+        cfg.progressive = prog
+        if source == "host_cache":
+            cfg.pool_budget_bytes = 4 * fn_bytes
+            cfg.exit_stage_ms = interval_ms
+        else:
+            cfg.pool_budget_bytes = fn_bytes  # one function: each setup evicts the other
+        ctx = S.sage_open(0, cfg)
+        y = torch.zeros((b, W), dtype=torch.float32, device="cuda")
+        ms = []
+        try:
+            if source == "device":
+                blobs = [S.make_blob(d.data_ptr(), fn_bytes, where=S.SAGE_SRC_DEVICE) for d in dblobs]
+            else:
+                blobs = [S.make_blob(a) for a in w.blobs]
+            f = S.fn_register(ctx, desc, [blobs[0]])
+            g = None if source == "host_cache" else S.fn_register(ctx, desc, [blobs[1]])
+            for r in range(reps + 1):
+                if g is None:
+                    run(ctx, f, b, y)
+                    time.sleep(1.3 * interval_ms / 1e3)
+                    S.sage_tick(ctx)  # second stage: f's blocks are in the host cache
+                else:
+                    run(ctx, g, 1, y)  # g takes the pool: f's blocks are out
+                torch.cuda.synchronize()
+                t = run(ctx, f, b, y)
+                if r:
+                    ms.append(t)
+            st = S.sage_get_stats(ctx)
+            if source == "host_cache":
+                assert st["host_reloads"] >= reps * w.n_blocks, st["host_reloads"]
+            outs[(source, prog, b)] = y.clone()
+        finally:
+            S.sage_close(ctx)
+        return float(np.median(ms))
+
+    res = {}
+    for source in ("device", "host_cache", "pageable"):
+        for b in batches:
+            off = case(source, 0, b)
+            on = case(source, 1, b)
+            same = bool(torch.equal(outs[(source, 0, b)], outs[(source, 1, b)]))
+            res[f"{source}/b{b}"] = {"off_ms": round(off, 3), "on_ms": round(on, 3), "speedup": round(off / on, 3),
+                                     "outputs_identical": same}
+            log(f"progressive {source} b={b}: {res[f'{source}/b{b}']}")
+            if not same:
+                raise RuntimeError(f"progressive outputs differ: {source} b={b}")
+    gmean = float(np.exp(np.mean([np.log(v["speedup"]) for v in res.values()])))
+    return _line("cold setup+invoke e2e ms, per-layer readiness vs whole-reload setup, 1 MI355X", gmean,
+                 "x geometric-mean speedup", reps, 1, res[f"host_cache/b{maxb}"]["on_ms"],
+                 {"workload": f"progressive setup: 1 BF16 MLP 8 x 4096^2 (256 MiB), every block reloaded (from "
+                              f"device memory, the pinned host cache, pageable host memory), batch {list(batches)}, "
+                              "device I/O"},
+                 "bf16", cases=res)
+
+
 WORKLOADS = {"batching": batching, "stencil": stencil, "mlp_f32": mlp_f32, "serving": serving,
-             "exit_stages": exit_stages, "rw_only": rw_only}
+             "exit_stages": exit_stages, "rw_only": rw_only,
+             "progressive": progressive}

@@ -126,6 +126,14 @@ typedef struct {
    * source remains).  Later setups reload from where the bytes are. */
   double exit_stage_ms;
   size_t host_cache_bytes;   /* host-cache budget for demoted blocks; 0 = no limit */
+  /* 1: per-kernel readiness for the MLP kinds (the kernel executor's check of
+   * section "Taxon Shim", made per layer).  A setup whose reload crosses the
+   * host link (host cache or host source) returns once the copies are
+   * issued; layer l of the body then waits only for the copies holding
+   * layer l's weights, so early layers compute while later ones are still
+   * arriving.  0 (default), and reloads from device sources: fn_setup
+   * returns with every block resident. */
+  uint32_t progressive;
 } sage_config;
 
 typedef struct {

@@ -26,6 +26,7 @@ static void demote(Ctx& c, const std::vector<uint32_t>& due) {
   Pool& P = c.pool;
   Ring& R = c.ring;
   const size_t per = std::min<size_t>(R.chunk / kBlock, R.cap[0]);
+  HIPX(hipEventSynchronize(R.ev[0]));    // slot 0's last batch (e.g. of a reload) has read its buffers
   HIPX(hipEventSynchronize(R.ev_c[0]));  // slot 0's last registration COPY has read its buffers
   for (size_t i = 0; i < due.size(); i += per) {
     const size_t n = std::min(per, due.size() - i);
@@ -47,6 +48,7 @@ static void demote(Ctx& c, const std::vector<uint32_t>& due) {
       P.evict(cl, h != kNone);
       if (h == kNone) continue;
       Class& k = P.cls[cl];
+      P.host_release(cl);  // an older host copy not yet released after its reload
       k.hbuf = h;
       k.hoff = (uint32_t)j;
       k.hgen = P.demotions;
@@ -72,6 +74,7 @@ void advance_exit(Ctx& c) {
   const double now = now_ms();
   Pool& P = c.pool;
   if (c.cfg.share) {
+    settle_reloads(c, false);
     std::vector<uint32_t> due;
     for (uint32_t cl = P.lru_front(); cl != kNone; cl = P.cls[cl].lru_next) {
       if (now - P.cls[cl].idle_since < T) break;  // the LRU list is in idle order

@@ -122,6 +122,7 @@ struct Class {
   uint32_t hbuf = kNone;      // host-cache buffer holding its bytes after demotion, or kNone
   uint32_t hoff = 0;          // block index inside that buffer
   uint64_t hgen = 0;          // demotion number of its current host copy
+  uint64_t fill = 0;          // number of the progressive reload that last filled its slot
 };
 
 // Pinned host buffer of the host cache: blocks demoted together.
@@ -188,6 +189,9 @@ class Pool {
   std::vector<uint32_t> free_;
   std::vector<uint32_t> free_cls_;
   std::vector<uint32_t> free_hbufs_;
+  std::multimap<uint32_t, uint8_t*> spare_host_;  // released pinned buffers by size in blocks
+  uint64_t spare_bytes_ = 0;
+  static constexpr uint64_t kSpareHostBytes = 1ull << 30;
   FpIndex index_;
   uint32_t lru_head_ = kNone, lru_tail_ = kNone;
   uint32_t mark_ = 0;
@@ -248,6 +252,7 @@ struct Fn {
   int live = 0;
   Module* mod = nullptr;
   hipEvent_t ready = nullptr;         // data of the function is in place
+  std::vector<hipEvent_t> seg;        // progressive reload: layer l's blocks are in place
   uint32_t block_len(uint32_t b) const;
   const uint8_t* block_src(uint32_t b, bool* dev) const;
 };
@@ -336,6 +341,8 @@ class Worker {
 };
 
 // ------------------------------------------------------------------ context
+constexpr size_t kReloadStageBlocks = 4096;  // reload staging: 256 MiB, cycled by region
+
 struct Ctx {
   int device = 0;
   int cus = 256;
@@ -358,6 +365,25 @@ struct Ctx {
   uint64_t* h_stage = nullptr;               // pinned staging for block-table uploads
   hipEvent_t stage_ev = nullptr;             // last upload from h_stage (on ctl)
   hipEvent_t ctl_ev = nullptr;               // marks the control stream for other streams to wait on
+  // progressive reloads (cfg.progressive): the last one's function and its
+  // completion (on ctl, after every copy stream joined), the copy streams'
+  // join markers, pinned op list and staging (the op list's upload marked by
+  // prog_ops_ev), and what is released once the last one has completed:
+  // host-cache copies that fed it and its device staging
+  uint64_t prog_fn = 0;
+  uint64_t reload_seq = 0, reload_seq_done = 0;  // progressive reloads issued / known complete
+  hipEvent_t reload_done = nullptr;
+  std::vector<hipEvent_t> join_ev;
+  uint8_t* prog_hops = nullptr;
+  size_t prog_hops_cap = 0;
+  hipEvent_t prog_ops_ev = nullptr;
+  // reload staging: device area, one region per batch, each with the event
+  // of the batch that last used it; pageable sources go through ring slots
+  uint8_t* rstage_dev = nullptr;
+  std::vector<hipEvent_t> rstage_ev;
+  size_t rstage_next = 0, rhost_next = 0;
+  std::vector<std::pair<uint32_t, uint64_t>> deferred_host;  // (class, host generation)
+  std::vector<void*> deferred_dev;                           // DevCache buffers
   size_t h_stage_cap = 0;
   std::map<std::string, TuneEntry> tune;     // "width:shape" -> time of one full wave of tiles (ms)
   // counters
@@ -397,6 +423,12 @@ void register_shared(Ctx& c, Fn& f);
 void copy_private(Ctx& c, Fn& f, uint8_t* dst, hipStream_t s);
 void reload_classes(Ctx& c, Fn& f, const std::vector<uint32_t>& missing);
 void refresh_table(Ctx& c, Fn& f);
+// Progressive reloads: release the host-cache copies of completed ones
+// (waiting for the last one first if `wait`); whether f's own reload may
+// still be landing, its layers then gated one by one.
+void settle_reloads(Ctx& c, bool wait);
+bool reload_landing(Ctx& c, const Fn& f);
+bool reload_feeds(Ctx& c, const Fn& f);  // a progressive reload in flight fills a class of f
 
 // grouped execution
 struct Call {

@@ -84,6 +84,9 @@ void Pool::destroy() {
   for (uint8_t* s : segs_) (void)hipFree(s);
   for (HostBuf& h : hbufs)
     if (h.p) (void)hipHostFree(h.p);
+  for (auto& kv : spare_host_) (void)hipHostFree(kv.second);
+  spare_host_.clear();
+  spare_bytes_ = 0;
   hbufs.clear();
   free_hbufs_.clear();
   host_lru.clear();
@@ -213,10 +216,17 @@ void Pool::drop_class(uint32_t c) {
 }
 
 uint32_t Pool::host_buffer(uint32_t blocks, uint64_t budget_bytes) {
-  const uint64_t bytes = (uint64_t)blocks * kBlock;
+  uint64_t bytes = (uint64_t)blocks * kBlock;
   if (budget_bytes && host_bytes + bytes > budget_bytes) return kNone;
   uint8_t* p = nullptr;
-  if (hipHostMalloc((void**)&p, bytes, hipHostMallocDefault) != hipSuccess) {
+  // a spare pinned buffer of the same size first: pinning and unpinning cost
+  // milliseconds per buffer, more than moving its bytes over the link
+  auto it = spare_host_.find(blocks);
+  if (it != spare_host_.end()) {
+    p = it->second;
+    spare_host_.erase(it);
+    spare_bytes_ -= bytes;
+  } else if (hipHostMalloc((void**)&p, bytes, hipHostMallocDefault) != hipSuccess) {
     (void)hipGetLastError();
     return kNone;
   }
@@ -238,8 +248,14 @@ void Pool::host_release(uint32_t c) {
   if (k.hbuf == kNone) return;
   HostBuf& h = hbufs[k.hbuf];
   if (--h.live == 0) {
-    (void)hipHostFree(h.p);
-    host_bytes -= (uint64_t)h.blocks * kBlock;
+    const uint64_t bytes = (uint64_t)h.blocks * kBlock;
+    if (spare_bytes_ + bytes <= kSpareHostBytes) {
+      spare_host_.emplace(h.blocks, h.p);
+      spare_bytes_ += bytes;
+    } else {
+      (void)hipHostFree(h.p);
+    }
+    host_bytes -= bytes;
     h = HostBuf{};
     free_hbufs_.push_back(k.hbuf);
   }

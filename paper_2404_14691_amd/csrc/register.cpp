@@ -79,6 +79,7 @@ void ring_destroy(Ctx& c) {
 static void ring_reserve(Ctx& c, int slot, size_t nblk) {
   Ring& R = c.ring;
   if (R.cap[slot] >= nblk) return;
+  HIPX(hipEventSynchronize(R.ev[slot]));
   HIPX(hipEventSynchronize(R.ev_c[slot]));  // an in-flight COPY may still read the old op buffers
   (void)hipFree(R.dops_c[slot]);
   (void)hipHostFree(R.hops_c[slot]);
@@ -255,6 +256,7 @@ void register_shared(Ctx& c, Fn& f) {
   auto issue = [&](Chunk& ch) {
     ch.slot = free_slots.back();
     free_slots.pop_back();
+    HIPX(hipEventSynchronize(R.ev[ch.slot]));  // e.g. a progressive reload still reading the slot
     ring_reserve(c, ch.slot, ch.nblk);
     hipStream_t s = stream_of(ch.slot);
     const Src& src = f.srcs[ch.blob];
@@ -435,7 +437,7 @@ void copy_private(Ctx& c, Fn& f, uint8_t* dst, hipStream_t s) {
       for (uint64_t off = 0; off < src.n; off += R.chunk, k++) {
         const int slot = (int)(k % R.slots);
         hipStream_t cs = c.streams[slot % c.streams.size()];
-        if (k >= R.slots) HIPX(hipEventSynchronize(R.ev[slot]));  // slot's previous copy done
+        HIPX(hipEventSynchronize(R.ev[slot]));  // slot's previous copy done
         const uint64_t n = std::min<uint64_t>(R.chunk, src.n - off);
         fill_parallel(c, R.host[slot], src.p + off, n);
         HIPX(hipMemcpyAsync(d + off, R.host[slot], n, hipMemcpyHostToDevice, cs));
@@ -450,91 +452,274 @@ void copy_private(Ctx& c, Fn& f, uint8_t* dst, hipStream_t s) {
 // ------------------------------------------------------------ reloads
 // Bring evicted classes of `f` back: a demoted class from its host-cache
 // copy, any other from the source block of `f` that first referenced it (the
-// source is read-only and was verified equal at registration).  Pinned host
-// bytes reach the device staging buffer in one DMA per contiguous run.
-void reload_classes(Ctx& c, Fn& f, const std::vector<uint32_t>& missing) {
-  if (missing.empty()) return;
+// source is read-only and was verified equal at registration).
+//
+// The classes go in the order of their first block in `f`, so for the MLP
+// kinds layer l's weights are complete once every class first used at or
+// before layer l's last block has landed.  Every class gets its slot, and the
+// block table and one op list for the whole reload go out, before any copy.
+// The copies are issued in batches of at most one chunk, never across a
+// layer's end, round the copy streams.  Host bytes pass through a device
+// staging area of kReloadStageBlocks blocks cut into one region per batch; a
+// region is taken again once the batch that last used it (in this reload or
+// an earlier one) has completed, so the host waits only when a reload is
+// larger than the staging area.  Pinned bytes (the host cache) reach it in
+// one DMA per contiguous run; pageable source bytes first go, one parallel
+// memcpy per run, to the pinned buffer of a registration ring slot (taken
+// once the slot's event has completed); device sources are copied in place.
+//
+// Progressive (cfg.progressive, MLP kinds, some bytes over the host link):
+// at each layer's end the copy streams are joined into the control stream
+// and f.seg[l] is recorded there, and the call returns without waiting;
+// layer l's launch waits for f.seg[l] (the kernel executor's readiness
+// check, per kernel).  Otherwise the call waits for the whole reload.  Either
+// way f.ready and reload_done mark its end, and its op list and the
+// host-cache copies that fed it are released once it has completed.
+void reload_classes(Ctx& c, Fn& f, const std::vector<uint32_t>& missing_in) {
+  if (missing_in.empty()) return;
   const double t_start = now_ms();
   Pool& P = c.pool;
-  Ring& R = c.ring;
+  settle_reloads(c, false);
   std::unordered_map<uint32_t, uint32_t> first;
   for (uint32_t b = 0; b < f.n_blocks; b++) first.emplace(f.cls[b], b);
+  std::vector<uint32_t> missing = missing_in;
+  const size_t n = missing.size();
+  std::stable_sort(missing.begin(), missing.end(),
+                   [&](uint32_t a, uint32_t b) { return first.at(a) < first.at(b); });
+  const bool mlp = !is_grid(f.d.kind) && f.d.layers > 0;
+  const uint32_t n_seg = mlp ? f.d.layers : 1;
+  std::vector<size_t> seg_end(n_seg, n);
+  if (mlp) {
+    const uint64_t lbytes = (uint64_t)f.d.width * f.d.width * (f.d.kind == SAGE_MLP_F32 ? 4 : 2);
+    for (uint32_t l = 0, j = 0; l < n_seg; l++) {
+      const uint32_t last = (uint32_t)(((uint64_t)(l + 1) * lbytes - 1) / kBlock);
+      while (j < n && first.at(missing[j]) <= last) j++;
+      seg_end[l] = j;
+    }
+    seg_end.back() = n;
+  }
   const uint32_t mark = P.new_mark();
   for (uint32_t cl : f.distinct) P.cls[cl].mark = mark;
   auto protect = [&](uint32_t cl) { return P.cls[cl].mark == mark; };
-  // Batches go round the staging ring on the copy streams, so staging of one
-  // overlaps the copies of the others.  Every stream first waits for the
-  // control stream: a freed slot may still be the target of a registration
-  // copy in flight there.
-  HIPX(hipEventRecord(c.ctl_ev, c.ctl));
-  for (size_t k = 0; k < R.slots; k++) HIPX(hipEventSynchronize(R.ev_c[k]));
-  for (hipStream_t cs : c.streams) HIPX(hipStreamWaitEvent(cs, c.ctl_ev, 0));
-  size_t i = 0, batch = 0;
-  std::vector<uint32_t> from_host;
-  while (i < missing.size()) {
-    const int slot = (int)(batch % R.slots);
-    hipStream_t s = c.streams[slot % c.streams.size()];
-    if (batch >= R.slots) HIPX(hipEventSynchronize(R.ev[slot]));  // the slot's previous batch is done
-    batch++;
-    const size_t per_slot = std::min<size_t>(R.chunk / kBlock, R.cap[slot]);
-    BlkOp* ops = R.hops[slot];
-    uint32_t nops = 0;
-    size_t staged = 0;
-    // runs of contiguous pinned host blocks reach the staging buffer in one DMA each
-    const uint8_t* run_src = nullptr;
-    size_t run_at = 0, run_n = 0;
-    auto flush_run = [&] {
-      if (run_n)
-        HIPX(hipMemcpyAsync(R.dev[slot] + run_at * kBlock, run_src, run_n * kBlock, hipMemcpyHostToDevice, s));
-      run_n = 0;
-    };
-    while (i < missing.size() && nops < per_slot) {
-      const uint32_t cl = missing[i++];
-      Class& k = P.cls[cl];
-      const uint32_t len = k.len;
-      const uint32_t slotid = P.alloc_slot(protect);
-      if (slotid == kNone) fail(SAGE_ENOMEM, "pool full during reload");
-      k.slot = slotid;
-      P.index_add(cl);
-      bool dev = false;
-      const uint8_t* hsrc = nullptr;  // pinned host bytes to stage, if any
-      if (k.hbuf != kNone) {
-        // the bytes wait in the pinned host cache (second or third stage)
-        hsrc = P.hbufs[k.hbuf].p + (uint64_t)k.hoff * kBlock;
-        from_host.push_back(cl);
-        c.host_reloads++;
-      } else {
-        const uint8_t* src = f.block_src(first.at(cl), &dev);
-        if (dev) {
-          ops[nops++] = BlkOp{(uint64_t)src, (uint64_t)P.addr(slotid), len, 0};
-        } else {
-          std::memcpy(R.host[slot] + staged * kBlock, src, len);
-          hsrc = R.host[slot] + staged * kBlock;
-        }
-      }
-      if (hsrc) {
-        if (!(run_n && hsrc == run_src + run_n * kBlock)) {
-          flush_run();
-          run_src = hsrc;
-          run_at = staged;
-        }
-        run_n++;
-        ops[nops++] = BlkOp{(uint64_t)(R.dev[slot] + staged * kBlock), (uint64_t)P.addr(slotid), len, 0};
-        staged++;
-      }
-      c.h2d += len;
-      c.reloads++;
+  for (size_t j = 0; j < n; j++) {
+    const uint32_t slotid = P.alloc_slot(protect);
+    if (slotid == kNone) {
+      for (size_t r = 0; r < j; r++) P.evict(missing[r]);
+      fail(SAGE_ENOMEM, "pool full during reload");
     }
-    flush_run();
-    HIPX(hipMemcpyAsync(R.dops[slot], ops, nops * sizeof(BlkOp), hipMemcpyHostToDevice, s));
-    const int tok = c.timer.start("blkcopy", s, 1);
-    HIPX(launch_blkcopy(R.dops[slot], nops, R.dres[slot], c.max_groups_copy(), s));
-    c.timer.stop(tok, s);
-    HIPX(hipEventRecord(R.ev[slot], s));
+    P.cls[missing[j]].slot = slotid;
+    P.index_add(missing[j]);
   }
-  for (hipStream_t cs : c.streams) HIPX(hipStreamSynchronize(cs));
-  for (uint32_t cl : from_host) P.host_release(cl);  // back in HBM: the host copy goes
+  // where each class comes from: 0 device source, 1 host cache (pinned,
+  // whole blocks), 2 registered host source (through pinned staging)
+  std::vector<uint8_t> kind(n);
+  std::vector<const uint8_t*> src(n);
+  size_t n_host = 0, n_page = 0;
+  for (size_t j = 0; j < n; j++) {
+    const Class& k = P.cls[missing[j]];
+    bool dev = false;
+    if (k.hbuf != kNone) {
+      kind[j] = 1;
+      src[j] = P.hbufs[k.hbuf].p + (uint64_t)k.hoff * kBlock;
+    } else {
+      src[j] = f.block_src(first.at(missing[j]), &dev);
+      kind[j] = dev ? 0 : 2;
+    }
+    n_host += kind[j] != 0;
+    n_page += kind[j] == 2;
+  }
+  const bool gate = c.cfg.progressive && mlp && n_host > 0;
+  // batches and their staging regions
+  const size_t per_batch = std::min<size_t>(std::max<size_t>(1, c.ring.chunk / kBlock), kReloadStageBlocks);
+  const size_t n_regions = kReloadStageBlocks / per_batch;
+  if (n_host && !c.rstage_dev) HIPX(hipMalloc((void**)&c.rstage_dev, kReloadStageBlocks * kBlock));
+  Ring& R = c.ring;
+  while (c.rstage_ev.size() < n_regions) {
+    hipEvent_t e;
+    HIPX(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    c.rstage_ev.push_back(e);
+  }
+  struct Batch {
+    size_t j0, j1;
+    uint32_t seg;
+    int region;  // -1: no host bytes
+  };
+  std::vector<Batch> batches;
+  std::vector<size_t> stage_at(n, 0);
+  for (uint32_t l = 0, j = 0; l < n_seg; l++) {
+    while (j < seg_end[l]) {
+      Batch bt{j, std::min(seg_end[l], j + per_batch), l, -1};
+      size_t h = 0;
+      for (size_t q = bt.j0; q < bt.j1; q++)
+        if (kind[q]) {
+          if (bt.region < 0) bt.region = (int)(c.rstage_next++ % n_regions);
+          stage_at[q] = (size_t)bt.region * per_batch + h++;
+        }
+      batches.push_back(bt);
+      j = (uint32_t)bt.j1;
+    }
+  }
+  // the op list: the previous reload's upload has read the pinned buffer
+  HIPX(hipEventSynchronize(c.prog_ops_ev));
+  if (c.prog_hops_cap < n * sizeof(BlkOp)) {
+    if (c.prog_hops) HIPX(hipHostFree(c.prog_hops));
+    c.prog_hops = nullptr;
+    c.prog_hops_cap = 0;
+    HIPX(hipHostMalloc((void**)&c.prog_hops, n * sizeof(BlkOp), hipHostMallocDefault));
+    c.prog_hops_cap = n * sizeof(BlkOp);
+  }
+  uint8_t* dmeta = (uint8_t*)c.cache.get(n * (sizeof(BlkOp) + 4));
+  c.deferred_dev.push_back(dmeta);
+  BlkOp* dops = reinterpret_cast<BlkOp*>(dmeta);
+  uint32_t* dres = reinterpret_cast<uint32_t*>(dmeta + n * sizeof(BlkOp));
+  BlkOp* hops = reinterpret_cast<BlkOp*>(c.prog_hops);
+  for (size_t j = 0; j < n; j++) {
+    const Class& k = P.cls[missing[j]];
+    const uint64_t from = kind[j] ? (uint64_t)(c.rstage_dev + stage_at[j] * kBlock) : (uint64_t)src[j];
+    hops[j] = BlkOp{from, (uint64_t)P.addr(k.slot), k.len, 0};
+    c.h2d += k.len;
+    c.reloads++;
+    if (kind[j] == 1) c.host_reloads++;
+  }
+  // control stream: op list, block table, then the mark the copy streams start
+  // behind (a freed slot may still be the target of a copy in flight there)
+  HIPX(hipMemcpyAsync(dops, hops, n * sizeof(BlkOp), hipMemcpyHostToDevice, c.ctl));
+  HIPX(hipEventRecord(c.prog_ops_ev, c.ctl));
+  refresh_table(c, f);
+  HIPX(hipEventRecord(c.ctl_ev, c.ctl));
+  for (hipStream_t cs : c.streams) HIPX(hipStreamWaitEvent(cs, c.ctl_ev, 0));
+  while (gate && f.seg.size() < f.d.layers) {
+    hipEvent_t e;
+    HIPX(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    f.seg.push_back(e);
+  }
+  std::vector<bool> dirty(c.streams.size(), false);
+  auto join = [&] {  // the control stream waits for the copy streams used since the last join
+    for (size_t k = 0; k < c.streams.size(); k++) {
+      if (!dirty[k]) continue;
+      HIPX(hipEventRecord(c.join_ev[k], c.streams[k]));
+      HIPX(hipStreamWaitEvent(c.ctl, c.join_ev[k], 0));
+      dirty[k] = false;
+    }
+  };
+  size_t bi = 0;
+  for (uint32_t l = 0; l < n_seg; l++) {
+    for (; bi < batches.size() && batches[bi].seg == l; bi++) {
+      const Batch& bt = batches[bi];
+      const size_t si = bi % c.streams.size();
+      hipStream_t s = c.streams[si];
+      if (bt.region >= 0) {
+        HIPX(hipEventSynchronize(c.rstage_ev[bt.region]));  // its last batch has read the region
+        // pageable source runs into a ring slot's pinned buffer, one parallel memcpy each
+        int hs = -1;
+        size_t hn = 0;
+        std::vector<const uint8_t*> pinned_at(bt.j1 - bt.j0, nullptr);
+        uint8_t* cp_to = nullptr;
+        const uint8_t* cp_from = nullptr;
+        size_t cp_n = 0;
+        for (size_t q = bt.j0; q < bt.j1; q++) {
+          if (kind[q] != 2) continue;
+          if (hs < 0) {
+            hs = (int)(c.rhost_next++ % R.slots);
+            HIPX(hipEventSynchronize(R.ev[hs]));  // the slot's last user has read its buffer
+          }
+          uint8_t* to = R.host[hs] + hn++ * kBlock;
+          pinned_at[q - bt.j0] = to;
+          if (!(cp_n && cp_n % kBlock == 0 && to == cp_to + cp_n && src[q] == cp_from + cp_n)) {
+            if (cp_n) fill_parallel(c, cp_to, cp_from, cp_n);
+            cp_to = to;
+            cp_from = src[q];
+            cp_n = 0;
+          }
+          cp_n += P.cls[missing[q]].len;
+        }
+        if (cp_n) fill_parallel(c, cp_to, cp_from, cp_n);
+        // pinned bytes to the device staging, one DMA per run contiguous on both sides
+        const uint8_t* run_src = nullptr;
+        size_t run_at = 0, run_n = 0;
+        auto flush = [&] {
+          if (run_n)
+            HIPX(hipMemcpyAsync(c.rstage_dev + run_at * kBlock, run_src, run_n * kBlock, hipMemcpyHostToDevice,
+                                s));
+          run_n = 0;
+        };
+        for (size_t q = bt.j0; q < bt.j1; q++) {
+          if (!kind[q]) continue;
+          const uint8_t* from = kind[q] == 1 ? src[q] : pinned_at[q - bt.j0];
+          if (!(run_n && from == run_src + run_n * kBlock && stage_at[q] == run_at + run_n)) {
+            flush();
+            run_src = from;
+            run_at = stage_at[q];
+          }
+          run_n++;
+        }
+        flush();
+        if (hs >= 0) HIPX(hipEventRecord(R.ev[hs], s));
+      }
+      const int tok = c.timer.start("blkcopy", s, 1);
+      HIPX(launch_blkcopy(dops + bt.j0, (uint32_t)(bt.j1 - bt.j0), dres + bt.j0, c.max_groups_copy(), s));
+      c.timer.stop(tok, s);
+      if (bt.region >= 0) HIPX(hipEventRecord(c.rstage_ev[bt.region], s));
+      dirty[si] = true;
+    }
+    if (gate) {
+      join();
+      HIPX(hipEventRecord(f.seg[l], c.ctl));
+    }
+  }
+  join();
+  HIPX(hipEventRecord(f.ready, c.ctl));
+  HIPX(hipEventRecord(c.reload_done, c.ctl));
+  c.reload_seq++;
+  for (uint32_t cl : missing) P.cls[cl].fill = c.reload_seq;
+  c.prog_fn = gate ? f.id : 0;
+  for (size_t q = 0; q < n; q++)
+    if (kind[q] == 1) c.deferred_host.push_back({missing[q], P.cls[missing[q]].hgen});
+  if (!gate) settle_reloads(c, true);  // resident on return; the host copies go
   c.t_reload += now_ms() - t_start;
+}
+
+// Whether every progressive reload issued so far has completed.
+static bool reloads_done(Ctx& c) {
+  if (c.reload_seq_done == c.reload_seq) return true;
+  const hipError_t q = hipEventQuery(c.reload_done);
+  if (q == hipErrorNotReady) {
+    (void)hipGetLastError();
+    return false;
+  }
+  HIPX(q);
+  c.reload_seq_done = c.reload_seq;
+  return true;
+}
+
+void settle_reloads(Ctx& c, bool wait) {
+  if (c.deferred_host.empty() && c.deferred_dev.empty()) return;
+  if (wait) {
+    HIPX(hipEventSynchronize(c.reload_done));
+    c.reload_seq_done = c.reload_seq;
+  } else if (!reloads_done(c)) {
+    return;
+  }
+  Pool& P = c.pool;
+  for (const auto& [cl, gen] : c.deferred_host) {
+    const Class& k = P.cls[cl];
+    if (k.alive && k.hbuf != kNone && k.hgen == gen) P.host_release(cl);
+  }
+  c.deferred_host.clear();
+  for (void* q : c.deferred_dev) c.cache.put(q);
+  c.deferred_dev.clear();
+}
+
+bool reload_landing(Ctx& c, const Fn& f) {
+  if (c.prog_fn != f.id || f.seg.size() != f.d.layers) return false;
+  return !reloads_done(c);
+}
+
+bool reload_feeds(Ctx& c, const Fn& f) {
+  if (reloads_done(c)) return false;
+  for (uint32_t cl : f.distinct)
+    if (c.pool.cls[cl].fill > c.reload_seq_done) return true;
+  return false;
 }
 
 // Rebuild the device block table of `f` when any of its classes moved.

@@ -234,10 +234,15 @@ sage_status sage_open(int device, const sage_config* cfg, sage_ctx** out) {
     HIPX(hipStreamCreateWithFlags(&c.ctl, hipStreamNonBlocking));
     HIPX(hipEventCreateWithFlags(&c.stage_ev, hipEventDisableTiming));
     HIPX(hipEventCreateWithFlags(&c.ctl_ev, hipEventDisableTiming));
+    HIPX(hipEventCreateWithFlags(&c.reload_done, hipEventDisableTiming));
+    HIPX(hipEventCreateWithFlags(&c.prog_ops_ev, hipEventDisableTiming));
     for (uint32_t i = 0; i < c.cfg.streams; i++) {
       hipStream_t s;
       HIPX(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
       c.streams.push_back(s);
+      hipEvent_t e;
+      HIPX(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      c.join_ev.push_back(e);
     }
     size_t free_b = 0, total_b = 0;
     HIPX(hipMemGetInfo(&free_b, &total_b));
@@ -246,6 +251,7 @@ sage_status sage_open(int device, const sage_config* cfg, sage_ctx** out) {
     if (budget < 1) fail(SAGE_EINVAL, "pool budget below one block");
     c.pool.init(budget, (size_t)std::min<uint64_t>(16384, budget));
     ring_init(c);
+    if (c.cfg.share) HIPX(hipMalloc((void**)&c.rstage_dev, kReloadStageBlocks * kBlock));  // reload staging
     flights_init(c);
     tune_load(c);
     c.worker.start(device);
@@ -268,8 +274,10 @@ sage_status sage_close(sage_ctx* p) {
       (void)hipSetDevice(c.device);
       (void)hipDeviceSynchronize();
       flights_destroy(c);
-      for (auto& kv : c.fns)
+      for (auto& kv : c.fns) {
         if (kv.second->ready) (void)hipEventDestroy(kv.second->ready);
+        for (hipEvent_t e : kv.second->seg) (void)hipEventDestroy(e);
+      }
       c.fns.clear();
       c.invs.clear();
       c.cache.release_all();
@@ -284,6 +292,14 @@ sage_status sage_close(sage_ctx* p) {
       c.h_stage = nullptr;
       if (c.stage_ev) (void)hipEventDestroy(c.stage_ev);
       if (c.ctl_ev) (void)hipEventDestroy(c.ctl_ev);
+      if (c.reload_done) (void)hipEventDestroy(c.reload_done);
+      if (c.prog_ops_ev) (void)hipEventDestroy(c.prog_ops_ev);
+      if (c.prog_hops) (void)hipHostFree(c.prog_hops);
+      if (c.rstage_dev) (void)hipFree(c.rstage_dev);
+      for (hipEvent_t e : c.rstage_ev) (void)hipEventDestroy(e);
+      c.deferred_dev.clear();
+      c.deferred_host.clear();
+      for (hipEvent_t e : c.join_ev) (void)hipEventDestroy(e);
       c.timer.destroy();
       for (hipStream_t s : c.streams) (void)hipStreamDestroy(s);
       (void)hipStreamDestroy(c.ctl);
@@ -378,15 +394,18 @@ sage_status fn_unregister(sage_ctx* p, sage_fn id) {
     Fn& f = fn_of(c, id);
     if (f.live > 0) fail(SAGE_EBUSY, "function has %d live setups", f.live);
     for (size_t i = 0; i < c.flights.size(); i++) finish_flight(c, (int)i);
+    // copies from f's sources or host-cache copies may still be in flight;
+    // the caller may free the sources on return
+    HIPX(hipEventSynchronize(f.ready));
+    settle_reloads(c, true);
     Pool& P = c.pool;
     for (uint32_t cl : f.cls) P.cls[cl].members--;
     for (uint32_t cl : f.distinct)
       if (P.cls[cl].members == 0) P.drop_class(cl);
     c.logical -= f.ro_bytes;
-    // copies from f's sources may still be in flight; the caller may free them on return
-    HIPX(hipEventSynchronize(f.ready));
     if (f.d_table) c.cache.put(f.d_table);
     (void)hipEventDestroy(f.ready);
+    for (hipEvent_t e : f.seg) (void)hipEventDestroy(e);
     c.fns.erase(id);
   });
 }
@@ -508,6 +527,7 @@ sage_status sage_get_stats(sage_ctx* p, sage_stats* out) {
     std::lock_guard<std::recursive_mutex> lk(c.mu);
     HIPX(hipSetDevice(c.device));
     advance_exit(c);
+    settle_reloads(c, false);
     std::memset(out, 0, sizeof *out);
     const Pool& P = c.pool;
     for (const Class& k : P.cls) {

@@ -57,7 +57,8 @@ class sage_config(C.Structure):
     _fields_ = [("ring_slots", C.c_size_t), ("chunk_bytes", C.c_size_t), ("streams", C.c_uint32),
                 ("fill_threads", C.c_uint32), ("inflight_groups", C.c_uint32), ("share", C.c_uint32),
                 ("batch", C.c_uint32), ("serial_setup", C.c_uint32), ("pool_budget_bytes", C.c_size_t),
-                ("tune_cache", C.c_char_p), ("exit_stage_ms", C.c_double), ("host_cache_bytes", C.c_size_t)]
+                ("tune_cache", C.c_char_p), ("exit_stage_ms", C.c_double), ("host_cache_bytes", C.c_size_t),
+                ("progressive", C.c_uint32)]
 
 
 class sage_stats(C.Structure):
