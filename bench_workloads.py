@@ -59,12 +59,8 @@ def batching(S, torch, log, steps=10, warmup=2):
         t0 = time.perf_counter()
         fn = S.fn_register(ctx, desc, blob)
         reg = (time.perf_counter() - t0) * 1e3
-        setup = []
-        invs = []
-        for b in batches:
-            t0 = time.perf_counter()
-            invs.append(S.fn_setup(ctx, fn, b))
-            setup.append((time.perf_counter() - t0) * 1e3)
+        # the requests arrive together: one admission call, each request's own time
+        invs, setup = S.fn_setup_batch(ctx, [fn] * len(batches), batches, timed=True)
         setup[0] += reg
         S.fn_invoke_batch(ctx, invs, ins, outs, io)
         S.fn_release_batch(ctx, invs)

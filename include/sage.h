@@ -169,7 +169,7 @@ typedef struct {
   uint64_t module_loads;    /* code objects loaded (first load included) */
   uint64_t module_unloads;  /* code objects unloaded by the multi-stage exit */
   double t_module_ms;       /* host wall time in code-object loads */
-  double t_reload_ms;       /* host wall time in fn_setup reloads of missing blocks */
+  double t_reload_ms;       /* host wall time in fn_setup reloads of missing blocks (issue only, when progressive) */
 } sage_stats;
 
 /* ----------------------------------------------------------------- context */
@@ -220,8 +220,11 @@ sage_status sage_tick(sage_ctx* ctx);
  * runnable; the analogue of SageLoadToGPU() (section "Programming of
  * Function Handle").  Admission: the function's evicted blocks are reloaded
  * (evicting unreferenced blocks of other functions, least recently released
- * first) and each distinct block of the function gains one reference.  With
- * share=0 the read-only data is copied into a private buffer instead.
+ * first) and each distinct block of the function gains one reference.  The
+ * call returns with the blocks resident, except with `progressive` set and
+ * blocks coming over the host link: then it returns once their copies are
+ * issued, and the body waits for them layer by layer.  With share=0 the
+ * read-only data is copied into a private buffer instead.
  * Errors: ENOMEM (cannot admit; nothing changed), ENOTFOUND, EINVAL. */
 sage_status fn_setup(sage_ctx* ctx, sage_fn fn, uint32_t batch, sage_inv* out);
 
@@ -231,9 +234,10 @@ sage_status fn_setup(sage_ctx* ctx, sage_fn fn, uint32_t batch, sage_inv* out);
 
 /* fn_setup for n requests (fns[i], batches[i]) in order; stops at the first
  * failure, returning its status, with out[0..k) set for the k that
- * succeeded (*n_done = k). */
+ * succeeded (*n_done = k).  setup_ms (may be NULL; n entries) receives each
+ * request's own setup time in ms, host wall clock inside the library. */
 sage_status fn_setup_batch(sage_ctx* ctx, size_t n, const sage_fn* fns, const uint32_t* batches, sage_inv* out,
-                           size_t* n_done);
+                           size_t* n_done, double* setup_ms);
 
 /* Run one set-up invocation: in = X / u0 as described in sage_fn_desc,
  * out = Y / u.  The body waits for the function's data (the kernel-executor

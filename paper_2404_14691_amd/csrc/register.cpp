@@ -667,7 +667,13 @@ void reload_classes(Ctx& c, Fn& f, const std::vector<uint32_t>& missing_in) {
       HIPX(hipEventRecord(f.seg[l], c.ctl));
     }
   }
-  join();
+  if (gate) {
+    join();
+  } else {
+    // the host waits for the copy streams themselves; the marks below then
+    // follow only the control stream's own uploads
+    for (hipStream_t cs : c.streams) HIPX(hipStreamSynchronize(cs));
+  }
   HIPX(hipEventRecord(f.ready, c.ctl));
   HIPX(hipEventRecord(c.reload_done, c.ctl));
   c.reload_seq++;

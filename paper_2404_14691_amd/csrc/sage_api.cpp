@@ -422,7 +422,7 @@ sage_status fn_setup(sage_ctx* p, sage_fn id, uint32_t batch, sage_inv* out) {
 }
 
 sage_status fn_setup_batch(sage_ctx* p, size_t n, const sage_fn* fns, const uint32_t* batches, sage_inv* out,
-                           size_t* n_done) {
+                           size_t* n_done, double* setup_ms) {
   size_t k = 0;
   const sage_status st = guard([&] {
     Ctx& c = ctx_of(p);
@@ -430,7 +430,12 @@ sage_status fn_setup_batch(sage_ctx* p, size_t n, const sage_fn* fns, const uint
     std::lock_guard<std::recursive_mutex> lk(c.mu);
     const double t0 = now_ms();
     try {
-      for (; k < n; k++) out[k] = setup_internal(c, fns[k], batches[k]);
+      for (double t = t0; k < n; k++) {
+        out[k] = setup_internal(c, fns[k], batches[k]);
+        const double t1 = now_ms();
+        if (setup_ms) setup_ms[k] = t1 - t;
+        t = t1;
+      }
     } catch (...) {
       c.t_setup += now_ms() - t0;
       throw;

@@ -116,7 +116,7 @@ _sigs = {
                                   C.POINTER(_P), C.POINTER(C.c_size_t), C.c_uint32]),
     "fn_release": (C.c_int, [_P, C.c_uint64]),
     "fn_setup_batch": (C.c_int, [_P, C.c_size_t, C.POINTER(C.c_uint64), C.POINTER(C.c_uint32),
-                                 C.POINTER(C.c_uint64), C.POINTER(C.c_size_t)]),
+                                 C.POINTER(C.c_uint64), C.POINTER(C.c_size_t), C.POINTER(C.c_double)]),
     "fn_release_batch": (C.c_int, [_P, C.c_size_t, C.POINTER(C.c_uint64)]),
     "sage_get_stats": (C.c_int, [_P, C.POINTER(sage_stats)]),
     "sage_fn_fingerprints": (C.c_int, [_P, C.c_uint64, C.POINTER(C.c_uint64), C.c_size_t]),
@@ -268,13 +268,15 @@ def fn_release(ctx: int, inv: int) -> None:
     _check(_lib.fn_release(ctx, inv), "fn_release")
 
 
-def fn_setup_batch(ctx: int, fns, batches) -> list:
+def fn_setup_batch(ctx: int, fns, batches, timed: bool = False):
+    """Invocation handles; with timed=True also each request's own setup time (ms)."""
     n = len(fns)
     out = (C.c_uint64 * n)()
     done = C.c_size_t()
-    st = _lib.fn_setup_batch(ctx, n, (C.c_uint64 * n)(*fns), (C.c_uint32 * n)(*batches), out, C.byref(done))
+    ms = (C.c_double * n)() if timed else None
+    st = _lib.fn_setup_batch(ctx, n, (C.c_uint64 * n)(*fns), (C.c_uint32 * n)(*batches), out, C.byref(done), ms)
     _check(st, "fn_setup_batch")
-    return list(out)
+    return (list(out), list(ms)) if timed else list(out)
 
 
 def fn_release_batch(ctx: int, invs) -> None:

@@ -88,3 +88,24 @@ def test_zero_length_kernels_are_no_ops(sage_ctx_factory, torch_cuda):
     S.sage_blkcopy(ctx, out.data_ptr(), 0, out.data_ptr())
     torch.cuda.synchronize()
     assert int(out.item()) == 7
+
+
+def test_setup_batch_times_each_request(sage_ctx_factory, torch_cuda):
+    """fn_setup_batch with per-request times: one positive time per request,
+    their sum within the call's own wall time; a failing request stops the
+    batch with the earlier ones set up."""
+    import time
+    from paper_2404_14691_amd import sage as S
+    ctx = sage_ctx_factory()
+    w = synth.shared_mlp_bf16_functions(n_fns=2, layers=2, width=256, share_frac=0.0, seed=33)
+    desc = S.mlp_desc(S.SAGE_MLP_BF16, 2, 256)
+    fns = [S.fn_register(ctx, desc, [S.make_blob(b)]) for b in w.blobs]
+    t0 = time.perf_counter()
+    invs, ms = S.fn_setup_batch(ctx, [fns[0], fns[1], fns[0]], [3, 5, 1], timed=True)
+    wall = (time.perf_counter() - t0) * 1e3
+    assert len(invs) == len(set(invs)) == 3 and len(ms) == 3
+    assert all(m > 0 for m in ms) and sum(ms) <= wall
+    assert S.sage_get_stats(ctx)["live_setups"] == 3
+    S.fn_release_batch(ctx, invs)
+    assert _status(S.fn_setup_batch, ctx, [fns[1], fns[0]], [2, 0]) == S.SAGE_EINVAL
+    assert S.sage_get_stats(ctx)["live_setups"] == 1  # the first request of the failed batch
