@@ -170,6 +170,8 @@ typedef struct {
   uint64_t module_unloads;  /* code objects unloaded by the multi-stage exit */
   double t_module_ms;       /* host wall time in code-object loads */
   double t_reload_ms;       /* host wall time in fn_setup reloads of missing blocks (issue only, when progressive) */
+  double t_release_ms;      /* fn_release / fn_release_batch calls */
+  double t_unregister_ms;   /* fn_unregister calls */
 } sage_stats;
 
 /* ----------------------------------------------------------------- context */

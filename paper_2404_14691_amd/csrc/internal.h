@@ -390,7 +390,7 @@ struct Ctx {
   uint64_t logical = 0, h2d = 0, reloads = 0, registrations = 0, invocations = 0, mismatches = 0;
   double t_register = 0, t_code = 0, t_fp_wait = 0, t_dedup = 0, t_verify = 0, t_setup = 0, t_invoke = 0;
   uint64_t host_reloads = 0, module_unloads = 0;
-  double t_reload = 0;
+  double t_reload = 0, t_release = 0, t_unregister = 0;
   uint64_t module_loads = 0;                 // under module_mu
   double t_module = 0;                       // under module_mu
   Serve* serve = nullptr;                    // running serving loop, if any

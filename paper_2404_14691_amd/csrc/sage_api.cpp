@@ -392,6 +392,7 @@ sage_status fn_unregister(sage_ctx* p, sage_fn id) {
     Ctx& c = ctx_of(p);
     std::lock_guard<std::recursive_mutex> lk(c.mu);
     Fn& f = fn_of(c, id);
+    const double t0 = now_ms();
     if (f.live > 0) fail(SAGE_EBUSY, "function has %d live setups", f.live);
     for (size_t i = 0; i < c.flights.size(); i++) finish_flight(c, (int)i);
     // copies from f's sources or host-cache copies may still be in flight;
@@ -407,6 +408,7 @@ sage_status fn_unregister(sage_ctx* p, sage_fn id) {
     (void)hipEventDestroy(f.ready);
     for (hipEvent_t e : f.seg) (void)hipEventDestroy(e);
     c.fns.erase(id);
+    c.t_unregister += now_ms() - t0;
   });
 }
 
@@ -451,7 +453,9 @@ sage_status fn_release_batch(sage_ctx* p, size_t n, const sage_inv* invs) {
     Ctx& c = ctx_of(p);
     if (n && !invs) fail(SAGE_EINVAL, "null argument");
     std::lock_guard<std::recursive_mutex> lk(c.mu);
+    const double t0 = now_ms();
     for (size_t i = 0; i < n; i++) release_internal(c, invs[i]);
+    c.t_release += now_ms() - t0;
   });
 }
 
@@ -459,7 +463,9 @@ sage_status fn_release(sage_ctx* p, sage_inv id) {
   return guard([&] {
     Ctx& c = ctx_of(p);
     std::lock_guard<std::recursive_mutex> lk(c.mu);
+    const double t0 = now_ms();
     release_internal(c, id);
+    c.t_release += now_ms() - t0;
   });
 }
 
@@ -569,6 +575,8 @@ sage_status sage_get_stats(sage_ctx* p, sage_stats* out) {
     out->host_reloads = c.host_reloads;
     out->module_unloads = c.module_unloads;
     out->t_reload_ms = c.t_reload;
+    out->t_release_ms = c.t_release;
+    out->t_unregister_ms = c.t_unregister;
     {
       std::lock_guard<std::mutex> mk(c.module_mu);
       out->module_loads = c.module_loads;

@@ -70,7 +70,7 @@ class sage_stats(C.Structure):
                                    "t_setup_ms", "t_invoke_ms")] + \
         [(n, C.c_uint64) for n in ("host_cached_bytes", "demotions", "host_reloads", "module_loads",
                                    "module_unloads")] + \
-        [(n, C.c_double) for n in ("t_module_ms", "t_reload_ms")]
+        [(n, C.c_double) for n in ("t_module_ms", "t_reload_ms", "t_release_ms", "t_unregister_ms")]
 
     def as_dict(self) -> dict:
         return {n: (int(getattr(self, n)) if t is C.c_uint64 else float(getattr(self, n)))
