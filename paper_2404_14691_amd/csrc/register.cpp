@@ -510,178 +510,188 @@ void reload_classes(Ctx& c, Fn& f, const std::vector<uint32_t>& missing_in) {
     P.cls[missing[j]].slot = slotid;
     P.index_add(missing[j]);
   }
-  // where each class comes from: 0 device source, 1 host cache (pinned,
-  // whole blocks), 2 registered host source (through pinned staging)
-  std::vector<uint8_t> kind(n);
-  std::vector<const uint8_t*> src(n);
-  size_t n_host = 0, n_page = 0;
-  for (size_t j = 0; j < n; j++) {
-    const Class& k = P.cls[missing[j]];
-    bool dev = false;
-    if (k.hbuf != kNone) {
-      kind[j] = 1;
-      src[j] = P.hbufs[k.hbuf].p + (uint64_t)k.hoff * kBlock;
-    } else {
-      src[j] = f.block_src(first.at(missing[j]), &dev);
-      kind[j] = dev ? 0 : 2;
-    }
-    n_host += kind[j] != 0;
-    n_page += kind[j] == 2;
-  }
-  const bool gate = c.cfg.progressive && mlp && n_host > 0;
-  // batches and their staging regions
-  const size_t per_batch = std::min<size_t>(std::max<size_t>(1, c.ring.chunk / kBlock), kReloadStageBlocks);
-  const size_t n_regions = kReloadStageBlocks / per_batch;
-  if (n_host && !c.rstage_dev) HIPX(hipMalloc((void**)&c.rstage_dev, kReloadStageBlocks * kBlock));
-  Ring& R = c.ring;
-  while (c.rstage_ev.size() < n_regions) {
-    hipEvent_t e;
-    HIPX(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    c.rstage_ev.push_back(e);
-  }
-  struct Batch {
-    size_t j0, j1;
-    uint32_t seg;
-    int region;  // -1: no host bytes
-  };
-  std::vector<Batch> batches;
-  std::vector<size_t> stage_at(n, 0);
-  for (uint32_t l = 0, j = 0; l < n_seg; l++) {
-    while (j < seg_end[l]) {
-      Batch bt{j, std::min(seg_end[l], j + per_batch), l, -1};
-      size_t h = 0;
-      for (size_t q = bt.j0; q < bt.j1; q++)
-        if (kind[q]) {
-          if (bt.region < 0) bt.region = (int)(c.rstage_next++ % n_regions);
-          stage_at[q] = (size_t)bt.region * per_batch + h++;
-        }
-      batches.push_back(bt);
-      j = (uint32_t)bt.j1;
-    }
-  }
-  // the op list: the previous reload's upload has read the pinned buffer
-  HIPX(hipEventSynchronize(c.prog_ops_ev));
-  if (c.prog_hops_cap < n * sizeof(BlkOp)) {
-    if (c.prog_hops) HIPX(hipHostFree(c.prog_hops));
-    c.prog_hops = nullptr;
-    c.prog_hops_cap = 0;
-    HIPX(hipHostMalloc((void**)&c.prog_hops, n * sizeof(BlkOp), hipHostMallocDefault));
-    c.prog_hops_cap = n * sizeof(BlkOp);
-  }
-  uint8_t* dmeta = (uint8_t*)c.cache.get(n * (sizeof(BlkOp) + 4));
-  c.deferred_dev.push_back(dmeta);
-  BlkOp* dops = reinterpret_cast<BlkOp*>(dmeta);
-  uint32_t* dres = reinterpret_cast<uint32_t*>(dmeta + n * sizeof(BlkOp));
-  BlkOp* hops = reinterpret_cast<BlkOp*>(c.prog_hops);
-  for (size_t j = 0; j < n; j++) {
-    const Class& k = P.cls[missing[j]];
-    const uint64_t from = kind[j] ? (uint64_t)(c.rstage_dev + stage_at[j] * kBlock) : (uint64_t)src[j];
-    hops[j] = BlkOp{from, (uint64_t)P.addr(k.slot), k.len, 0};
-    c.h2d += k.len;
-    c.reloads++;
-    if (kind[j] == 1) c.host_reloads++;
-  }
-  // control stream: op list, block table, then the mark the copy streams start
-  // behind (a freed slot may still be the target of a copy in flight there)
-  HIPX(hipMemcpyAsync(dops, hops, n * sizeof(BlkOp), hipMemcpyHostToDevice, c.ctl));
-  HIPX(hipEventRecord(c.prog_ops_ev, c.ctl));
-  refresh_table(c, f);
-  HIPX(hipEventRecord(c.ctl_ev, c.ctl));
-  for (hipStream_t cs : c.streams) HIPX(hipStreamWaitEvent(cs, c.ctl_ev, 0));
-  while (gate && f.seg.size() < f.d.layers) {
-    hipEvent_t e;
-    HIPX(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    f.seg.push_back(e);
-  }
-  std::vector<bool> dirty(c.streams.size(), false);
-  auto join = [&] {  // the control stream waits for the copy streams used since the last join
-    for (size_t k = 0; k < c.streams.size(); k++) {
-      if (!dirty[k]) continue;
-      HIPX(hipEventRecord(c.join_ev[k], c.streams[k]));
-      HIPX(hipStreamWaitEvent(c.ctl, c.join_ev[k], 0));
-      dirty[k] = false;
-    }
-  };
-  size_t bi = 0;
-  for (uint32_t l = 0; l < n_seg; l++) {
-    for (; bi < batches.size() && batches[bi].seg == l; bi++) {
-      const Batch& bt = batches[bi];
-      const size_t si = bi % c.streams.size();
-      hipStream_t s = c.streams[si];
-      if (bt.region >= 0) {
-        HIPX(hipEventSynchronize(c.rstage_ev[bt.region]));  // its last batch has read the region
-        // pageable source runs into a ring slot's pinned buffer, one parallel memcpy each
-        int hs = -1;
-        size_t hn = 0;
-        std::vector<const uint8_t*> pinned_at(bt.j1 - bt.j0, nullptr);
-        uint8_t* cp_to = nullptr;
-        const uint8_t* cp_from = nullptr;
-        size_t cp_n = 0;
-        for (size_t q = bt.j0; q < bt.j1; q++) {
-          if (kind[q] != 2) continue;
-          if (hs < 0) {
-            hs = (int)(c.rhost_next++ % R.slots);
-            HIPX(hipEventSynchronize(R.ev[hs]));  // the slot's last user has read its buffer
-          }
-          uint8_t* to = R.host[hs] + hn++ * kBlock;
-          pinned_at[q - bt.j0] = to;
-          if (!(cp_n && cp_n % kBlock == 0 && to == cp_to + cp_n && src[q] == cp_from + cp_n)) {
-            if (cp_n) fill_parallel(c, cp_to, cp_from, cp_n);
-            cp_to = to;
-            cp_from = src[q];
-            cp_n = 0;
-          }
-          cp_n += P.cls[missing[q]].len;
-        }
-        if (cp_n) fill_parallel(c, cp_to, cp_from, cp_n);
-        // pinned bytes to the device staging, one DMA per run contiguous on both sides
-        const uint8_t* run_src = nullptr;
-        size_t run_at = 0, run_n = 0;
-        auto flush = [&] {
-          if (run_n)
-            HIPX(hipMemcpyAsync(c.rstage_dev + run_at * kBlock, run_src, run_n * kBlock, hipMemcpyHostToDevice,
-                                s));
-          run_n = 0;
-        };
-        for (size_t q = bt.j0; q < bt.j1; q++) {
-          if (!kind[q]) continue;
-          const uint8_t* from = kind[q] == 1 ? src[q] : pinned_at[q - bt.j0];
-          if (!(run_n && from == run_src + run_n * kBlock && stage_at[q] == run_at + run_n)) {
-            flush();
-            run_src = from;
-            run_at = stage_at[q];
-          }
-          run_n++;
-        }
-        flush();
-        if (hs >= 0) HIPX(hipEventRecord(R.ev[hs], s));
+  // from here on the classes hold slots their bytes have not reached: a
+  // failure takes them out again, so that no later setup reads them
+  try {
+    // where each class comes from: 0 device source, 1 host cache (pinned,
+    // whole blocks), 2 registered host source (through pinned staging)
+    std::vector<uint8_t> kind(n);
+    std::vector<const uint8_t*> src(n);
+    size_t n_host = 0, n_page = 0;
+    for (size_t j = 0; j < n; j++) {
+      const Class& k = P.cls[missing[j]];
+      bool dev = false;
+      if (k.hbuf != kNone) {
+        kind[j] = 1;
+        src[j] = P.hbufs[k.hbuf].p + (uint64_t)k.hoff * kBlock;
+      } else {
+        src[j] = f.block_src(first.at(missing[j]), &dev);
+        kind[j] = dev ? 0 : 2;
       }
-      const int tok = c.timer.start("blkcopy", s, 1);
-      HIPX(launch_blkcopy(dops + bt.j0, (uint32_t)(bt.j1 - bt.j0), dres + bt.j0, c.max_groups_copy(), s));
-      c.timer.stop(tok, s);
-      if (bt.region >= 0) HIPX(hipEventRecord(c.rstage_ev[bt.region], s));
-      dirty[si] = true;
+      n_host += kind[j] != 0;
+      n_page += kind[j] == 2;
+    }
+    const bool gate = c.cfg.progressive && mlp && n_host > 0;
+    // batches and their staging regions
+    const size_t per_batch = std::min<size_t>(std::max<size_t>(1, c.ring.chunk / kBlock), kReloadStageBlocks);
+    const size_t n_regions = kReloadStageBlocks / per_batch;
+    if (n_host && !c.rstage_dev) HIPX(hipMalloc((void**)&c.rstage_dev, kReloadStageBlocks * kBlock));
+    Ring& R = c.ring;
+    while (c.rstage_ev.size() < n_regions) {
+      hipEvent_t e;
+      HIPX(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      c.rstage_ev.push_back(e);
+    }
+    struct Batch {
+      size_t j0, j1;
+      uint32_t seg;
+      int region;  // -1: no host bytes
+    };
+    std::vector<Batch> batches;
+    std::vector<size_t> stage_at(n, 0);
+    for (uint32_t l = 0, j = 0; l < n_seg; l++) {
+      while (j < seg_end[l]) {
+        Batch bt{j, std::min(seg_end[l], j + per_batch), l, -1};
+        size_t h = 0;
+        for (size_t q = bt.j0; q < bt.j1; q++)
+          if (kind[q]) {
+            if (bt.region < 0) bt.region = (int)(c.rstage_next++ % n_regions);
+            stage_at[q] = (size_t)bt.region * per_batch + h++;
+          }
+        batches.push_back(bt);
+        j = (uint32_t)bt.j1;
+      }
+    }
+    // the op list: the previous reload's upload has read the pinned buffer
+    HIPX(hipEventSynchronize(c.prog_ops_ev));
+    if (c.prog_hops_cap < n * sizeof(BlkOp)) {
+      if (c.prog_hops) HIPX(hipHostFree(c.prog_hops));
+      c.prog_hops = nullptr;
+      c.prog_hops_cap = 0;
+      HIPX(hipHostMalloc((void**)&c.prog_hops, n * sizeof(BlkOp), hipHostMallocDefault));
+      c.prog_hops_cap = n * sizeof(BlkOp);
+    }
+    uint8_t* dmeta = (uint8_t*)c.cache.get(n * (sizeof(BlkOp) + 4));
+    c.deferred_dev.push_back(dmeta);
+    BlkOp* dops = reinterpret_cast<BlkOp*>(dmeta);
+    uint32_t* dres = reinterpret_cast<uint32_t*>(dmeta + n * sizeof(BlkOp));
+    BlkOp* hops = reinterpret_cast<BlkOp*>(c.prog_hops);
+    for (size_t j = 0; j < n; j++) {
+      const Class& k = P.cls[missing[j]];
+      const uint64_t from = kind[j] ? (uint64_t)(c.rstage_dev + stage_at[j] * kBlock) : (uint64_t)src[j];
+      hops[j] = BlkOp{from, (uint64_t)P.addr(k.slot), k.len, 0};
+      c.h2d += k.len;
+      c.reloads++;
+      if (kind[j] == 1) c.host_reloads++;
+    }
+    // control stream: op list, block table, then the mark the copy streams start
+    // behind (a freed slot may still be the target of a copy in flight there)
+    HIPX(hipMemcpyAsync(dops, hops, n * sizeof(BlkOp), hipMemcpyHostToDevice, c.ctl));
+    HIPX(hipEventRecord(c.prog_ops_ev, c.ctl));
+    refresh_table(c, f);
+    HIPX(hipEventRecord(c.ctl_ev, c.ctl));
+    for (hipStream_t cs : c.streams) HIPX(hipStreamWaitEvent(cs, c.ctl_ev, 0));
+    while (gate && f.seg.size() < f.d.layers) {
+      hipEvent_t e;
+      HIPX(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      f.seg.push_back(e);
+    }
+    std::vector<bool> dirty(c.streams.size(), false);
+    auto join = [&] {  // the control stream waits for the copy streams used since the last join
+      for (size_t k = 0; k < c.streams.size(); k++) {
+        if (!dirty[k]) continue;
+        HIPX(hipEventRecord(c.join_ev[k], c.streams[k]));
+        HIPX(hipStreamWaitEvent(c.ctl, c.join_ev[k], 0));
+        dirty[k] = false;
+      }
+    };
+    size_t bi = 0;
+    for (uint32_t l = 0; l < n_seg; l++) {
+      for (; bi < batches.size() && batches[bi].seg == l; bi++) {
+        const Batch& bt = batches[bi];
+        const size_t si = bi % c.streams.size();
+        hipStream_t s = c.streams[si];
+        if (bt.region >= 0) {
+          HIPX(hipEventSynchronize(c.rstage_ev[bt.region]));  // its last batch has read the region
+          // pageable source runs into a ring slot's pinned buffer, one parallel memcpy each
+          int hs = -1;
+          size_t hn = 0;
+          std::vector<const uint8_t*> pinned_at(bt.j1 - bt.j0, nullptr);
+          uint8_t* cp_to = nullptr;
+          const uint8_t* cp_from = nullptr;
+          size_t cp_n = 0;
+          for (size_t q = bt.j0; q < bt.j1; q++) {
+            if (kind[q] != 2) continue;
+            if (hs < 0) {
+              hs = (int)(c.rhost_next++ % R.slots);
+              HIPX(hipEventSynchronize(R.ev[hs]));  // the slot's last user has read its buffer
+            }
+            uint8_t* to = R.host[hs] + hn++ * kBlock;
+            pinned_at[q - bt.j0] = to;
+            if (!(cp_n && cp_n % kBlock == 0 && to == cp_to + cp_n && src[q] == cp_from + cp_n)) {
+              if (cp_n) fill_parallel(c, cp_to, cp_from, cp_n);
+              cp_to = to;
+              cp_from = src[q];
+              cp_n = 0;
+            }
+            cp_n += P.cls[missing[q]].len;
+          }
+          if (cp_n) fill_parallel(c, cp_to, cp_from, cp_n);
+          // pinned bytes to the device staging, one DMA per run contiguous on both sides
+          const uint8_t* run_src = nullptr;
+          size_t run_at = 0, run_n = 0;
+          auto flush = [&] {
+            if (run_n)
+              HIPX(hipMemcpyAsync(c.rstage_dev + run_at * kBlock, run_src, run_n * kBlock, hipMemcpyHostToDevice,
+                                  s));
+            run_n = 0;
+          };
+          for (size_t q = bt.j0; q < bt.j1; q++) {
+            if (!kind[q]) continue;
+            const uint8_t* from = kind[q] == 1 ? src[q] : pinned_at[q - bt.j0];
+            if (!(run_n && from == run_src + run_n * kBlock && stage_at[q] == run_at + run_n)) {
+              flush();
+              run_src = from;
+              run_at = stage_at[q];
+            }
+            run_n++;
+          }
+          flush();
+          if (hs >= 0) HIPX(hipEventRecord(R.ev[hs], s));
+        }
+        const int tok = c.timer.start("blkcopy", s, 1);
+        HIPX(launch_blkcopy(dops + bt.j0, (uint32_t)(bt.j1 - bt.j0), dres + bt.j0, c.max_groups_copy(), s));
+        c.timer.stop(tok, s);
+        if (bt.region >= 0) HIPX(hipEventRecord(c.rstage_ev[bt.region], s));
+        dirty[si] = true;
+      }
+      if (gate) {
+        join();
+        HIPX(hipEventRecord(f.seg[l], c.ctl));
+      }
     }
     if (gate) {
       join();
-      HIPX(hipEventRecord(f.seg[l], c.ctl));
+    } else {
+      // the host waits for the copy streams themselves; the marks below then
+      // follow only the control stream's own uploads
+      for (hipStream_t cs : c.streams) HIPX(hipStreamSynchronize(cs));
     }
+    HIPX(hipEventRecord(f.ready, c.ctl));
+    HIPX(hipEventRecord(c.reload_done, c.ctl));
+    c.reload_seq++;
+    for (uint32_t cl : missing) P.cls[cl].fill = c.reload_seq;
+    c.prog_fn = gate ? f.id : 0;
+    for (size_t q = 0; q < n; q++)
+      if (kind[q] == 1) c.deferred_host.push_back({missing[q], P.cls[missing[q]].hgen});
+    if (!gate) settle_reloads(c, true);  // resident on return; the host copies go
+  } catch (...) {
+    for (hipStream_t cs : c.streams) (void)hipStreamSynchronize(cs);
+    (void)hipStreamSynchronize(c.ctl);
+    for (uint32_t cl : missing)
+      if (P.cls[cl].slot != kNone) P.evict(cl);
+    throw;
   }
-  if (gate) {
-    join();
-  } else {
-    // the host waits for the copy streams themselves; the marks below then
-    // follow only the control stream's own uploads
-    for (hipStream_t cs : c.streams) HIPX(hipStreamSynchronize(cs));
-  }
-  HIPX(hipEventRecord(f.ready, c.ctl));
-  HIPX(hipEventRecord(c.reload_done, c.ctl));
-  c.reload_seq++;
-  for (uint32_t cl : missing) P.cls[cl].fill = c.reload_seq;
-  c.prog_fn = gate ? f.id : 0;
-  for (size_t q = 0; q < n; q++)
-    if (kind[q] == 1) c.deferred_host.push_back({missing[q], P.cls[missing[q]].hgen});
-  if (!gate) settle_reloads(c, true);  // resident on return; the host copies go
   c.t_reload += now_ms() - t_start;
 }
 
