@@ -181,7 +181,8 @@ def test_f32_mlp_full_size_sixteen_invocations(sage_ctx_factory, torch_cuda):
     assert S.sage_get_stats(ctx)["h2d_bytes"] == 16 * wl.weights.nbytes
 
 
-@pytest.mark.parametrize("shape,sweeps", [((18, 20, 32), 5), ((9, 7, 64), 4), ((5, 3, 128), 1), ((6, 6, 16), 0)])
+@pytest.mark.parametrize("shape,sweeps", [((18, 20, 32), 5), ((9, 7, 64), 4), ((5, 3, 128), 1), ((6, 6, 16), 0),
+                                          ((70, 45, 64), 3)])
 def test_stencil_vs_oracle(sage_ctx_factory, torch_cuda, shape, sweeps):
     from paper_2404_14691_amd import sage as S
     ctx = sage_ctx_factory()
@@ -217,7 +218,8 @@ def test_stencil_zero_coefficient_identity(sage_ctx_factory, torch_cuda):
     assert np.array_equal(out, u)
 
 
-@pytest.mark.parametrize("shape,sweeps,coef", [((7, 9, 20), 3, 0.7), ((4, 5, 8), 1, 1.0), ((18, 20, 300), 4, 0.35)])
+@pytest.mark.parametrize("shape,sweeps,coef", [((7, 9, 20), 3, 0.7), ((4, 5, 8), 1, 1.0), ((18, 20, 300), 4, 0.35),
+                                               ((66, 33, 260), 2, 0.5)])
 def test_relax_vs_oracle_and_plain(sage_ctx_factory, torch_cuda, shape, sweeps, coef):
     """The relaxation kind has no read-only data: it registers with no blobs
     and its sweep uses one constant coefficient.  Shared and plain contexts
