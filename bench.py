@@ -331,7 +331,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (this path has no "
-              f"multi-GPU form; see DESIGN.md for how it would shard)", file=sys.stderr)
+              f"multi-GPU form: it would shard by function, each GPU with its own pool)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -347,9 +347,9 @@ def main():
     log(f"workload ready: {len(wl.requests)} requests, {wl.rows} rows")
     cfg = S.sage_config_default()
     cfg.pool_budget_bytes = 8 << 30
-    tune_file = os.path.join(ROOT, "gpurun_out", "tune_cache.txt")
-    if os.path.isdir(os.path.dirname(tune_file)):
-        cfg.tune_cache = tune_file.encode()
+    # autotuner cache file, if one is named; otherwise tile timings stay in memory
+    if os.environ.get("SAGE_TUNE_CACHE"):
+        cfg.tune_cache = os.environ["SAGE_TUNE_CACHE"].encode()
     ctx = S.sage_open(0, cfg)
     pcfg = S.sage_config_default()
     pcfg.share = 0
