@@ -75,6 +75,9 @@ class DevCache {
 class KernelTimer {
  public:
   bool on = false;
+  // Have n event pairs ready (created outside the timed work; a start then
+  // costs two event records and no allocation).
+  void reserve(size_t n);
   // Record a start event on s; returns a token for stop().
   int start(const char* name, hipStream_t s, uint32_t launches);
   void stop(int token, hipStream_t s);
@@ -91,7 +94,9 @@ class KernelTimer {
     bool busy;
   };
   std::vector<Pair> pairs_;
+  std::vector<int> free_;  // indices of pairs not in use
   std::map<std::string, std::pair<double, uint64_t>> acc_;
+  int add_pair();
 };
 
 // ------------------------------------------------------------------- pool
@@ -342,6 +347,7 @@ class Worker {
 
 // ------------------------------------------------------------------ context
 constexpr size_t kReloadStageBlocks = 4096;  // reload staging: 256 MiB, cycled by region
+constexpr size_t kTimerPairs = 2048;          // event pairs made ready when kernel timing is switched on
 
 struct Ctx {
   int device = 0;

@@ -678,6 +678,7 @@ sage_status sage_timing_enable(sage_ctx* p, int on) {
     Ctx& c = ctx_of(p);
     std::lock_guard<std::recursive_mutex> lk(c.mu);
     c.timer.on = on != 0;
+    if (c.timer.on) c.timer.reserve(kTimerPairs);
   });
 }
 

@@ -103,20 +103,27 @@ void DevCache::release_all() {
 }
 
 // ---------------------------------------------------------- KernelTimer
+int KernelTimer::add_pair() {
+  Pair p{};
+  HIPX(hipEventCreate(&p.a));
+  HIPX(hipEventCreate(&p.b));
+  pairs_.push_back(p);
+  return (int)pairs_.size() - 1;
+}
+
+void KernelTimer::reserve(size_t n) {
+  while (pairs_.size() < n) free_.push_back(add_pair());
+}
+
 int KernelTimer::start(const char* name, hipStream_t s, uint32_t launches) {
   if (!on) return -1;
-  int tok = -1;
-  for (size_t i = 0; i < pairs_.size(); i++)
-    if (!pairs_[i].busy) {
-      tok = (int)i;
-      break;
-    }
-  if (tok < 0) {
-    Pair p{};
-    HIPX(hipEventCreate(&p.a));
-    HIPX(hipEventCreate(&p.b));
-    pairs_.push_back(p);
-    tok = (int)pairs_.size() - 1;
+  if (free_.empty()) collect();  // pairs whose interval completed come back
+  int tok;
+  if (!free_.empty()) {
+    tok = free_.back();
+    free_.pop_back();
+  } else {
+    tok = add_pair();
   }
   Pair& p = pairs_[tok];
   p.busy = true;
@@ -144,6 +151,7 @@ void KernelTimer::collect() {
     a.first += ms;
     a.second += p.launches;
     p.busy = false;
+    free_.push_back((int)(&p - pairs_.data()));
   }
 }
 
@@ -171,6 +179,7 @@ void KernelTimer::destroy() {
     (void)hipEventDestroy(p.b);
   }
   pairs_.clear();
+  free_.clear();
 }
 
 // ------------------------------------------------------ setup branches

@@ -253,14 +253,31 @@ def fn_invoke(ctx: int, inv: int, inp, out, io_flags: int = 0) -> None:
 
 
 def fn_invoke_batch(ctx: int, invs, inputs, outputs, io_flags: int = 0) -> None:
+    """invs: handles (a list, or a uint64 array); inputs/outputs: one entry per
+    handle as for fn_invoke, or, for device I/O, a uint64 array of shape
+    (n, 2) holding (address, nbytes) rows, marshalled without a Python loop."""
     n = len(invs)
-    ids = (C.c_uint64 * n)(*invs)
-    ins = [_io_ptr(x, bool(io_flags & SAGE_IO_DEVICE_IN)) for x in inputs]
-    outs = [_io_ptr(x, bool(io_flags & SAGE_IO_DEVICE_OUT)) for x in outputs]
-    ip = (_P * n)(*[p for p, _ in ins])
-    ib = (C.c_size_t * n)(*[b for _, b in ins])
-    op = (_P * n)(*[p for p, _ in outs])
-    ob = (C.c_size_t * n)(*[b for _, b in outs])
+    keep = []
+
+    def u64(a):
+        a = np.ascontiguousarray(a, dtype=np.uint64)
+        keep.append(a)
+        return a
+
+    ids = u64(invs).ctypes.data_as(C.POINTER(C.c_uint64)) if isinstance(invs, np.ndarray) \
+        else (C.c_uint64 * n)(*invs)
+
+    def side(xs, device):
+        if device and isinstance(xs, np.ndarray):
+            if xs.shape != (n, 2):
+                raise ValueError("device I/O array must have shape (n, 2)")
+            return (u64(xs[:, 0]).ctypes.data_as(C.POINTER(_P)),
+                    u64(xs[:, 1]).ctypes.data_as(C.POINTER(C.c_size_t)))
+        pairs = [_io_ptr(x, device) for x in xs]
+        return (_P * n)(*[p for p, _ in pairs]), (C.c_size_t * n)(*[b for _, b in pairs])
+
+    ip, ib = side(inputs, bool(io_flags & SAGE_IO_DEVICE_IN))
+    op, ob = side(outputs, bool(io_flags & SAGE_IO_DEVICE_OUT))
     _check(_lib.fn_invoke_batch(ctx, n, ids, ip, ib, op, ob, io_flags), "fn_invoke_batch")
 
 
@@ -269,8 +286,20 @@ def fn_release(ctx: int, inv: int) -> None:
 
 
 def fn_setup_batch(ctx: int, fns, batches, timed: bool = False):
-    """Invocation handles; with timed=True also each request's own setup time (ms)."""
+    """Invocation handles; with timed=True also each request's own setup time
+    (ms).  Given numpy arrays, returns numpy arrays (no Python loop)."""
     n = len(fns)
+    if isinstance(fns, np.ndarray):
+        f = np.ascontiguousarray(fns, dtype=np.uint64)
+        b = np.ascontiguousarray(batches, dtype=np.uint32)
+        out = np.zeros(n, dtype=np.uint64)
+        ms = np.zeros(n, dtype=np.float64) if timed else None
+        done = C.c_size_t()
+        st = _lib.fn_setup_batch(ctx, n, f.ctypes.data_as(C.POINTER(C.c_uint64)),
+                                 b.ctypes.data_as(C.POINTER(C.c_uint32)), out.ctypes.data_as(C.POINTER(C.c_uint64)),
+                                 C.byref(done), ms.ctypes.data_as(C.POINTER(C.c_double)) if timed else None)
+        _check(st, "fn_setup_batch")
+        return (out, ms) if timed else out
     out = (C.c_uint64 * n)()
     done = C.c_size_t()
     ms = (C.c_double * n)() if timed else None
@@ -281,6 +310,10 @@ def fn_setup_batch(ctx: int, fns, batches, timed: bool = False):
 
 def fn_release_batch(ctx: int, invs) -> None:
     n = len(invs)
+    if isinstance(invs, np.ndarray):
+        a = np.ascontiguousarray(invs, dtype=np.uint64)
+        _check(_lib.fn_release_batch(ctx, n, a.ctypes.data_as(C.POINTER(C.c_uint64))), "fn_release_batch")
+        return
     _check(_lib.fn_release_batch(ctx, n, (C.c_uint64 * n)(*invs)), "fn_release_batch")
 
 

@@ -109,3 +109,36 @@ def test_setup_batch_times_each_request(sage_ctx_factory, torch_cuda):
     S.fn_release_batch(ctx, invs)
     assert _status(S.fn_setup_batch, ctx, [fns[1], fns[0]], [2, 0]) == S.SAGE_EINVAL
     assert S.sage_get_stats(ctx)["live_setups"] == 1  # the first request of the failed batch
+
+
+def test_batch_calls_take_arrays(sage_ctx_factory, torch_cuda):
+    """Handles and device I/O descriptors passed as numpy arrays give the
+    same outputs as the per-request lists."""
+    from paper_2404_14691_amd import sage as S
+    torch = torch_cuda
+    ctx = sage_ctx_factory()
+    w = synth.shared_mlp_bf16_functions(n_fns=2, layers=2, width=256, share_frac=0.0, seed=34)
+    desc = S.mlp_desc(S.SAGE_MLP_BF16, 2, 256)
+    fns = [S.fn_register(ctx, desc, [S.make_blob(b)]) for b in w.blobs]
+    batches = [3, 1, 4]
+    rows = sum(batches)
+    x = torch.from_numpy(synth.bf16_inputs(rows, 256, 34, 0).view(np.int16)).cuda()
+    io = S.SAGE_IO_DEVICE_IN | S.SAGE_IO_DEVICE_OUT
+    offs = np.concatenate([[0], np.cumsum(batches)[:-1]])
+    ins = [(x.data_ptr() + int(o) * 512, b * 512) for o, b in zip(offs, batches)]
+    results = []
+    for arrays in (False, True):
+        y = torch.zeros((rows, 256), dtype=torch.float32, device="cuda")
+        outs = [(y.data_ptr() + int(o) * 1024, b * 1024) for o, b in zip(offs, batches)]
+        f = [fns[0], fns[1], fns[0]]
+        if arrays:
+            invs, ms = S.fn_setup_batch(ctx, np.array(f, dtype=np.uint64), np.array(batches), timed=True)
+            assert isinstance(invs, np.ndarray) and ms.shape == (3,)
+            S.fn_invoke_batch(ctx, invs, np.array(ins, dtype=np.uint64), np.array(outs, dtype=np.uint64), io)
+        else:
+            invs = S.fn_setup_batch(ctx, f, batches)
+            S.fn_invoke_batch(ctx, invs, ins, outs, io)
+        S.fn_release_batch(ctx, invs)
+        results.append(y.cpu().numpy())
+    assert np.array_equal(results[0], results[1]) and np.abs(results[0]).sum() > 0
+    assert S.sage_get_stats(ctx)["live_setups"] == 0
