@@ -372,6 +372,16 @@ sage_status sage_selftest_setup_overlap(double load_ms, double host_ms, double c
 sage_status sage_selftest_plan(uint32_t width, const uint32_t* rows, size_t n_groups, const char* const* shapes,
                                const double* wave_ms, size_t n_shapes, uint32_t cus, char* out, size_t cap);
 
+/* Host-only check of the per-layer readiness of a reload (`progressive`):
+ * first[0..n) is the first block, in the function, of each reloaded class in
+ * reload order (non-decreasing); a layer's weights span layer_bytes bytes
+ * from l * layer_bytes.  out[l] (layers entries) receives how many leading
+ * classes hold every block of layers 0..l: layer l's launch waits for
+ * exactly those copies.  EINVAL for a decreasing `first` or empty input.
+ * Needs no GPU. */
+sage_status sage_selftest_segments(const uint32_t* first, size_t n, uint32_t layers, uint64_t layer_bytes,
+                                   size_t* out);
+
 #if defined(__GNUC__)
 #pragma GCC visibility pop
 #endif

@@ -433,6 +433,9 @@ void refresh_table(Ctx& c, Fn& f);
 // (waiting for the last one first if `wait`); whether f's own reload may
 // still be landing, its layers then gated one by one.
 void settle_reloads(Ctx& c, bool wait);
+// per layer, how many leading classes of a reload (ordered by first block)
+// hold every block of layers 0..l
+std::vector<size_t> layer_segments(const std::vector<uint32_t>& first, uint32_t layers, uint64_t layer_bytes);
 bool reload_landing(Ctx& c, const Fn& f);
 bool reload_feeds(Ctx& c, const Fn& f);  // a progressive reload in flight fills a class of f
 

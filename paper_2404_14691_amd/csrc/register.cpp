@@ -490,13 +490,9 @@ void reload_classes(Ctx& c, Fn& f, const std::vector<uint32_t>& missing_in) {
   const uint32_t n_seg = mlp ? f.d.layers : 1;
   std::vector<size_t> seg_end(n_seg, n);
   if (mlp) {
-    const uint64_t lbytes = (uint64_t)f.d.width * f.d.width * (f.d.kind == SAGE_MLP_F32 ? 4 : 2);
-    for (uint32_t l = 0, j = 0; l < n_seg; l++) {
-      const uint32_t last = (uint32_t)(((uint64_t)(l + 1) * lbytes - 1) / kBlock);
-      while (j < n && first.at(missing[j]) <= last) j++;
-      seg_end[l] = j;
-    }
-    seg_end.back() = n;
+    std::vector<uint32_t> firsts(n);
+    for (size_t j = 0; j < n; j++) firsts[j] = first.at(missing[j]);
+    seg_end = layer_segments(firsts, n_seg, (uint64_t)f.d.width * f.d.width * (f.d.kind == SAGE_MLP_F32 ? 4 : 2));
   }
   const uint32_t mark = P.new_mark();
   for (uint32_t cl : f.distinct) P.cls[cl].mark = mark;
@@ -706,6 +702,23 @@ static bool reloads_done(Ctx& c) {
   HIPX(q);
   c.reload_seq_done = c.reload_seq;
   return true;
+}
+
+// Layer l of a function whose blocks [l * layer_bytes, (l + 1) * layer_bytes)
+// hold its weights needs every class used by a block overlapping that range.
+// With the classes of a reload ordered by their first block (`first`,
+// non-decreasing), the classes used by layers 0..l are exactly those whose
+// first block is at most layer l's last block: a prefix of the order.
+std::vector<size_t> layer_segments(const std::vector<uint32_t>& first, uint32_t layers, uint64_t layer_bytes) {
+  std::vector<size_t> end(layers, first.size());
+  size_t j = 0;
+  for (uint32_t l = 0; l < layers; l++) {
+    const uint64_t last = ((uint64_t)(l + 1) * layer_bytes - 1) / kBlock;
+    while (j < first.size() && first[j] <= last) j++;
+    end[l] = j;
+  }
+  if (layers) end[layers - 1] = first.size();
+  return end;
 }
 
 void settle_reloads(Ctx& c, bool wait) {

@@ -716,6 +716,17 @@ sage_status sage_selftest_plan(uint32_t width, const uint32_t* rows, size_t n_gr
   });
 }
 
+sage_status sage_selftest_segments(const uint32_t* first, size_t n, uint32_t layers, uint64_t layer_bytes,
+                                   size_t* out) {
+  return guard([&] {
+    if ((n && !first) || !out || !layers || !layer_bytes) fail(SAGE_EINVAL, "null argument or empty input");
+    for (size_t j = 1; j < n; j++)
+      if (first[j] < first[j - 1]) fail(SAGE_EINVAL, "first blocks must be non-decreasing");
+    const std::vector<size_t> end = layer_segments(std::vector<uint32_t>(first, first + n), layers, layer_bytes);
+    std::copy(end.begin(), end.end(), out);
+  });
+}
+
 sage_status sage_tick(sage_ctx* p) {
   return guard([&] {
     Ctx& c = ctx_of(p);

@@ -131,6 +131,8 @@ _sigs = {
     "sage_timing_reset": (C.c_int, [_P]),
     "sage_last_launch": (C.c_int, [_P, C.c_char_p, C.c_size_t]),
     "sage_tick": (C.c_int, [_P]),
+    "sage_selftest_segments": (C.c_int, [C.POINTER(C.c_uint32), C.c_size_t, C.c_uint32, C.c_uint64,
+                                         C.POINTER(C.c_size_t)]),
     "sage_selftest_plan": (C.c_int, [C.c_uint32, C.POINTER(C.c_uint32), C.c_size_t, C.POINTER(C.c_char_p),
                                      C.POINTER(C.c_double), C.c_size_t, C.c_uint32, C.c_char_p, C.c_size_t]),
     "sage_selftest_setup_overlap": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_int,
@@ -378,6 +380,16 @@ def sage_timing_get(ctx: int, kernel: str):
 
 def sage_timing_reset(ctx: int) -> None:
     _check(_lib.sage_timing_reset(ctx), "sage_timing_reset")
+
+
+def sage_selftest_segments(first, layers: int, layer_bytes: int) -> list:
+    """Per layer, the number of leading reload classes (ordered by first
+    block) that layer's launch waits for; host only."""
+    n = len(first)
+    f = (C.c_uint32 * max(n, 1))(*first)
+    out = (C.c_size_t * layers)()
+    _check(_lib.sage_selftest_segments(f, n, layers, layer_bytes, out), "sage_selftest_segments")
+    return list(out)
 
 
 def sage_selftest_plan(width: int, rows, wave_ms: dict, cus: int = 256):
