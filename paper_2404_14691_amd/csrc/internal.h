@@ -348,6 +348,7 @@ class Worker {
 // ------------------------------------------------------------------ context
 constexpr size_t kReloadStageBlocks = 4096;  // reload staging: 256 MiB, cycled by region
 constexpr size_t kTimerPairs = 2048;          // event pairs made ready when kernel timing is switched on
+constexpr uint64_t kDevChunkBytes = 64ull << 20;  // registration chunk of a device-resident source
 
 struct Ctx {
   int device = 0;
@@ -383,6 +384,14 @@ struct Ctx {
   uint8_t* prog_hops = nullptr;
   size_t prog_hops_cap = 0;
   hipEvent_t prog_ops_ev = nullptr;
+  // registration-wide VERIFY / COPY op lists of device-source chunks:
+  // pinned and device buffers, reg_ev marking the last upload that reads them
+  BlkOp* reg_hops = nullptr;
+  BlkOp* reg_dops = nullptr;
+  uint32_t* reg_hres = nullptr;
+  uint32_t* reg_dres = nullptr;
+  size_t reg_cap = 0;
+  hipEvent_t reg_ev = nullptr;
   // reload staging: device area, one region per batch, each with the event
   // of the batch that last used it; pageable sources go through ring slots
   uint8_t* rstage_dev = nullptr;

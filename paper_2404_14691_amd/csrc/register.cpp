@@ -228,8 +228,10 @@ void register_shared(Ctx& c, Fn& f) {
   Ring& R = c.ring;
   std::vector<Chunk> chunks;
   for (uint32_t b = 0; b < f.srcs.size(); b++) {
-    // device sources need no staging: fingerprint and commit them whole
-    const uint64_t step = f.srcs[b].dev ? std::max<uint64_t>(f.srcs[b].n, 1) : R.chunk;
+    // device sources need no staging: they are fingerprinted in large chunks
+    // in place, and their VERIFY / COPY work waits for the whole registration
+    const uint64_t step = f.srcs[b].dev ? std::max<uint64_t>(std::min<uint64_t>(f.srcs[b].n, kDevChunkBytes), 1)
+                                        : R.chunk;
     for (uint64_t off = 0; off < f.srcs[b].n; off += step) {
       Chunk ch{};
       ch.blob = b;
@@ -252,6 +254,46 @@ void register_shared(Ctx& c, Fn& f) {
   for (int s = (int)R.slots; s-- > 0;) free_slots.push_back(s);
 
   auto stream_of = [&](int slot) { return c.streams[slot % c.streams.size()]; };
+
+  // bytes a VERIFY compares against: the first block of a class still being
+  // copied (its source), else its pool slot
+  auto ref_addr = [&](uint32_t cl) -> uint64_t {
+    const Class& k = P.cls[cl];
+    return (uint64_t)(k.pending ? k.pending : P.addr(k.slot));
+  };
+  // first candidate after `after` (or the first one) with the block's length
+  auto next_cand = [&](uint64_t fp, uint32_t len, uint32_t after) -> uint32_t {
+    uint32_t k = after == kNone ? P.chain_head(fp) : P.cls[after].next;
+    for (; k != kNone; k = P.cls[k].next) {
+      P.cls[k].mark = mark;
+      if (P.cls[k].len == len) return k;
+    }
+    return kNone;
+  };
+  // a new class for block gb whose bytes are at `data`, in a fresh slot
+  auto new_class_for = [&](uint32_t gb, const uint8_t* data) -> uint32_t {
+    const uint32_t slotid = P.alloc_slot(protect);
+    if (slotid == kNone)
+      fail(SAGE_ENOMEM, "pool full: no unreferenced block to evict (budget %llu slots)", (unsigned long long)P.budget);
+    const uint32_t cl = P.new_class(f.fps[gb], f.block_len(gb));
+    P.cls[cl].slot = slotid;
+    P.cls[cl].pending = data;
+    P.index_add(cl);
+    created.push_back(cl);
+    P.cls[cl].mark = mark;
+    f.cls[gb] = cl;
+    return cl;
+  };
+  // device-source chunks: VERIFY and COPY operations gathered over the whole
+  // registration and run once at its end (one device round trip instead of
+  // one per chunk); the classes they create keep their source as `pending`
+  struct DPend {
+    uint32_t gb, cand, op;
+    const uint8_t* data;
+  };
+  std::vector<BlkOp> dv, dc;
+  std::vector<DPend> dpend;
+  std::vector<uint32_t> dnew;
 
   auto issue = [&](Chunk& ch) {
     ch.slot = free_slots.back();
@@ -295,34 +337,19 @@ void register_shared(Ctx& c, Fn& f) {
     };
     std::vector<Pend> pend;
     std::vector<uint32_t> chunk_new;
-    auto ref_addr = [&](uint32_t cl) -> uint64_t {
-      const Class& k = P.cls[cl];
-      return (uint64_t)(k.pending ? k.pending : P.addr(k.slot));
-    };
+    const bool deferred = f.srcs[ch.blob].dev;
     auto make_new = [&](uint32_t i) {
-      const uint32_t gb = ch.first + i, len = f.block_len(gb);
-      const uint32_t slotid = P.alloc_slot(protect);
-      if (slotid == kNone)
-        fail(SAGE_ENOMEM, "pool full: no unreferenced block to evict (budget %llu slots)",
-             (unsigned long long)P.budget);
-      const uint32_t cl = P.new_class(f.fps[gb], len);
-      P.cls[cl].slot = slotid;
-      P.cls[cl].pending = ch.data + (uint64_t)i * kBlock;
-      P.index_add(cl);
-      created.push_back(cl);
-      chunk_new.push_back(cl);
-      P.cls[cl].mark = mark;
-      f.cls[gb] = cl;
-      cops[ncops++] = BlkOp{(uint64_t)(ch.data + (uint64_t)i * kBlock), (uint64_t)P.addr(slotid), len, 0};
-    };
-    // first candidate after `after` (or the first one) with the block's length
-    auto next_cand = [&](uint64_t fp, uint32_t len, uint32_t after) -> uint32_t {
-      uint32_t k = after == kNone ? P.chain_head(fp) : P.cls[after].next;
-      for (; k != kNone; k = P.cls[k].next) {
-        P.cls[k].mark = mark;
-        if (P.cls[k].len == len) return k;
+      const uint32_t gb = ch.first + i;
+      const uint8_t* data = ch.data + (uint64_t)i * kBlock;
+      const uint32_t cl = new_class_for(gb, data);
+      const BlkOp op{(uint64_t)data, (uint64_t)P.addr(P.cls[cl].slot), f.block_len(gb), 0};
+      if (deferred) {
+        dc.push_back(op);
+        dnew.push_back(cl);
+      } else {
+        cops[ncops++] = op;
+        chunk_new.push_back(cl);
       }
-      return kNone;
     };
     for (uint32_t i = 0; i < ch.nblk; i++) {
       const uint32_t gb = ch.first + i;
@@ -330,9 +357,13 @@ void register_shared(Ctx& c, Fn& f) {
       f.fps[gb] = fp;
       const uint32_t len = f.block_len(gb);
       const uint32_t cand = next_cand(fp, len, kNone);
-      if (cand != kNone) {
+      const uint8_t* data = ch.data + (uint64_t)i * kBlock;
+      if (cand != kNone && deferred) {
+        dpend.push_back({gb, cand, (uint32_t)dv.size(), data});
+        dv.push_back(BlkOp{(uint64_t)data, ref_addr(cand), len, 1});
+      } else if (cand != kNone) {
         pend.push_back({i, cand, nops});
-        ops[nops++] = BlkOp{(uint64_t)(ch.data + (uint64_t)i * kBlock), ref_addr(cand), len, 1};
+        ops[nops++] = BlkOp{(uint64_t)data, ref_addr(cand), len, 1};
       } else {
         make_new(i);
       }
@@ -381,6 +412,79 @@ void register_shared(Ctx& c, Fn& f) {
     c.t_dedup += now_ms() - t1;
   };
 
+  // the device-source chunks' VERIFYs, round by round until every block has
+  // its class, then one COPY launch for the new classes, left in flight
+  auto resolve_deferred = [&] {
+    if (dv.empty() && dc.empty()) return;
+    double t1 = now_ms();
+    HIPX(hipEventSynchronize(c.reg_ev));  // the previous registration's uploads have read the lists
+    const size_t need = std::max<size_t>(dv.size(), dc.size() + dv.size());
+    if (c.reg_cap < need) {
+      HIPX(hipStreamSynchronize(c.ctl));
+      if (c.reg_hops) HIPX(hipHostFree(c.reg_hops));
+      if (c.reg_hres) HIPX(hipHostFree(c.reg_hres));
+      if (c.reg_dops) HIPX(hipFree(c.reg_dops));
+      if (c.reg_dres) HIPX(hipFree(c.reg_dres));
+      c.reg_hops = c.reg_dops = nullptr;
+      c.reg_hres = c.reg_dres = nullptr;
+      c.reg_cap = 0;
+      const size_t cap = std::max<size_t>(need, 4096);
+      HIPX(hipHostMalloc((void**)&c.reg_hops, cap * sizeof(BlkOp), hipHostMallocDefault));
+      HIPX(hipHostMalloc((void**)&c.reg_hres, cap * 4, hipHostMallocDefault));
+      HIPX(hipMalloc((void**)&c.reg_dops, cap * sizeof(BlkOp)));
+      HIPX(hipMalloc((void**)&c.reg_dres, cap * 4));
+      c.reg_cap = cap;
+    }
+    hipStream_t s = c.ctl;
+    while (!dv.empty()) {
+      const double tv = now_ms();
+      c.t_dedup += tv - t1;
+      const uint32_t n = (uint32_t)dv.size();
+      std::memcpy(c.reg_hops, dv.data(), n * sizeof(BlkOp));
+      HIPX(hipMemcpyAsync(c.reg_dops, c.reg_hops, n * sizeof(BlkOp), hipMemcpyHostToDevice, s));
+      const int tok = c.timer.start("blkcopy", s, 1);
+      HIPX(launch_blkcopy(c.reg_dops, n, c.reg_dres, c.max_groups_copy(), s));
+      c.timer.stop(tok, s);
+      HIPX(hipMemcpyAsync(c.reg_hres, c.reg_dres, n * 4, hipMemcpyDeviceToHost, s));
+      HIPX(hipEventRecord(c.reg_ev, s));
+      HIPX(hipEventSynchronize(c.reg_ev));
+      t1 = now_ms();
+      c.t_verify += t1 - tv;
+      std::vector<BlkOp> dv2;
+      std::vector<DPend> dp2;
+      for (const DPend& q : dpend) {
+        if (c.reg_hres[q.op] == 0) {
+          f.cls[q.gb] = q.cand;
+          continue;
+        }
+        c.mismatches++;
+        const uint32_t len = f.block_len(q.gb);
+        const uint32_t nxt = next_cand(f.fps[q.gb], len, q.cand);
+        if (nxt != kNone) {
+          dp2.push_back({q.gb, nxt, (uint32_t)dv2.size(), q.data});
+          dv2.push_back(BlkOp{(uint64_t)q.data, ref_addr(nxt), len, 1});
+        } else {
+          const uint32_t cl = new_class_for(q.gb, q.data);
+          dc.push_back(BlkOp{(uint64_t)q.data, (uint64_t)P.addr(P.cls[cl].slot), len, 0});
+          dnew.push_back(cl);
+        }
+      }
+      dv.swap(dv2);
+      dpend.swap(dp2);
+    }
+    if (!dc.empty()) {
+      const uint32_t n = (uint32_t)dc.size();
+      std::memcpy(c.reg_hops, dc.data(), n * sizeof(BlkOp));
+      HIPX(hipMemcpyAsync(c.reg_dops, c.reg_hops, n * sizeof(BlkOp), hipMemcpyHostToDevice, s));
+      const int tok = c.timer.start("blkcopy", s, 1);
+      HIPX(launch_blkcopy(c.reg_dops, n, c.reg_dres, c.max_groups_copy(), s));
+      c.timer.stop(tok, s);
+      HIPX(hipEventRecord(c.reg_ev, s));  // the lists are free again once this COPY has run
+    }
+    for (uint32_t cl : dnew) P.cls[cl].pending = nullptr;
+    c.t_dedup += now_ms() - t1;
+  };
+
   try {
     std::deque<size_t> inflight;
     size_t next = 0;
@@ -394,6 +498,7 @@ void register_shared(Ctx& c, Fn& f) {
       process(ch);
       free_slots.push_back(ch.slot);
     }
+    resolve_deferred();
   } catch (...) {
     for (hipStream_t s : c.streams) (void)hipStreamSynchronize(s);
     (void)hipStreamSynchronize(c.ctl);
