@@ -391,7 +391,8 @@ struct Ctx {
   uint32_t* reg_hres = nullptr;
   uint32_t* reg_dres = nullptr;
   size_t reg_cap = 0;
-  hipEvent_t reg_ev = nullptr;
+  hipEvent_t reg_ev = nullptr;   // behind the last COPY that reads the lists
+  hipEvent_t reg_vev = nullptr;  // behind the last VERIFY results' copy to the host
   // reload staging: device area, one region per batch, each with the event
   // of the batch that last used it; pageable sources go through ring slots
   uint8_t* rstage_dev = nullptr;

@@ -359,6 +359,7 @@ void register_shared(Ctx& c, Fn& f) {
       const uint32_t cand = next_cand(fp, len, kNone);
       const uint8_t* data = ch.data + (uint64_t)i * kBlock;
       if (cand != kNone && deferred) {
+        f.cls[gb] = cand;  // until its VERIFY says otherwise
         dpend.push_back({gb, cand, (uint32_t)dv.size(), data});
         dv.push_back(BlkOp{(uint64_t)data, ref_addr(cand), len, 1});
       } else if (cand != kNone) {
@@ -412,77 +413,129 @@ void register_shared(Ctx& c, Fn& f) {
     c.t_dedup += now_ms() - t1;
   };
 
-  // the device-source chunks' VERIFYs, round by round until every block has
-  // its class, then one COPY launch for the new classes, left in flight
-  auto resolve_deferred = [&] {
+  // Device-source chunks, at the end of the registration: every gathered
+  // VERIFY and the COPY of the classes created so far go out at once (op
+  // list up, VERIFY, its results down, COPY left in flight), and the
+  // blocks are counted into their candidates' classes before the results
+  // are back.  A failed VERIFY (a fingerprint collision) takes the counts
+  // back, settles the blocks round by round as the staged chunks do, copies
+  // the classes that split off and counts again.
+  auto reg_reserve = [&](size_t need) {
+    if (c.reg_cap >= need) return;
+    HIPX(hipStreamSynchronize(c.ctl));
+    if (c.reg_hops) HIPX(hipHostFree(c.reg_hops));
+    if (c.reg_hres) HIPX(hipHostFree(c.reg_hres));
+    if (c.reg_dops) HIPX(hipFree(c.reg_dops));
+    if (c.reg_dres) HIPX(hipFree(c.reg_dres));
+    c.reg_hops = c.reg_dops = nullptr;
+    c.reg_hres = c.reg_dres = nullptr;
+    c.reg_cap = 0;
+    const size_t cap = std::max<size_t>(need, 4096);
+    HIPX(hipHostMalloc((void**)&c.reg_hops, cap * sizeof(BlkOp), hipHostMallocDefault));
+    HIPX(hipHostMalloc((void**)&c.reg_hres, cap * 4, hipHostMallocDefault));
+    HIPX(hipMalloc((void**)&c.reg_dops, cap * sizeof(BlkOp)));
+    HIPX(hipMalloc((void**)&c.reg_dres, cap * 4));
+    c.reg_cap = cap;
+  };
+  hipStream_t ctl = c.ctl;
+  auto launch_ops = [&](const BlkOp* dev_ops, uint32_t n, uint32_t* dev_res) {
+    const int tok = c.timer.start("blkcopy", ctl, 1);
+    HIPX(launch_blkcopy(dev_ops, n, dev_res, c.max_groups_copy(), ctl));
+    c.timer.stop(tok, ctl);
+  };
+  auto start_deferred = [&] {
     if (dv.empty() && dc.empty()) return;
-    double t1 = now_ms();
-    HIPX(hipEventSynchronize(c.reg_ev));  // the previous registration's uploads have read the lists
-    const size_t need = std::max<size_t>(dv.size(), dc.size() + dv.size());
-    if (c.reg_cap < need) {
-      HIPX(hipStreamSynchronize(c.ctl));
-      if (c.reg_hops) HIPX(hipHostFree(c.reg_hops));
-      if (c.reg_hres) HIPX(hipHostFree(c.reg_hres));
-      if (c.reg_dops) HIPX(hipFree(c.reg_dops));
-      if (c.reg_dres) HIPX(hipFree(c.reg_dres));
-      c.reg_hops = c.reg_dops = nullptr;
-      c.reg_hres = c.reg_dres = nullptr;
-      c.reg_cap = 0;
-      const size_t cap = std::max<size_t>(need, 4096);
-      HIPX(hipHostMalloc((void**)&c.reg_hops, cap * sizeof(BlkOp), hipHostMallocDefault));
-      HIPX(hipHostMalloc((void**)&c.reg_hres, cap * 4, hipHostMallocDefault));
-      HIPX(hipMalloc((void**)&c.reg_dops, cap * sizeof(BlkOp)));
-      HIPX(hipMalloc((void**)&c.reg_dres, cap * 4));
-      c.reg_cap = cap;
+    HIPX(hipEventSynchronize(c.reg_ev));  // the previous registration's COPY has read the lists
+    reg_reserve(dv.size() + dc.size());
+    const uint32_t nv = (uint32_t)dv.size(), nc = (uint32_t)dc.size();
+    std::memcpy(c.reg_hops, dv.data(), nv * sizeof(BlkOp));
+    std::memcpy(c.reg_hops + nv, dc.data(), nc * sizeof(BlkOp));
+    HIPX(hipMemcpyAsync(c.reg_dops, c.reg_hops, (size_t)(nv + nc) * sizeof(BlkOp), hipMemcpyHostToDevice, ctl));
+    if (nv) {
+      launch_ops(c.reg_dops, nv, c.reg_dres);
+      HIPX(hipMemcpyAsync(c.reg_hres, c.reg_dres, nv * 4, hipMemcpyDeviceToHost, ctl));
+      HIPX(hipEventRecord(c.reg_vev, ctl));
     }
-    hipStream_t s = c.ctl;
-    while (!dv.empty()) {
-      const double tv = now_ms();
-      c.t_dedup += tv - t1;
-      const uint32_t n = (uint32_t)dv.size();
-      std::memcpy(c.reg_hops, dv.data(), n * sizeof(BlkOp));
-      HIPX(hipMemcpyAsync(c.reg_dops, c.reg_hops, n * sizeof(BlkOp), hipMemcpyHostToDevice, s));
-      const int tok = c.timer.start("blkcopy", s, 1);
-      HIPX(launch_blkcopy(c.reg_dops, n, c.reg_dres, c.max_groups_copy(), s));
-      c.timer.stop(tok, s);
-      HIPX(hipMemcpyAsync(c.reg_hres, c.reg_dres, n * 4, hipMemcpyDeviceToHost, s));
-      HIPX(hipEventRecord(c.reg_ev, s));
-      HIPX(hipEventSynchronize(c.reg_ev));
-      t1 = now_ms();
-      c.t_verify += t1 - tv;
-      std::vector<BlkOp> dv2;
-      std::vector<DPend> dp2;
-      for (const DPend& q : dpend) {
-        if (c.reg_hres[q.op] == 0) {
-          f.cls[q.gb] = q.cand;
-          continue;
-        }
-        c.mismatches++;
-        const uint32_t len = f.block_len(q.gb);
-        const uint32_t nxt = next_cand(f.fps[q.gb], len, q.cand);
-        if (nxt != kNone) {
-          dp2.push_back({q.gb, nxt, (uint32_t)dv2.size(), q.data});
-          dv2.push_back(BlkOp{(uint64_t)q.data, ref_addr(nxt), len, 1});
-        } else {
-          const uint32_t cl = new_class_for(q.gb, q.data);
-          dc.push_back(BlkOp{(uint64_t)q.data, (uint64_t)P.addr(P.cls[cl].slot), len, 0});
-          dnew.push_back(cl);
-        }
+    if (nc) launch_ops(c.reg_dops + nv, nc, c.reg_dres + nv);
+    HIPX(hipEventRecord(c.reg_ev, ctl));
+    dc.clear();
+  };
+  bool counted = false;
+  auto count_in = [&] {
+    for (uint32_t cl : f.cls) P.cls[cl].members++;
+    counted = true;
+    // distinct classes in creation order (the order ties are broken in)
+    const uint32_t dmark = P.new_mark();
+    f.distinct.clear();
+    for (uint32_t cl : f.cls)
+      if (P.cls[cl].mark != dmark) {
+        P.cls[cl].mark = dmark;
+        f.distinct.push_back(cl);
       }
-      dv.swap(dv2);
-      dpend.swap(dp2);
+    P.sort_by_seq(f.distinct);
+    const double now = now_ms();
+    for (uint32_t cl : f.distinct)
+      if (P.cls[cl].active == 0) P.lru_back(cl, now);
+  };
+  auto finish_deferred = [&] {
+    if (!dv.empty()) {
+      const double tv = now_ms();
+      HIPX(hipEventSynchronize(c.reg_vev));
+      c.t_verify += now_ms() - tv;
+      bool all_equal = true;
+      for (size_t q = 0; q < dv.size() && all_equal; q++) all_equal = c.reg_hres[q] == 0;
+      if (!all_equal) {
+        for (uint32_t cl : f.cls) P.cls[cl].members--;
+        counted = false;
+        for (uint32_t cl : f.cls) P.cls[cl].mark = mark;  // protected again while classes split off
+        bool first_round = true;
+        while (!dv.empty()) {
+          if (!first_round) {
+            const double tr = now_ms();
+            const uint32_t n = (uint32_t)dv.size();
+            std::memcpy(c.reg_hops, dv.data(), n * sizeof(BlkOp));
+            HIPX(hipMemcpyAsync(c.reg_dops, c.reg_hops, n * sizeof(BlkOp), hipMemcpyHostToDevice, ctl));
+            launch_ops(c.reg_dops, n, c.reg_dres);
+            HIPX(hipMemcpyAsync(c.reg_hres, c.reg_dres, n * 4, hipMemcpyDeviceToHost, ctl));
+            HIPX(hipEventRecord(c.reg_vev, ctl));
+            HIPX(hipEventSynchronize(c.reg_vev));
+            c.t_verify += now_ms() - tr;
+          }
+          first_round = false;
+          std::vector<BlkOp> dv2;
+          std::vector<DPend> dp2;
+          for (const DPend& q : dpend) {
+            if (c.reg_hres[q.op] == 0) {
+              f.cls[q.gb] = q.cand;
+              continue;
+            }
+            c.mismatches++;
+            const uint32_t len = f.block_len(q.gb);
+            const uint32_t nxt = next_cand(f.fps[q.gb], len, q.cand);
+            if (nxt != kNone) {
+              f.cls[q.gb] = nxt;
+              dp2.push_back({q.gb, nxt, (uint32_t)dv2.size(), q.data});
+              dv2.push_back(BlkOp{(uint64_t)q.data, ref_addr(nxt), len, 1});
+            } else {
+              const uint32_t cl = new_class_for(q.gb, q.data);
+              dc.push_back(BlkOp{(uint64_t)q.data, (uint64_t)P.addr(P.cls[cl].slot), len, 0});
+              dnew.push_back(cl);
+            }
+          }
+          dv.swap(dv2);
+          dpend.swap(dp2);
+        }
+        if (!dc.empty()) {
+          const uint32_t n = (uint32_t)dc.size();
+          std::memcpy(c.reg_hops, dc.data(), n * sizeof(BlkOp));
+          HIPX(hipMemcpyAsync(c.reg_dops, c.reg_hops, n * sizeof(BlkOp), hipMemcpyHostToDevice, ctl));
+          launch_ops(c.reg_dops, n, c.reg_dres);
+          HIPX(hipEventRecord(c.reg_ev, ctl));
+        }
+        count_in();
+      }
     }
-    if (!dc.empty()) {
-      const uint32_t n = (uint32_t)dc.size();
-      std::memcpy(c.reg_hops, dc.data(), n * sizeof(BlkOp));
-      HIPX(hipMemcpyAsync(c.reg_dops, c.reg_hops, n * sizeof(BlkOp), hipMemcpyHostToDevice, s));
-      const int tok = c.timer.start("blkcopy", s, 1);
-      HIPX(launch_blkcopy(c.reg_dops, n, c.reg_dres, c.max_groups_copy(), s));
-      c.timer.stop(tok, s);
-      HIPX(hipEventRecord(c.reg_ev, s));  // the lists are free again once this COPY has run
-    }
-    for (uint32_t cl : dnew) P.cls[cl].pending = nullptr;
-    c.t_dedup += now_ms() - t1;
+    for (uint32_t cl : dnew) P.cls[cl].pending = nullptr;  // their COPYs are ordered on the control stream
   };
 
   try {
@@ -498,26 +551,17 @@ void register_shared(Ctx& c, Fn& f) {
       process(ch);
       free_slots.push_back(ch.slot);
     }
-    resolve_deferred();
+    start_deferred();
+    count_in();  // optimistic for the deferred VERIFYs: corrected above if one fails
+    finish_deferred();
   } catch (...) {
     for (hipStream_t s : c.streams) (void)hipStreamSynchronize(s);
     (void)hipStreamSynchronize(c.ctl);
+    if (counted)
+      for (uint32_t cl : f.cls) P.cls[cl].members--;
     for (uint32_t cl : created) P.drop_class(cl);
     throw;
   }
-  for (uint32_t cl : f.cls) P.cls[cl].members++;
-  // distinct classes in creation order (the order ties are broken in)
-  const uint32_t dmark = P.new_mark();
-  f.distinct.clear();
-  for (uint32_t cl : f.cls)
-    if (P.cls[cl].mark != dmark) {
-      P.cls[cl].mark = dmark;
-      f.distinct.push_back(cl);
-    }
-  P.sort_by_seq(f.distinct);
-  const double now = now_ms();
-  for (uint32_t cl : f.distinct)
-    if (P.cls[cl].active == 0) P.lru_back(cl, now);
   c.h2d += f.ro_bytes;
 }
 

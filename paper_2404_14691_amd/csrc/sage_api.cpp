@@ -237,6 +237,7 @@ sage_status sage_open(int device, const sage_config* cfg, sage_ctx** out) {
     HIPX(hipEventCreateWithFlags(&c.reload_done, hipEventDisableTiming));
     HIPX(hipEventCreateWithFlags(&c.prog_ops_ev, hipEventDisableTiming));
     HIPX(hipEventCreateWithFlags(&c.reg_ev, hipEventDisableTiming));
+    HIPX(hipEventCreateWithFlags(&c.reg_vev, hipEventDisableTiming));
     for (uint32_t i = 0; i < c.cfg.streams; i++) {
       hipStream_t s;
       HIPX(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
@@ -297,6 +298,7 @@ sage_status sage_close(sage_ctx* p) {
       if (c.prog_ops_ev) (void)hipEventDestroy(c.prog_ops_ev);
       if (c.prog_hops) (void)hipHostFree(c.prog_hops);
       if (c.reg_ev) (void)hipEventDestroy(c.reg_ev);
+      if (c.reg_vev) (void)hipEventDestroy(c.reg_vev);
       if (c.reg_hops) (void)hipHostFree(c.reg_hops);
       if (c.reg_hres) (void)hipHostFree(c.reg_hres);
       if (c.reg_dops) (void)hipFree(c.reg_dops);

@@ -106,16 +106,24 @@ def test_register_serial_and_unpipelined_agree(sage_ctx_factory, torch_cuda):
         assert np.array_equal(a, b)
 
 
-def test_forced_fingerprint_collisions(sage_ctx_factory, torch_cuda, monkeypatch):
+@pytest.mark.parametrize("where", ["host", "device"])
+def test_forced_fingerprint_collisions(sage_ctx_factory, torch_cuda, monkeypatch, where):
     """Every fingerprint forced to one value: only byte verification keeps
-    blocks apart, and the partition is still the byte-exact one."""
+    blocks apart, and the partition is still the byte-exact one (staged
+    chunks settle their VERIFYs chunk by chunk; device sources at the end of
+    the registration, after counting the blocks in optimistically)."""
     from paper_2404_14691_amd import sage as S
+    torch = torch_cuda
     monkeypatch.setenv("SAGE_TEST_FP_CONST", "12345")
     ctx = sage_ctx_factory(chunk_bytes=256 << 10, ring_slots=2)
     monkeypatch.delenv("SAGE_TEST_FP_CONST")
     # BF16 MLP of width 256 and 8 layers: 1 MiB = the first 16 blocks of each blob
     blobs = [np.ascontiguousarray(b[: 8 * 256 * 256]) for b in _blobs()]
-    fns = [S.fn_register(ctx, S.mlp_desc(S.SAGE_MLP_BF16, 8, 256), [S.make_blob(b)]) for b in blobs]
+    keep = [torch.from_numpy(b.view(np.uint8)).cuda() for b in blobs] if where == "device" else []
+    torch.cuda.synchronize()
+    srcs = [S.make_blob(d.data_ptr(), d.numel(), where=S.SAGE_SRC_DEVICE) for d in keep] if where == "device" \
+        else [S.make_blob(b) for b in blobs]
+    fns = [S.fn_register(ctx, S.mlp_desc(S.SAGE_MLP_BF16, 8, 256), [s]) for s in srcs]
     canon = OD.partition_dict(blobs, 65536)
     lib = [[(int(c),) for c in S.sage_fn_block_info(ctx, f)[0]] for f in fns]
     assert OD.same_partition(canon, lib)
@@ -144,3 +152,49 @@ def test_register_rejects_bad_layouts(sage_ctx_factory, torch_cuda):
     with pytest.raises(S.SageError) as e:
         S.fn_setup(ctx, 999999, 1)
     assert e.value.status == S.SAGE_ENOTFOUND
+
+
+def test_device_source_across_chunks(sage_ctx_factory, torch_cuda):
+    """A 160 MiB device source is fingerprinted in three chunks; blocks equal
+    to blocks of earlier chunks (still being copied from the source) and to
+    another function's blocks join their classes; fingerprints, partition,
+    accounting and sampled slot bytes match the oracle."""
+    from paper_2404_14691_amd import sage as S
+    torch = torch_cuda
+    layers, width = 5, 4096                      # 5 x 32 MiB = 2560 blocks
+    w = synth.shared_mlp_bf16_functions(n_fns=2, layers=layers, width=width, share_frac=0.1, seed=9)
+    blobs = [b.copy() for b in w.blobs]
+    per = 65536 // 2
+    planted = [(1500, 10), (2100, 10), (2500, 1100), (1030, 1029)]   # (copy, original): across chunks
+    for dst, src in planted:
+        blobs[0][dst * per:(dst + 1) * per] = blobs[0][src * per:(src + 1) * per]
+    blobs[0][30 * per:31 * per] = 0
+    blobs[0][2300 * per:2301 * per] = 0
+    blobs[1][700 * per:701 * per] = blobs[0][2200 * per:2201 * per]    # the second function joins a late class
+    ctx = sage_ctx_factory(pool_budget_bytes=1 << 30)
+    dev = [torch.from_numpy(b.view(np.uint8)).cuda() for b in blobs]
+    torch.cuda.synchronize()
+    desc = S.mlp_desc(S.SAGE_MLP_BF16, layers, width)
+    fns = [S.fn_register(ctx, desc, [S.make_blob(d.data_ptr(), d.numel(), where=S.SAGE_SRC_DEVICE)]) for d in dev]
+    for f, b in zip(fns, blobs):
+        assert np.array_equal(S.sage_fn_fingerprints(ctx, f), OF.fp64k_blob(b))
+    canon = OD.partition_dict(blobs, 65536)
+    info = [S.sage_fn_block_info(ctx, f) for f in fns]
+    assert OD.same_partition(canon, [[(int(c),) for c in cls] for cls, _, _ in info])
+    cls0 = info[0][0]
+    for dst, src in planted:
+        assert cls0[dst] == cls0[src]
+    assert cls0[30] == cls0[2300] and info[1][0][700] == cls0[2200]
+    acc = OD.accounting(blobs, 65536, canon)
+    st = S.sage_get_stats(ctx)
+    assert st["unique_bytes"] == acc["unique"] and st["classes"] == acc["n_classes"]
+    rng = np.random.default_rng(9)
+    for fi, b in enumerate(blobs):
+        raw = b.view(np.uint8)
+        slots = info[fi][1]
+        picks = sorted(set(rng.choice(len(slots), 48, replace=False).tolist()) | {d for d, _ in planted} | {30, 2300})
+        for k in picks:
+            assert np.array_equal(S.sage_read_slot(ctx, int(slots[k])), raw[k * 65536:(k + 1) * 65536]), (fi, k)
+    for f in fns:
+        S.fn_unregister(ctx, f)
+
