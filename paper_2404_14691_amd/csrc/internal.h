@@ -157,7 +157,7 @@ class Pool {
   void init(uint64_t budget_slots, size_t seg_slots);
   void destroy();
   uint8_t* addr(uint32_t slot) const {
-    return segs_[slot / seg_slots_] + (uint64_t)(slot % seg_slots_) * kBlock;
+    return segs_[slot >> seg_shift_] + (uint64_t)(slot & (seg_slots_ - 1)) * kBlock;
   }
   // Take a free slot, growing the arena up to the budget, else evicting the
   // front unreferenced class that `protect` does not hold.  kNone if none.
@@ -190,7 +190,8 @@ class Pool {
  private:
   bool grow_arena();
   std::vector<uint8_t*> segs_;
-  size_t seg_slots_ = 16384;
+  size_t seg_slots_ = 16384;  // slot ids of segment k start at k * seg_slots_ (a power of two)
+  uint32_t seg_shift_ = 14;
   std::vector<uint32_t> free_;
   std::vector<uint32_t> free_cls_;
   std::vector<uint32_t> free_hbufs_;

@@ -77,7 +77,11 @@ void FpIndex::clear() {
 // ---------------------------------------------------------------- Pool
 void Pool::init(uint64_t budget_slots, size_t seg_slots) {
   budget = budget_slots;
-  seg_slots_ = seg_slots;
+  // a power-of-two stride, so that a slot's segment and offset are a shift
+  // and a mask; a segment still holds no more slots than the budget leaves
+  seg_shift_ = 0;
+  while (((size_t)1 << seg_shift_) < std::max<size_t>(seg_slots, 1)) seg_shift_++;
+  seg_slots_ = (size_t)1 << seg_shift_;
 }
 
 void Pool::destroy() {

@@ -294,6 +294,13 @@ void register_shared(Ctx& c, Fn& f) {
   std::vector<BlkOp> dv, dc;
   std::vector<DPend> dpend;
   std::vector<uint32_t> dnew;
+  bool any_dev = false;
+  for (const Src& sr : f.srcs) any_dev |= sr.dev;
+  if (any_dev) {
+    dv.reserve(f.n_blocks);
+    dc.reserve(f.n_blocks);
+    dpend.reserve(f.n_blocks);
+  }
 
   auto issue = [&](Chunk& ch) {
     ch.slot = free_slots.back();
