@@ -307,8 +307,12 @@ void register_shared(Ctx& c, Fn& f) {
     free_slots.pop_back();
     HIPX(hipEventSynchronize(R.ev[ch.slot]));  // e.g. a progressive reload still reading the slot
     ring_reserve(c, ch.slot, ch.nblk);
-    hipStream_t s = stream_of(ch.slot);
     const Src& src = f.srcs[ch.blob];
+    // device chunks are fingerprinted one after another on one stream, so
+    // the first chunk's fingerprints arrive first instead of all at once
+    // (they only share HBM bandwidth); staged chunks keep their slot's stream
+    // for the host-to-device copies
+    hipStream_t s = src.dev ? c.streams[0] : stream_of(ch.slot);
     if (src.dev) {
       ch.data = src.p + ch.off;
     } else {
