@@ -276,6 +276,98 @@ def host_link(S, torch, wl):
     return out
 
 
+def _host_cpu():
+    """(BLAS threads, nproc, CPU model) of this host."""
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    cpu = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
+    except OSError:
+        pass
+    return int(cores), os.cpu_count(), cpu
+
+
+def cpu_baseline_workload(name, min_s=3.0):
+    """The oracle on the host for a secondary workload, on a bounded sample
+    of it, in the workload's unit (invocations/s); None for workloads
+    without one."""
+    from oracle import fingerprint as OF
+    from oracle import mlp as OM
+    from oracle import stencil as OS
+    from paper_2404_14691_amd import synth
+    cores, nproc, cpu = _host_cpu()
+    if name == "mlp_f32":
+        # a step registers the 32 MiB of weights (fingerprints) and runs 16 invocations of 8 rows
+        wl = synth.mlp_f32_workload()
+        t0 = time.perf_counter()
+        passes = 0
+        while passes < 2 or time.perf_counter() - t0 < min_s:
+            OF.fp64k_blob(wl.weights)
+            W = wl.weights.astype(np.float64)
+            for x in wl.inputs:
+                OM.mlp_forward(x, W)
+            passes += 1
+        el = time.perf_counter() - t0
+        value = 16 * passes / el
+        sample = (f"{passes} passes of the workload's 16 invocations (2 x 2048^2 float64 layers, 8 rows), each "
+                  f"pass with the fingerprints of the 32 MiB of weights; {el:.1f} s")
+    elif name == "stencil":
+        # one sweep of one 512^3 field; an invocation is 20 sweeps, a step
+        # 32 invocations plus the fingerprints of the 512 MiB coefficient grid
+        n, sweeps, n_inv = 512, 20, 32
+        c = synth.stencil_coefficients(n, seed=0)
+        t0 = time.perf_counter()
+        OF.fp64k_blob(c)
+        t_fp = time.perf_counter() - t0
+        u0 = synth.stencil_field(n, 0, seed=0)
+        t0 = time.perf_counter()
+        OS.jacobi7(u0, c, 1)
+        t_sw = time.perf_counter() - t0
+        del u0, c
+        step_s = t_fp + n_inv * sweeps * t_sw
+        value = n_inv / step_s
+        cores = 1  # numpy's elementwise array arithmetic runs on one thread
+        sample = (f"one float64 sweep of one 512^3 field ({t_sw:.2f} s = {n ** 3 / t_sw / 1e6:.0f} Mcell/s) and "
+                  f"the fingerprints of the 512 MiB coefficient grid ({t_fp:.2f} s); step = fingerprints + "
+                  f"{n_inv} invocations x {sweeps} sweeps ({step_s:.0f} s, extrapolated)")
+    elif name == "batching":
+        # the 256 invocations in a seeded order, at least 16 and until min_s
+        # of invocation time; extrapolated to the step when cut short
+        W_, L_ = 4096, 8
+        w = synth.shared_mlp_bf16_functions(n_fns=1, layers=L_, width=W_, share_frac=0.0, seed=3)
+        batches = [int(b) for b in synth.lognormal_batches(256, seed=3)]
+        order = np.random.default_rng(0).permutation(256)
+        t0 = time.perf_counter()
+        OF.fp64k_blob(w.blobs[0])
+        t_fp = time.perf_counter() - t0
+        Wt = OM.bf16_to_f64(w.blobs[0]).reshape(L_, W_, W_)
+        t_inv, done = 0.0, []
+        for i in order:
+            if len(done) >= 16 and t_inv >= min_s:
+                break
+            x = OM.bf16_to_f64(synth.bf16_inputs(batches[i], W_, 3, int(i)))
+            t0 = time.perf_counter()
+            OM.mlp_forward(x, Wt)
+            t_inv += time.perf_counter() - t0
+            done.append(int(i))
+        del Wt
+        step_s = t_fp + 256 * t_inv / len(done)
+        value = 256 / step_s
+        sample = (f"{len(done)} of the 256 invocations in a seeded order ({sum(batches[i] for i in done)} rows, "
+                  f"{t_inv:.1f} s) and the fingerprints of the 256 MiB of weights ({t_fp:.1f} s) in float64 "
+                  f"numpy; step = fingerprints + 256 x mean invocation ({step_s:.1f} s"
+                  f"{', extrapolated' if len(done) < 256 else ''})")
+    else:
+        return None
+    return {"value": float(f"{value:.4g}"), "unit": "invocations/s", "cores": cores, "kind": "oracle", "nproc": nproc,
+            "cpu_model": cpu, "sample": sample}
+
+
 def cpu_baseline(wl, min_s=10.0, max_inv=1024):
     """The oracle on the host: fingerprints and the cross-function dedup map
     of all functions' blobs, then invocations of the workload's requests in
@@ -299,19 +391,9 @@ def cpu_baseline(wl, min_s=10.0, max_inv=1024):
         n_inv += 1
     del Ws
     step_s = t_reg + len(wl.requests) * t_inv / n_inv
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:
-        cores = os.cpu_count() or 1
-    cpu = ""
-    try:
-        with open("/proc/cpuinfo") as fh:
-            cpu = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
-    except OSError:
-        pass
-    return {"value": len(wl.requests) / step_s, "unit": "invocations/s", "cores": int(cores), "kind": "oracle",
-            "nproc": os.cpu_count(), "cpu_model": cpu, "blas_threads": int(cores),
+    cores, nproc, cpu = _host_cpu()
+    return {"value": len(wl.requests) / step_s, "unit": "invocations/s", "cores": cores, "kind": "oracle",
+            "nproc": nproc, "cpu_model": cpu, "blas_threads": cores,
             "sample": f"fingerprints + cross-function dedup map of all {wl.n_fns} functions (4 x 256 MiB, "
                       f"{t_reg:.1f} s) and {n_inv} invocations of the workload's requests in order "
                       f"({t_inv:.1f} s) in float64 numpy; step = registrations + {len(wl.requests)} x mean "
@@ -344,7 +426,13 @@ def main():
 
     if args.workload != "sharing":
         import bench_workloads
-        print(bench_workloads.WORKLOADS[args.workload](S, torch, log), flush=True)
+        line = json.loads(bench_workloads.WORKLOADS[args.workload](S, torch, log))
+        if not args.no_cpu:
+            cb = cpu_baseline_workload(args.workload)
+            if cb is not None:
+                log("cpu baseline (oracle) done")
+                line["cpu_baseline"] = cb
+        print(json.dumps(line), flush=True)
         return
 
     log("generating workload")
