@@ -211,6 +211,7 @@ def mlp_f32(S, torch, log, reps=5):
     blob = wl.weights.reshape(-1)
     desc = S.mlp_desc(S.SAGE_MLP_F32, 2, 2048)
     res = {}
+    k_ms = k_n = 0
     for name, share in (("shared", 1), ("plain", 0)):
         cfg = S.sage_config_default()
         cfg.share = share
@@ -219,6 +220,9 @@ def mlp_f32(S, torch, log, reps=5):
         try:
             times, lat = [], []
             for r in range(reps + 1):
+                if share and r == 1:  # device time of the layer launches over the timed passes
+                    S.sage_timing_reset(ctx)
+                    S.sage_timing_enable(ctx, True)
                 y = np.zeros((8, 2048), dtype=np.float32)
                 t0 = time.perf_counter()
                 fn = S.fn_register(ctx, desc, [S.make_blob(blob)])
@@ -235,15 +239,26 @@ def mlp_f32(S, torch, log, reps=5):
                     lat += one
             res[name] = {"ms_16_invocations": round(min(times) * 1e3, 3), "invocation_ms_p50": round(_pct(lat, 50), 4),
                          "invocation_ms_p99": round(_pct(lat, 99), 4)}
+            if share:
+                S.sage_timing_enable(ctx, False)
+                k_ms, k_n = S.sage_timing_get(ctx, "mlp_f32")
         finally:
             S.sage_close(ctx)
     value = 16 / (res["shared"]["ms_16_invocations"] * 1e-3)
+    # one launch is one layer of one invocation: 2048^2 FP32 weights read,
+    # 8 rows of input read and of output written
+    avg = k_ms / max(k_n, 1)
+    alg = 2048 * 2048 * 4 + 2 * 8 * 2048 * 4
+    gbs = alg / (avg * 1e-3) / 1e9 if k_n else 0.0
     return _line("invocations/sec, shared vs plain, 1 MI355X", value, "invocations/s", reps, 1,
                  res["shared"]["ms_16_invocations"],
                  {"workload": "mlp_f32: 2-layer FP32 MLP 2048x2048 (32 MiB weights in host memory), 16 sequential "
                               "invocations of 8 rows, host inputs/outputs; includes fn_register"},
                  "f32", detail=res,
-                 speedup_vs_plain=round(res["plain"]["ms_16_invocations"] / res["shared"]["ms_16_invocations"], 2))
+                 speedup_vs_plain=round(res["plain"]["ms_16_invocations"] / res["shared"]["ms_16_invocations"], 2),
+                 roofline={"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "mlp_f32_layer",
+                           "avg_launch_ms": round(avg, 5), "bytes_per_launch": alg, "launches": k_n})
 
 
 # ---------------------------------------------------------------- serving

@@ -698,13 +698,23 @@ SAGE_GGEMM6(ggemm6_bf16_256x128, 256, 128, 64, 64, 4, false)
 
 // ---------------------------------------------------------------- FP32 MLP
 // Tiles: (group, block of 8 output columns); wave w of the workgroup owns
-// columns 8*cb + 2w and 8*cb + 2w + 1 and walks the group's rows 8 at a
-// time.  Lane l accumulates k = 4l + 256i (i = 0, 1, ...) with fmaf in order,
-// then a fixed xor-butterfly sums the lanes.
+// columns 8*cb + 2w and 8*cb + 2w + 1 and walks the group's rows 8 at a time.
+// Lane l accumulates k = 4l + 256i (i = 0, 1, ...) with fmaf in order, then a
+// fixed xor-butterfly sums the lanes, so the order depends on nothing but K.
+// A few rows are bound by load latency, not bandwidth: per K chunk of 2048,
+// each wave loads its two weight rows into registers with every load issued
+// before the first FMA, and the workgroup stages the 8 input rows in LDS
+// once for its four waves.
+constexpr uint32_t kF32KC = 2048;                       // K per chunk
+typedef __attribute__((address_space(1))) const f32x4 g_f32x4;
+
 extern "C" __global__ __launch_bounds__(256) void mlp_f32_layer(const GemmHdr* __restrict__ hdr,
                                                                 const GemmGroup* __restrict__ groups,
                                                                 LayerArgs la) {
-  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __shared__ __attribute__((aligned(16))) float xs[8][kF32KC];
+  constexpr int WPL = kF32KC / 256;                     // float4 per lane per weight row per chunk
+  constexpr int XPT = 8 * kF32KC / 4 / 256;             // float4 of staged rows per thread per chunk
+  const uint32_t t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const uint32_t K = la.K;
   const bool relu = la.flags & kRelu;
   for (uint32_t tile = blockIdx.x; tile < hdr->total_tiles; tile += gridDim.x) {
@@ -716,30 +726,55 @@ extern "C" __global__ __launch_bounds__(256) void mlp_f32_layer(const GemmHdr* _
     const float* w1 = reinterpret_cast<const float*>(wtab[off1 >> kBlockShift] + (off1 & (kBlock - 1)));
     for (uint32_t r0 = 0; r0 < gr.m; r0 += 8) {
       const uint32_t nr = gr.m - r0 < 8 ? gr.m - r0 : 8;
-      const float* ar[8];
-#pragma unroll
-      for (int i = 0; i < 8; i++)
-        ar[i] = reinterpret_cast<const float*>(a_row(la, gr.row0 + r0 + ((uint32_t)i < nr ? i : 0), 4));
       float acc0[8], acc1[8];
 #pragma unroll
       for (int i = 0; i < 8; i++) acc0[i] = acc1[i] = 0.f;
-      for (uint32_t k = lane * 4; k < K; k += 256) {
-        const float4 wa = *reinterpret_cast<const float4*>(w0 + k);
-        const float4 wb = *reinterpret_cast<const float4*>(w1 + k);
+      for (uint32_t kc = 0; kc < K; kc += kF32KC) {
+        const uint32_t kn = K - kc < kF32KC ? K - kc : kF32KC;  // a power of two >= 128
+        f32x4 wa[WPL], wb[WPL], xv[XPT];
 #pragma unroll
-        for (int i = 0; i < 8; i++) {
-          if ((uint32_t)i < nr) {
-            const float4 a = *reinterpret_cast<const float4*>(ar[i] + k);
-            acc0[i] = fmaf(a.x, wa.x, acc0[i]);
-            acc0[i] = fmaf(a.y, wa.y, acc0[i]);
-            acc0[i] = fmaf(a.z, wa.z, acc0[i]);
-            acc0[i] = fmaf(a.w, wa.w, acc0[i]);
-            acc1[i] = fmaf(a.x, wb.x, acc1[i]);
-            acc1[i] = fmaf(a.y, wb.y, acc1[i]);
-            acc1[i] = fmaf(a.z, wb.z, acc1[i]);
-            acc1[i] = fmaf(a.w, wb.w, acc1[i]);
+        for (int j = 0; j < WPL; j++) {
+          const uint32_t k = 4 * lane + 256 * j;
+          if (k < kn) {
+            wa[j] = *(g_f32x4*)(uintptr_t)(w0 + kc + k);
+            wb[j] = *(g_f32x4*)(uintptr_t)(w1 + kc + k);
           }
         }
+        // rows r0 .. r0 + nr - 1, columns kc .. kc + kn - 1, as float4 q of row i
+        const uint32_t q4 = kn / 4;
+#pragma unroll
+        for (int j = 0; j < XPT; j++) {
+          const uint32_t idx = t + 256 * j, i = idx / q4, q = idx % q4;
+          if (i < nr) xv[j] = *(g_f32x4*)(uintptr_t)(reinterpret_cast<const float*>(a_row(la, gr.row0 + r0 + i, 4)) +
+                                                    kc + 4 * q);
+        }
+#pragma unroll
+        for (int j = 0; j < XPT; j++) {
+          const uint32_t idx = t + 256 * j, i = idx / q4, q = idx % q4;
+          if (i < nr) *reinterpret_cast<f32x4*>(&xs[i][4 * q]) = xv[j];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < WPL; j++) {
+          const uint32_t k = 4 * lane + 256 * j;
+          if (k < kn) {
+#pragma unroll
+            for (int i = 0; i < 8; i++) {
+              if ((uint32_t)i < nr) {
+                const f32x4 a = *reinterpret_cast<const f32x4*>(&xs[i][k]);
+                acc0[i] = fmaf(a.x, wa[j].x, acc0[i]);
+                acc0[i] = fmaf(a.y, wa[j].y, acc0[i]);
+                acc0[i] = fmaf(a.z, wa[j].z, acc0[i]);
+                acc0[i] = fmaf(a.w, wa[j].w, acc0[i]);
+                acc1[i] = fmaf(a.x, wb[j].x, acc1[i]);
+                acc1[i] = fmaf(a.y, wb[j].y, acc1[i]);
+                acc1[i] = fmaf(a.z, wb[j].z, acc1[i]);
+                acc1[i] = fmaf(a.w, wb[j].w, acc1[i]);
+              }
+            }
+          }
+        }
+        __syncthreads();  // the next chunk or row block restages xs
       }
 #pragma unroll
       for (int i = 0; i < 8; i++) {
