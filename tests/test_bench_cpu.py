@@ -22,3 +22,16 @@ def test_workload_cpu_baseline_shape():
     assert cb["kind"] == "oracle" and cb["unit"] == "invocations/s"
     assert cb["value"] > 0 and cb["cores"] >= 1 and "16 invocations" in cb["sample"]
     assert bench.cpu_baseline_workload("serving") is None
+
+
+def test_traffic_record_matches_the_gemm_sources():
+    """The committed HBM-traffic record of the headline GEMM layer is tied to
+    a digest of the GEMM sources; a change to them without re-taking the
+    counters would make bench.py report traffic as unknown."""
+    import bench
+    with open(bench.TRAFFIC_RECORD) as fh:
+        recs = [l for l in fh.read().splitlines() if l.startswith("traffic-record: ")]
+    assert recs, "no traffic record"
+    import json
+    digests = {json.loads(l[len("traffic-record: "):])["sources"] for l in recs}
+    assert bench.gemm_sources_digest() in digests
