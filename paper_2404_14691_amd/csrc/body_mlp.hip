@@ -713,7 +713,7 @@ extern "C" __global__ __launch_bounds__(256) void mlp_f32_layer(const GemmHdr* _
                                                                 LayerArgs la) {
   __shared__ __attribute__((aligned(16))) float xs[8][kF32KC];
   constexpr int WPL = kF32KC / 256;                     // float4 per lane per weight row per chunk
-  constexpr int XPT = 8 * kF32KC / 4 / 256;             // float4 of staged rows per thread per chunk
+  constexpr int XPR = kF32KC / 4 / 256;                 // float4 per thread per staged row per chunk
   const uint32_t t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const uint32_t K = la.K;
   const bool relu = la.flags & kRelu;
@@ -726,33 +726,46 @@ extern "C" __global__ __launch_bounds__(256) void mlp_f32_layer(const GemmHdr* _
     const float* w1 = reinterpret_cast<const float*>(wtab[off1 >> kBlockShift] + (off1 & (kBlock - 1)));
     for (uint32_t r0 = 0; r0 < gr.m; r0 += 8) {
       const uint32_t nr = gr.m - r0 < 8 ? gr.m - r0 : 8;
+      // the rows' addresses once per row block; loads are not branched
+      // around but clamped into valid rows and columns (a value loaded for
+      // a missing row or column is not used), so they all go out together
+      const float* ar[8];
+      if (la.a_tab) {
+#pragma unroll
+        for (int i = 0; i < 8; i++) ar[i] = reinterpret_cast<const float*>(la.a_tab[gr.row0 + r0 + ((uint32_t)i < nr ? i : 0)]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; i++)
+          ar[i] = reinterpret_cast<const float*>(la.a_base + (uint64_t)(gr.row0 + r0 + ((uint32_t)i < nr ? i : 0)) * K * 4);
+      }
       float acc0[8], acc1[8];
 #pragma unroll
       for (int i = 0; i < 8; i++) acc0[i] = acc1[i] = 0.f;
       for (uint32_t kc = 0; kc < K; kc += kF32KC) {
         const uint32_t kn = K - kc < kF32KC ? K - kc : kF32KC;  // a power of two >= 128
-        f32x4 wa[WPL], wb[WPL], xv[XPT];
+        f32x4 wa[WPL], wb[WPL], xv[8][XPR];
 #pragma unroll
         for (int j = 0; j < WPL; j++) {
-          const uint32_t k = 4 * lane + 256 * j;
-          if (k < kn) {
-            wa[j] = *(g_f32x4*)(uintptr_t)(w0 + kc + k);
-            wb[j] = *(g_f32x4*)(uintptr_t)(w1 + kc + k);
-          }
+          const uint32_t k = 4 * lane + 256 * j < kn ? 4 * lane + 256 * j : kn - 4;
+          wa[j] = *(g_f32x4*)(uintptr_t)(w0 + kc + k);
+          wb[j] = *(g_f32x4*)(uintptr_t)(w1 + kc + k);
         }
-        // rows r0 .. r0 + nr - 1, columns kc .. kc + kn - 1, as float4 q of row i
+        // rows r0 .. r0 + nr - 1, columns kc .. kc + kn - 1: float4 q = t + 256 m of each row
         const uint32_t q4 = kn / 4;
 #pragma unroll
-        for (int j = 0; j < XPT; j++) {
-          const uint32_t idx = t + 256 * j, i = idx / q4, q = idx % q4;
-          if (i < nr) xv[j] = *(g_f32x4*)(uintptr_t)(reinterpret_cast<const float*>(a_row(la, gr.row0 + r0 + i, 4)) +
-                                                    kc + 4 * q);
-        }
+        for (int i = 0; i < 8; i++)
 #pragma unroll
-        for (int j = 0; j < XPT; j++) {
-          const uint32_t idx = t + 256 * j, i = idx / q4, q = idx % q4;
-          if (i < nr) *reinterpret_cast<f32x4*>(&xs[i][4 * q]) = xv[j];
-        }
+          for (int m = 0; m < XPR; m++) {
+            const uint32_t q = t + 256 * m < q4 ? t + 256 * m : q4 - 1;
+            xv[i][m] = *(g_f32x4*)(uintptr_t)(ar[i] + kc + 4 * q);
+          }
+#pragma unroll
+        for (int i = 0; i < 8; i++)
+#pragma unroll
+          for (int m = 0; m < XPR; m++) {
+            const uint32_t q = t + 256 * m;
+            if ((uint32_t)i < nr && q < q4) *reinterpret_cast<f32x4*>(&xs[i][4 * q]) = xv[i][m];
+          }
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < WPL; j++) {
