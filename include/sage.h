@@ -348,6 +348,12 @@ sage_status sage_serve_reset_stats(sage_ctx* ctx);
 sage_status sage_timing_enable(sage_ctx* ctx, int on);
 sage_status sage_timing_get(sage_ctx* ctx, const char* kernel, double* total_ms, uint64_t* launches);
 sage_status sage_timing_reset(sage_ctx* ctx);
+/* Restrict timing to the launches of one name (one of the names above;
+ * NULL or "" times every kernel again).  Each timed interval costs two event
+ * records on its stream, so a caller measuring one kernel's device time
+ * can leave the others untimed.  The name is copied; EINVAL for an unknown
+ * name. */
+sage_status sage_timing_only(sage_ctx* ctx, const char* kernel);
 /* Describe the last MLP body launch of this context as text, e.g.
  * "ggemm6p_bf16_256x256:256+ggemm3t_bf16_32x32:384" (kernel:tiles per layer;
  * a second term is the thin-tile launch over split-off ragged row tiles).

@@ -75,6 +75,7 @@ class DevCache {
 class KernelTimer {
  public:
   bool on = false;
+  std::string only;  // when not empty: the one name timed
   // Have n event pairs ready (created outside the timed work; a start then
   // costs two event records and no allocation).
   void reserve(size_t n);

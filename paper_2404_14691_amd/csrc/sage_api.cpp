@@ -699,6 +699,18 @@ sage_status sage_timing_get(sage_ctx* p, const char* kernel, double* total_ms, u
   });
 }
 
+sage_status sage_timing_only(sage_ctx* p, const char* kernel) {
+  return guard([&] {
+    Ctx& c = ctx_of(p);
+    std::lock_guard<std::recursive_mutex> lk(c.mu);
+    const std::string k = kernel ? kernel : "";
+    static const char* const kNames[] = {"fp64k", "blkcopy", "ggemm_bf16", "mlp_f32", "stencil7"};
+    if (!k.empty() && std::find(std::begin(kNames), std::end(kNames), k) == std::end(kNames))
+      fail(SAGE_EINVAL, "unknown kernel name %s", k.c_str());
+    c.timer.only = k;
+  });
+}
+
 sage_status sage_timing_reset(sage_ctx* p) {
   return guard([&] {
     Ctx& c = ctx_of(p);

@@ -116,7 +116,7 @@ void KernelTimer::reserve(size_t n) {
 }
 
 int KernelTimer::start(const char* name, hipStream_t s, uint32_t launches) {
-  if (!on) return -1;
+  if (!on || (!only.empty() && only != name)) return -1;
   if (free_.empty()) collect();  // pairs whose interval completed come back
   int tok;
   if (!free_.empty()) {

@@ -129,6 +129,7 @@ _sigs = {
     "sage_timing_enable": (C.c_int, [_P, C.c_int]),
     "sage_timing_get": (C.c_int, [_P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]),
     "sage_timing_reset": (C.c_int, [_P]),
+    "sage_timing_only": (C.c_int, [_P, C.c_char_p]),
     "sage_last_launch": (C.c_int, [_P, C.c_char_p, C.c_size_t]),
     "sage_tick": (C.c_int, [_P]),
     "sage_selftest_segments": (C.c_int, [C.POINTER(C.c_uint32), C.c_size_t, C.c_uint32, C.c_uint64,
@@ -369,6 +370,11 @@ def sage_blkcopy(ctx: int, dev_ops: int, n_ops: int, dev_result: int, stream: in
 # ------------------------------------------------------------------ timing
 def sage_timing_enable(ctx: int, on: bool = True) -> None:
     _check(_lib.sage_timing_enable(ctx, 1 if on else 0), "sage_timing_enable")
+
+
+def sage_timing_only(ctx: int, kernel: str | None = None) -> None:
+    """Time only the launches of `kernel` (None: every kernel again)."""
+    _check(_lib.sage_timing_only(ctx, kernel.encode() if kernel else None), "sage_timing_only")
 
 
 def sage_timing_get(ctx: int, kernel: str):

@@ -142,3 +142,29 @@ def test_batch_calls_take_arrays(sage_ctx_factory, torch_cuda):
         results.append(y.cpu().numpy())
     assert np.array_equal(results[0], results[1]) and np.abs(results[0]).sum() > 0
     assert S.sage_get_stats(ctx)["live_setups"] == 0
+
+
+def test_timing_only_one_kernel(sage_ctx_factory, torch_cuda):
+    """With timing restricted to the GEMM, registrations record no fingerprint
+    or copy intervals and invocations still record theirs; the restriction
+    lifts with None, and an unknown name is rejected."""
+    from paper_2404_14691_amd import sage as S
+    layers, width = 2, 256
+    w = synth.shared_mlp_bf16_functions(n_fns=1, layers=layers, width=width, share_frac=0.0, seed=41)
+    x = synth.bf16_inputs(5, width, 41, 0)
+    y = np.zeros((5, width), dtype=np.float32)
+    desc = S.mlp_desc(S.SAGE_MLP_BF16, layers, width)
+    ctx = sage_ctx_factory()
+    assert _status(S.sage_timing_only, ctx, "no_such_kernel") == S.SAGE_EINVAL
+    S.sage_timing_enable(ctx, True)
+    for only, fp_timed in (("ggemm_bf16", False), (None, True)):
+        S.sage_timing_reset(ctx)
+        S.sage_timing_only(ctx, only)
+        fn = S.fn_register(ctx, desc, [S.make_blob(w.blobs[0])])
+        inv = S.fn_setup(ctx, fn, 5)
+        S.fn_invoke(ctx, inv, x, y)
+        S.fn_release(ctx, inv)
+        S.fn_unregister(ctx, fn)
+        assert (S.sage_timing_get(ctx, "fp64k")[1] > 0) == fp_timed, only
+        assert S.sage_timing_get(ctx, "ggemm_bf16")[1] >= layers, only
+    S.sage_timing_enable(ctx, False)
