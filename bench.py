@@ -40,8 +40,9 @@ BF16_PEAK_TFLOPS = 2500.0
 # runs summarised in this file; it is reported only while the GEMM sources
 # and the launch plan are the ones the counters were taken on.
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "ggemm_bf16_sharing_counters.md")
-GEMM_SOURCES = ("paper_2404_14691_amd/csrc/body_mlp.hip", "paper_2404_14691_amd/csrc/exec.cpp",
-                "paper_2404_14691_amd/csrc/layout.h")
+# The record is tied to the GEMM kernels' own sources (the launch plan, which
+# the host planner picks, is recorded beside it).
+GEMM_SOURCES = ("paper_2404_14691_amd/csrc/body_mlp.hip", "paper_2404_14691_amd/csrc/layout.h")
 
 
 _T0 = time.time()
@@ -134,9 +135,9 @@ def plain_step(S, ctx, wl):
     seen = set()
     for req in wl.requests:
         f = req[0]
-        t0 = time.perf_counter()
-        inv = S.fn_setup(ctx, fns[f], req[1])
-        dt = (time.perf_counter() - t0) * 1e3
+        # the library's own per-request setup clock, as on the shared path
+        invs, ms = S.fn_setup_batch(ctx, [fns[f]], [req[1]], timed=True)
+        inv, dt = invs[0], ms[0]
         if f not in seen:
             dt += reg_ms[f]
             seen.add(f)
@@ -274,6 +275,182 @@ def host_link(S, torch, wl):
         finally:
             S.sage_close(ctx)
     return out
+
+
+def host_sourced(S, torch, wl, shared_steps=10, naive_requests=64):
+    """The metric with the host link in it: the four functions' sources in
+    host memory (pinned, from sage_host_alloc, and pageable), inputs read from
+    and outputs written to host memory.
+
+    shared+batched step: fn_register x4 from the host sources (pipelined
+      H2D + fingerprint + dedup), fn_setup x256 (one call), one grouped
+      fn_invoke_batch, fn_release x256, fn_unregister x4;
+    plain step: fn_register x4 (code only), then per request fn_setup (a
+      private copy of its function's 256 MiB through the same pipelined H2D),
+      fn_invoke (one launch sequence), fn_release;
+    naive plain: plain with one staging slot on one stream and the code
+      branch serialised (no pipelining), on a seeded subsample of requests.
+
+    Setup latency of a request is the library's own clock for its fn_setup
+    (fn_setup_batch with per-request times) on both paths, plus its
+    function's fn_register wall time for the first request of each function.
+    Throughput_perf follows the paper's eq. (1): the achieved invocation rate
+    over the rate if each invocation cost only its computation time T_comp,
+    here the mean device time of one invocation's body run alone (the plain
+    path's launch sequences, HIP events on their stream)."""
+    desc = S.mlp_desc(S.SAGE_MLP_BF16, wl.layers, wl.width)
+    n_req = len(wl.requests)
+    ro_total = sum(b.nbytes for b in wl.host_blobs)
+    y = np.zeros((wl.rows, wl.width), dtype=np.float32)
+    ins = [wl.x_host[r:r + b] for _, b, r in wl.requests]
+    outs = [y[r:r + b] for _, b, r in wl.requests]
+    io_bytes = wl.x_host.nbytes + y.nbytes
+    fidx = wl.fidx
+    batches = wl.batch_arr
+    res = {"sources": "host memory; inputs from and outputs to host memory",
+           "expected_h2d_ro_bytes_per_step": {"plain": int(sum(wl.host_blobs[f].nbytes for f, _, _ in wl.requests)),
+                                              "shared": int(ro_total)}}
+
+    def sources(ctx, pinned):
+        if not pinned:
+            return list(wl.host_blobs), []
+        srcs = []
+        for b in wl.host_blobs:
+            a = S.pinned_array(ctx, b.shape, b.dtype)
+            a[:] = b
+            srcs.append(a)
+        return srcs, srcs
+
+    def register(ctx, srcs):
+        fns, reg_ms = [], []
+        for a in srcs:
+            t0 = time.perf_counter()
+            fns.append(S.fn_register(ctx, desc, [S.make_blob(a)]))
+            reg_ms.append((time.perf_counter() - t0) * 1e3)
+        return fns, reg_ms
+
+    def shared_step(ctx, srcs, want_pool=False):
+        fns, reg_ms = register(ctx, srcs)
+        invs, own = S.fn_setup_batch(ctx, np.asarray(fns, dtype=np.uint64)[fidx], batches, timed=True)
+        for f, i in wl.first_of_fn.items():
+            own[i] += reg_ms[f]
+        pool = S.sage_get_stats(ctx) if want_pool else None
+        S.fn_invoke_batch(ctx, list(invs), ins, outs, 0)
+        S.fn_release_batch(ctx, invs)
+        for f in fns:
+            S.fn_unregister(ctx, f)
+        return list(own), pool
+
+    def plain_step(ctx, srcs, reqs):
+        fns, reg_ms = register(ctx, srcs)
+        setup, seen = [], set()
+        for i in reqs:
+            f, b, _ = wl.requests[i]
+            invs, ms = S.fn_setup_batch(ctx, [fns[f]], [b], timed=True)
+            dt = ms[0]
+            if f not in seen:
+                dt += reg_ms[f]
+                seen.add(f)
+            setup.append(dt)
+            S.fn_invoke(ctx, invs[0], ins[i], outs[i], 0)
+            S.fn_release(ctx, invs[0])
+        for f in fns:
+            S.fn_unregister(ctx, f)
+        return setup
+
+    def pcts(v):
+        return {"p50": round(percentile(v, 50), 4), "p99": round(percentile(v, 99), 3)}
+
+    t_comp_ms = None
+    for kind in ("pinned", "pageable"):
+        pinned = kind == "pinned"
+        leg = {}
+        # ---- shared + batched
+        cfg = S.sage_config_default()
+        cfg.pool_budget_bytes = 8 << 30
+        ctx = S.sage_open(0, cfg)
+        try:
+            srcs, owned = sources(ctx, pinned)
+            pool = shared_step(ctx, srcs, want_pool=True)[1]
+            shared_step(ctx, srcs)
+            st0 = S.sage_get_stats(ctx)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            setup = []
+            for _ in range(shared_steps):
+                setup += shared_step(ctx, srcs)[0]
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            st1 = S.sage_get_stats(ctx)
+            rate = n_req * shared_steps / el
+            leg["shared_batched"] = {
+                "invocations_per_s": round(rate, 2), "ms_per_step": round(el / shared_steps * 1e3, 3),
+                "steps": shared_steps, "setup_ms": pcts(setup),
+                "h2d_ro_bytes_per_step": int((st1["h2d_bytes"] - st0["h2d_bytes"]) // shared_steps),
+                "h2d_io_bytes_per_step": int(io_bytes),
+                "ro_GBps_per_step": round(ro_total * shared_steps / el / 1e9, 2),
+                "resident_bytes": int(pool["resident_bytes"]), "unique_bytes": int(pool["unique_bytes"]),
+                "live_invocations": int(pool["live_setups"])}
+            for a in owned:
+                S.sage_host_free(ctx, a.ctypes.data)
+        finally:
+            S.sage_close(ctx)
+        log(f"host-sourced {kind}: shared {leg['shared_batched']}")
+        # ---- plain: a private copy per invocation through the pipelined H2D
+        for name, over, reqs in (("plain", {}, list(range(n_req))),
+                                 ("naive_plain", {"ring_slots": 1, "streams": 1, "serial_setup": 1},
+                                  sorted(np.random.default_rng(7).choice(n_req, naive_requests, replace=False)))):
+            if name == "naive_plain" and pinned:
+                continue  # pinned sources are copied by DMA without the ring: the naive form is the pageable one
+            cfg = S.sage_config_default()
+            cfg.share = 0
+            cfg.pool_budget_bytes = 1 << 20
+            for k, v in over.items():
+                setattr(cfg, k, v)
+            ctx = S.sage_open(0, cfg)
+            try:
+                srcs, owned = sources(ctx, pinned)
+                plain_step(ctx, srcs, reqs[:8])  # warm: code object, private buffers, staging
+                if t_comp_ms is None:
+                    S.sage_timing_reset(ctx)
+                    S.sage_timing_only(ctx, "ggemm_bf16")
+                    S.sage_timing_enable(ctx, True)
+                st0 = S.sage_get_stats(ctx)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                setup = plain_step(ctx, srcs, reqs)
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t0
+                st1 = S.sage_get_stats(ctx)
+                if t_comp_ms is None:
+                    S.sage_timing_enable(ctx, False)
+                    g_ms, g_n = S.sage_timing_get(ctx, "ggemm_bf16")
+                    t_comp_ms = g_ms / (g_n / wl.layers)
+                    res["t_comp_ms"] = {"value": round(t_comp_ms, 5), "invocations": int(g_n // wl.layers),
+                                        "what": "mean device time of one invocation's 8 layers run alone"}
+                rate = len(reqs) / el
+                leg[name] = {"invocations_per_s": round(rate, 2), "ms_per_step": round(el * 1e3, 3),
+                             "requests": len(reqs), "setup_ms": pcts(setup),
+                             "h2d_ro_bytes": int(st1["h2d_bytes"] - st0["h2d_bytes"]),
+                             "ro_GBps": round((st1["h2d_bytes"] - st0["h2d_bytes"]) / el / 1e9, 2)}
+                if name == "naive_plain":
+                    leg[name]["sample"] = f"{len(reqs)} of the {n_req} requests (seeded), in order"
+                for a in owned:
+                    S.sage_host_free(ctx, a.ctypes.data)
+            finally:
+                S.sage_close(ctx)
+            log(f"host-sourced {kind}: {name} {leg[name]}")
+        sb, pl = leg["shared_batched"], leg["plain"]
+        sb["plain_footprint_bytes_same_concurrency"] = int(sum(wl.host_blobs[f].nbytes for f, _, _ in wl.requests))
+        sb["density_vs_plain"] = round(sb["plain_footprint_bytes_same_concurrency"] / max(sb["resident_bytes"], 1), 2)
+        leg["speedup_vs_plain"] = round(sb["invocations_per_s"] / pl["invocations_per_s"], 2)
+        leg["setup_p50_vs_plain"] = round(pl["setup_ms"]["p50"] / max(sb["setup_ms"]["p50"], 1e-9), 2)
+        res[kind] = leg
+    for kind in ("pinned", "pageable"):
+        for name in ("shared_batched", "plain", "naive_plain"):
+            if name in res[kind]:
+                res[kind][name]["throughput_perf"] = round(res[kind][name]["invocations_per_s"] * t_comp_ms * 1e-3, 4)
+    return res
 
 
 def _host_cpu():
@@ -549,6 +726,8 @@ def main():
         "host_ms_per_step": host,
     }
     if not args.no_host_link and not args.only_shared:
+        log("host-sourced shared vs plain ...")
+        line["host_sourced"] = host_sourced(S, torch, wl)
         log("host-link registration runs ...")
         line["host_link_not_headline"] = host_link(S, torch, wl)
         log(f"host link: {line['host_link_not_headline']}")

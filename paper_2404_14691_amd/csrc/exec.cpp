@@ -368,7 +368,9 @@ int launch_stencil_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, in
   bool fed = false;
   for (const Call& cl : calls) fed = fed || reload_feeds(c, *cl.inv->fn);
   if (fed) HIPX(hipStreamWaitEvent(s, c.reload_done, 0));
-  ensure(&F.d_meta, &F.h_meta, &F.meta_cap, (size_t)std::max<uint32_t>(S, 1) * 2 * nf * 8);
+  // the flight's captured MLP graphs hold the meta buffer's address and row
+  // capacity: a move makes them stale
+  if (ensure(&F.d_meta, &F.h_meta, &F.meta_cap, (size_t)std::max<uint32_t>(S, 1) * 2 * nf * 8)) drop_graphs(F);
   uint64_t* tab = reinterpret_cast<uint64_t*>(F.h_meta);
   F.deliver.clear();
   std::vector<std::pair<const uint8_t*, uint8_t*>> io_fields;  // (input, final output) per field

@@ -350,7 +350,11 @@ class Worker {
 // ------------------------------------------------------------------ context
 constexpr size_t kReloadStageBlocks = 4096;  // reload staging: 256 MiB, cycled by region
 constexpr size_t kTimerPairs = 2048;          // event pairs made ready when kernel timing is switched on
-constexpr uint64_t kDevChunkBytes = 64ull << 20;  // registration chunk of a device-resident source
+// Registration chunk of a device-resident source (SAGE_DEV_CHUNK_BYTES
+// overrides it, e.g. for tests that span several chunks).  One launch
+// fingerprints a whole chunk: large chunks keep the kernel streaming at HBM
+// rate instead of paying a launch and a result copy per 64 MiB.
+constexpr uint64_t kDevChunkBytes = 1ull << 30;
 
 struct Ctx {
   int device = 0;
@@ -411,11 +415,14 @@ struct Ctx {
   double t_reload = 0, t_release = 0, t_unregister = 0;
   uint64_t module_loads = 0;                 // under module_mu
   double t_module = 0;                       // under module_mu
-  Serve* serve = nullptr;                    // running serving loop, if any
+  // running serving loop, if any; callers outside the loop thread take a
+  // reference under `mu` and keep the state alive while they wait on it
+  std::shared_ptr<Serve> serve;
   Worker worker;                             // code branch of fn_register
   std::string force_tile;                    // SAGE_TILE: fixed GEMM tile shape (tests)
   std::string last_launch;                   // kernels and tiles of the last MLP launch
   bool test_fp_const = false;                // force every fingerprint equal (collision test)
+  uint64_t dev_chunk = kDevChunkBytes;       // registration chunk of device-resident sources
   uint64_t test_fp_value = 0;
 
   bool is_pinned(const void* p, size_t n) const;

@@ -230,7 +230,7 @@ void register_shared(Ctx& c, Fn& f) {
   for (uint32_t b = 0; b < f.srcs.size(); b++) {
     // device sources need no staging: they are fingerprinted in large chunks
     // in place, and their VERIFY / COPY work waits for the whole registration
-    const uint64_t step = f.srcs[b].dev ? std::max<uint64_t>(std::min<uint64_t>(f.srcs[b].n, kDevChunkBytes), 1)
+    const uint64_t step = f.srcs[b].dev ? std::max<uint64_t>(std::min<uint64_t>(f.srcs[b].n, c.dev_chunk), 1)
                                         : R.chunk;
     for (uint64_t off = 0; off < f.srcs[b].n; off += step) {
       Chunk ch{};

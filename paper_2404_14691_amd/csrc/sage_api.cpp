@@ -258,6 +258,11 @@ sage_status sage_open(int device, const sage_config* cfg, sage_ctx** out) {
     tune_load(c);
     c.worker.start(device);
     if (const char* e = std::getenv("SAGE_TILE")) c.force_tile = e;
+    if (const char* e = std::getenv("SAGE_DEV_CHUNK_BYTES")) {
+      const uint64_t v = std::strtoull(e, nullptr, 0);
+      if (v < kBlock || v % kBlock) fail(SAGE_EINVAL, "SAGE_DEV_CHUNK_BYTES must be a positive multiple of 65536");
+      c.dev_chunk = v;
+    }
     if (const char* e = std::getenv("SAGE_TEST_FP_CONST")) {
       c.test_fp_const = true;
       c.test_fp_value = std::strtoull(e, nullptr, 0);

@@ -40,6 +40,7 @@ struct Serve {
   Clock::time_point t_first, t_last;
   bool any = false;
   uint32_t max_rows = 8192;
+  std::once_flag joined;  // the loop thread is joined once, whoever stops it
 };
 
 static double ms_between(Clock::time_point a, Clock::time_point b) {
@@ -134,7 +135,12 @@ static void serve_loop(Ctx& c, Serve& S) {
         for (auto it = pending.begin(); it != pending.end();) {
           Req& r = **it;
           bool drop = false;
-          if (!key || (same_shape(c, *key, r) && rows + r.batch <= S.max_rows)) {
+          if (!c.fns.count(r.fn)) {
+            // unregistered while it was queued: it can never be admitted
+            r.st = SAGE_ENOTFOUND;
+            r.err = "function " + std::to_string(r.fn) + " was unregistered while the request was queued";
+            drop = true;
+          } else if (!key || (same_shape(c, *key, r) && rows + r.batch <= S.max_rows)) {
             const sage_status st = guard([&] { r.inv = setup_internal(c, r.fn, r.batch); });
             if (st == SAGE_OK) {
               r.t_setup = Clock::now();
@@ -191,22 +197,34 @@ static void serve_loop(Ctx& c, Serve& S) {
   }
 }
 
-static Serve& serve_of(Ctx& c) {
+// A reference to the running loop's state, taken under the context mutex;
+// it stays valid while the caller waits on it, even across a concurrent stop.
+static std::shared_ptr<Serve> serve_of(Ctx& c) {
+  std::lock_guard<std::recursive_mutex> lk(c.mu);
   if (!c.serve) fail(SAGE_ESTATE, "serving loop not started");
-  return *c.serve;
+  return c.serve;
 }
 
+// Stop the loop: new submissions are refused, queued and in-flight requests
+// drain, then the thread is joined.  The context keeps the loop's state until
+// the join, so fn_invoke stays refused while the loop still owns the flights.
 void serve_destroy(Ctx& c) {
-  if (!c.serve) return;
-  Serve& S = *c.serve;
+  std::shared_ptr<Serve> sp;
   {
-    std::lock_guard<std::mutex> lk(S.qmu);
-    S.stop = true;
+    std::lock_guard<std::recursive_mutex> lk(c.mu);
+    sp = c.serve;
   }
-  S.qcv.notify_all();
-  if (S.th.joinable()) S.th.join();
-  delete c.serve;
-  c.serve = nullptr;
+  if (!sp) return;
+  {
+    std::lock_guard<std::mutex> lk(sp->qmu);
+    sp->stop = true;
+  }
+  sp->qcv.notify_all();
+  std::call_once(sp->joined, [&] {
+    if (sp->th.joinable()) sp->th.join();
+  });
+  std::lock_guard<std::recursive_mutex> lk(c.mu);
+  if (c.serve == sp) c.serve.reset();
 }
 
 static double pct(std::vector<double> v, double q) {
@@ -228,10 +246,11 @@ sage_status sage_serve_start(sage_ctx* p, uint32_t max_rows) {
     Ctx& c = ctx_ref(p);
     std::lock_guard<std::recursive_mutex> lk(c.mu);
     if (c.serve) fail(SAGE_ESTATE, "serving loop already running");
-    auto* S = new Serve();
+    auto sp = std::make_shared<Serve>();
+    Serve* S = sp.get();
     if (max_rows) S->max_rows = max_rows;
-    c.serve = S;
     S->running = true;
+    c.serve = sp;
     S->th = std::thread([&c, S] { serve_loop(c, *S); });
   });
 }
@@ -239,7 +258,7 @@ sage_status sage_serve_start(sage_ctx* p, uint32_t max_rows) {
 sage_status sage_serve_stop(sage_ctx* p) {
   return guard([&] {
     Ctx& c = ctx_ref(p);
-    if (!c.serve) fail(SAGE_ESTATE, "serving loop not started");
+    (void)serve_of(c);  // ESTATE when not running
     serve_destroy(c);
   });
 }
@@ -251,10 +270,10 @@ sage_status sage_submit(sage_ctx* p, sage_fn fn, uint32_t batch, const void* in,
     if (!req_id || !in || !out) fail(SAGE_EINVAL, "null argument");
     auto r = std::make_shared<Req>();
     r->t_arr = Clock::now();
+    std::shared_ptr<Serve> sp;
     {
       std::lock_guard<std::recursive_mutex> lk(c.mu);
-      Serve& S = serve_of(c);
-      (void)S;
+      sp = serve_of(c);
       const Fn& f = find_fn(c, fn);
       if (batch < 1 || in_bytes != in_bytes_for(f.d, batch) || out_bytes != out_bytes_for(f.d, batch))
         fail(SAGE_EINVAL, "request sizes do not match the function");
@@ -270,9 +289,10 @@ sage_status sage_submit(sage_ctx* p, sage_fn fn, uint32_t batch, const void* in,
     r->out = out;
     r->out_bytes = out_bytes;
     r->io = io_flags;
-    Serve& S = *c.serve;
+    Serve& S = *sp;
     {
       std::lock_guard<std::mutex> lk(S.qmu);
+      if (S.stop) fail(SAGE_ESTATE, "serving loop is stopping");
       if (!S.any) {
         S.any = true;
         S.t_first = r->t_arr;
@@ -289,7 +309,8 @@ sage_status sage_wait(sage_ctx* p, uint64_t req_id, double timeout_ms, sage_req_
   Ctx* cp = &ctx_ref(p);
   std::shared_ptr<Req> r;
   sage_status st = guard([&] {
-    Serve& S = serve_of(*cp);
+    const std::shared_ptr<Serve> sp = serve_of(*cp);
+    Serve& S = *sp;
     std::unique_lock<std::mutex> lk(S.qmu);
     auto it = S.reqs.find(req_id);
     if (it == S.reqs.end()) fail(SAGE_ENOTFOUND, "unknown request %llu", (unsigned long long)req_id);
@@ -316,7 +337,8 @@ sage_status sage_serve_stats(sage_ctx* p, sage_serve_report* out) {
   return guard([&] {
     Ctx& c = ctx_ref(p);
     if (!out) fail(SAGE_EINVAL, "null output");
-    Serve& S = serve_of(c);
+    const std::shared_ptr<Serve> sp = serve_of(c);
+    Serve& S = *sp;
     std::lock_guard<std::mutex> lk(S.qmu);
     std::memset(out, 0, sizeof *out);
     out->completed = S.completed;
@@ -336,7 +358,8 @@ sage_status sage_serve_stats(sage_ctx* p, sage_serve_report* out) {
 sage_status sage_serve_reset_stats(sage_ctx* p) {
   return guard([&] {
     Ctx& c = ctx_ref(p);
-    Serve& S = serve_of(c);
+    const std::shared_ptr<Serve> sp = serve_of(c);
+    Serve& S = *sp;
     std::lock_guard<std::mutex> lk(S.qmu);
     S.setup_ms.clear();
     S.e2e_ms.clear();

@@ -168,3 +168,32 @@ def test_timing_only_one_kernel(sage_ctx_factory, torch_cuda):
         assert (S.sage_timing_get(ctx, "fp64k")[1] > 0) == fp_timed, only
         assert S.sage_timing_get(ctx, "ggemm_bf16")[1] >= layers, only
     S.sage_timing_enable(ctx, False)
+
+
+def test_mlp_graph_after_stencil_grows_the_flight_metadata(sage_ctx_factory, torch_cuda):
+    """With one flight, an MLP group (its graph captured), then a sweep group
+    whose per-sweep field tables outgrow the flight's metadata buffer, then
+    the MLP group again: the second MLP run re-captures its graph on the new
+    buffer and returns the first run's bits."""
+    from paper_2404_14691_amd import sage as S
+    ctx = sage_ctx_factory(inflight_groups=1)
+    width, layers, b = 256, 3, 6
+    w = synth.shared_mlp_bf16_functions(n_fns=1, layers=layers, width=width, share_frac=0.0, seed=33)
+    fn = S.fn_register(ctx, S.mlp_desc(S.SAGE_MLP_BF16, layers, width), [S.make_blob(w.blobs[0])])
+    x = synth.bf16_inputs(b, width, 33, 0)
+    y0 = np.zeros((b, width), dtype=np.float32)
+    inv = S.fn_setup(ctx, fn, b)
+    S.fn_invoke(ctx, inv, x, y0)
+    # 8 fields x 9000 sweeps x 2 addresses x 8 bytes = 1.15 MB of field tables
+    shape = (4, 4, 8)
+    relax = S.fn_register(ctx, S.relax_desc(shape[2], shape[1], shape[0], 9000, 0.5), [])
+    rinv = S.fn_setup(ctx, relax, 8)
+    u0 = np.stack([synth.stencil_field(0, j, seed=33, shape=shape) for j in range(8)])
+    u = np.zeros_like(u0)
+    S.fn_invoke(ctx, rinv, u0, u)
+    assert np.isfinite(u).all()
+    y1 = np.full((b, width), np.nan, dtype=np.float32)
+    S.fn_invoke(ctx, inv, x, y1)
+    assert np.array_equal(y0, y1)
+    S.fn_release(ctx, inv)
+    S.fn_release(ctx, rinv)

@@ -154,8 +154,10 @@ def test_register_rejects_bad_layouts(sage_ctx_factory, torch_cuda):
     assert e.value.status == S.SAGE_ENOTFOUND
 
 
-def test_device_source_across_chunks(sage_ctx_factory, torch_cuda):
-    """A 160 MiB device source is fingerprinted in three chunks; blocks equal
+@pytest.mark.parametrize("chunk", [64 << 20, None])
+def test_device_source_across_chunks(sage_ctx_factory, torch_cuda, monkeypatch, chunk):
+    """A 160 MiB device source is fingerprinted in three 64 MiB chunks (or in
+    one, the default chunk size); blocks equal
     to blocks of earlier chunks (still being copied from the source) and to
     another function's blocks join their classes; fingerprints, partition,
     accounting and sampled slot bytes match the oracle."""
@@ -171,6 +173,8 @@ def test_device_source_across_chunks(sage_ctx_factory, torch_cuda):
     blobs[0][30 * per:31 * per] = 0
     blobs[0][2300 * per:2301 * per] = 0
     blobs[1][700 * per:701 * per] = blobs[0][2200 * per:2201 * per]    # the second function joins a late class
+    if chunk:
+        monkeypatch.setenv("SAGE_DEV_CHUNK_BYTES", str(chunk))
     ctx = sage_ctx_factory(pool_budget_bytes=1 << 30)
     dev = [torch.from_numpy(b.view(np.uint8)).cuda() for b in blobs]
     torch.cuda.synchronize()

@@ -79,3 +79,47 @@ def test_serving_rejects_inadmissible_request(sage_ctx_factory, torch_cuda):
     assert e.value.status == S.SAGE_ENOMEM
     S.sage_serve_stop(ctx)
     S.fn_release(ctx, inv)
+
+
+def test_unregister_while_queued_fails_the_request(sage_ctx_factory, torch_cuda):
+    """A request whose function is unregistered while it waits in the queue
+    fails with ENOTFOUND; the serving loop keeps running.  A long sweep keeps
+    the device busy so the request waits (the pool is held by a live setup of
+    another function) instead of failing at once."""
+    from paper_2404_14691_amd import sage as S
+    torch = torch_cuda
+    w = synth.shared_mlp_bf16_functions(n_fns=2, layers=LAYERS, width=WIDTH, share_frac=0.0, seed=13)
+    blocks = LAYERS * WIDTH * WIDTH * 2 // 65536
+    ctx = sage_ctx_factory(pool_budget_bytes=blocks * 65536, inflight_groups=2)
+    desc = S.mlp_desc(S.SAGE_MLP_BF16, LAYERS, WIDTH)
+    f0 = S.fn_register(ctx, desc, [S.make_blob(w.blobs[0])])
+    f1 = S.fn_register(ctx, desc, [S.make_blob(w.blobs[1])])
+    hold = S.fn_setup(ctx, f1, 1)                 # f1's blocks fill the pool: f0 cannot be admitted
+    nz, ny, nx = 64, 256, 1024                    # 64 MiB field, 400 sweeps: tens of ms on the device
+    busy = S.fn_register(ctx, S.relax_desc(nx, ny, nz, 400, 0.5), [])
+    u0 = torch.zeros((nz, ny, nx), dtype=torch.float32, device="cuda")
+    u1 = torch.empty_like(u0)
+    torch.cuda.synchronize()
+    io = S.SAGE_IO_DEVICE_IN | S.SAGE_IO_DEVICE_OUT
+    S.sage_serve_start(ctx)
+    rb = S.sage_submit(ctx, busy, 1, (u0.data_ptr(), u0.numel() * 4), (u1.data_ptr(), u1.numel() * 4), io)
+    time.sleep(0.002)
+    x = synth.bf16_inputs(2, WIDTH, 13, 0)
+    y = np.zeros((2, WIDTH), dtype=np.float32)
+    r0 = S.sage_submit(ctx, f0, 2, x, y)
+    S.fn_unregister(ctx, f0)
+    with pytest.raises(S.SageError) as e:
+        S.sage_wait(ctx, r0, 30000)
+    assert e.value.status == S.SAGE_ENOTFOUND
+    assert S.sage_wait(ctx, rb, 30000)["status"] == 0
+    # the loop still serves
+    x1 = synth.bf16_inputs(3, WIDTH, 13, 1)
+    y1 = np.zeros((3, WIDTH), dtype=np.float32)
+    assert S.sage_wait(ctx, S.sage_submit(ctx, f1, 3, x1, y1), 30000)["status"] == 0
+    S.sage_serve_stop(ctx)
+    ref = OM.mlp_forward(OM.bf16_to_f64(x1), OM.bf16_to_f64(w.blobs[1]).reshape(LAYERS, WIDTH, WIDTH))
+    assert OM.normwise_error(y1, ref) <= 2e-2
+    with pytest.raises(S.SageError) as e:
+        S.sage_submit(ctx, f1, 3, x1, y1)
+    assert e.value.status == S.SAGE_ESTATE
+    S.fn_release(ctx, hold)
