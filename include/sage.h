@@ -175,18 +175,29 @@ typedef struct {
 } sage_stats;
 
 /* ----------------------------------------------------------------- context */
+/* Defaults of every sage_config field (no passage in the paper: the ring,
+ * stream and pool parameters are this library's own). */
 void sage_config_default(sage_config* cfg);
 
 /* Open the library on `device` (HIP ordinal).  Loads the runtime kernels and
  * allocates the staging ring; roughly SageInit() of the paper's programming
  * model (section "Programming Model").  cfg may be NULL for defaults. */
 sage_status sage_open(int device, const sage_config* cfg, sage_ctx** out);
-/* Wait for all work, free every resource.  Live handles become invalid. */
+/* Wait for all work, free every resource.  Live handles become invalid.
+ * The end of the per-GPU memory daemon's life (section "SAGE Architecture":
+ * one daemon per GPU holds the shared data); the paper defines no call for
+ * it, so this is the library's own. */
 sage_status sage_close(sage_ctx* ctx);
+/* Message of the calling thread's last failure (the library's own error
+ * reporting; no passage in the paper). */
 const char* sage_last_error(void);
 
 /* Pinned host memory (hipHostMalloc) owned by the context; sources here are
- * copied to the device by DMA without staging. NULL on failure. */
+ * copied to the device by DMA without staging. NULL on failure.  The paper
+ * stages its CPU data in host memory ahead of the GPU copy (section
+ * "Parallelizing data and context"); pinned sources are this library's way
+ * to let that copy skip the staging ring.  Freed with sage_host_free or at
+ * sage_close. */
 void* sage_host_alloc(sage_ctx* ctx, size_t nbytes);
 void sage_host_free(sage_ctx* ctx, void* p);
 
@@ -211,7 +222,10 @@ sage_status fn_register(sage_ctx* ctx, const sage_fn_desc* desc, const sage_blob
 
 /* Drop a function.  EBUSY while it has live setups.  Blocks no other
  * registered function uses leave the pool.  Returns after every copy that
- * reads the function's sources has finished: the caller may free them. */
+ * reads the function's sources has finished: the caller may free them.
+ * The last stage of section "Multi-stage Resource Exit" (everything of the
+ * function is released), taken at once on the caller's request.  Requests
+ * of the function still queued in the serving loop fail with ENOTFOUND. */
 sage_status fn_unregister(sage_ctx* ctx, sage_fn fn);
 
 /* Apply the multi-stage exit now (it is also applied at the start of
@@ -237,7 +251,10 @@ sage_status fn_setup(sage_ctx* ctx, sage_fn fn, uint32_t batch, sage_inv* out);
 /* fn_setup for n requests (fns[i], batches[i]) in order; stops at the first
  * failure, returning its status, with out[0..k) set for the k that
  * succeeded (*n_done = k).  setup_ms (may be NULL; n entries) receives each
- * request's own setup time in ms, host wall clock inside the library. */
+ * request's own setup time in ms, host wall clock inside the library: the
+ * setup stage of section "Long Setup Time" (everything before compute) as
+ * this library sees it.  Requests arriving together (section "Low System
+ * Throughput": concurrent requests) are admitted in one call. */
 sage_status fn_setup_batch(sage_ctx* ctx, size_t n, const sage_fn* fns, const uint32_t* batches, sage_inv* out,
                            size_t* n_done, double* setup_ms);
 
@@ -253,7 +270,10 @@ sage_status fn_invoke(sage_ctx* ctx, sage_inv inv, const void* in, size_t in_byt
  * from a captured hipGraph when batch=1); stencil invocations of one
  * function run one sweep launch for all fields.  Invocations of different
  * kinds are split into several groups.  Blocking.  Each output equals the
- * invocation's fn_invoke output. */
+ * invocation's fn_invoke output.  No passage in the paper (it runs each
+ * invocation on its own); batching is the compute side of sharing: one read
+ * of the shared weights serves every invocation of the group.  in/out/
+ * in_bytes/out_bytes are arrays of n entries, as for fn_invoke. */
 sage_status fn_invoke_batch(sage_ctx* ctx, size_t n, const sage_inv* invs, const void* const* in,
                             const size_t* in_bytes, void* const* out, const size_t* out_bytes,
                             uint32_t io_flags);
@@ -263,10 +283,15 @@ sage_status fn_invoke_batch(sage_ctx* ctx, size_t n, const sage_inv* invs, const
  * Exit") and free its private buffers.  ESTATE if already released. */
 sage_status fn_release(sage_ctx* ctx, sage_inv inv);
 
-/* fn_release for n invocations; stops at the first failure. */
+/* fn_release for n invocations; stops at the first failure (first exit
+ * stage of section "Multi-stage Resource Exit" for each). */
 sage_status fn_release_batch(sage_ctx* ctx, size_t n, const sage_inv* invs);
 
-/* ---------------------------------------------------------- introspection */
+/* ---------------------------------------------------------- introspection
+ * Counters and parity introspection (no passage in the paper): what the
+ * tests compare with the oracle and what the benchmark reports. */
+/* Byte accounting (shared + private = logical), residency, references,
+ * H2D bytes and host time per setup stage, since open. */
 sage_status sage_get_stats(sage_ctx* ctx, sage_stats* out);
 /* Fingerprint of each of the function's blocks, in block order (n = count). */
 sage_status sage_fn_fingerprints(sage_ctx* ctx, sage_fn fn, uint64_t* out, size_t n);
@@ -387,6 +412,20 @@ sage_status sage_selftest_plan(uint32_t width, const uint32_t* rows, size_t n_gr
  * Needs no GPU. */
 sage_status sage_selftest_segments(const uint32_t* first, size_t n, uint32_t layers, uint64_t layer_bytes,
                                    size_t* out);
+
+/* Host-only randomized check of the block pool (the structure behind
+ * sections "Read-only Memory Sharing" and "Multi-stage Resource Exit":
+ * shared slots, references, eviction of unreferenced blocks) and of its
+ * fingerprint index.  Runs n_ops random registrations, references,
+ * releases, reloads and drops on a pool of budget_slots slots (a host
+ * stand-in arena: no device memory) against a plain model, checking after
+ * every operation: residency and slots, no slot held twice, used slots =
+ * resident classes, the eviction order, and that each fingerprint chain
+ * holds exactly the resident classes of its fingerprint; then random
+ * inserts and deletions of the index against a hash map.  Stops at the first
+ * violation: EINVAL, *failed_op = its operation number (n_ops when all
+ * passed) and the reason in sage_last_error.  Needs no GPU. */
+sage_status sage_selftest_pool(uint64_t seed, uint32_t n_ops, uint32_t budget_slots, uint32_t* failed_op);
 
 #if defined(__GNUC__)
 #pragma GCC visibility pop

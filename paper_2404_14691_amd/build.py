@@ -31,7 +31,8 @@ def hipcc() -> str:
 # packed FP32 instructions are disabled for every device compile
 DEVICE_FLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17",
                 "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-HOST_SOURCES = ["sage_api.cpp", "register.cpp", "exec.cpp", "pool.cpp", "util.cpp", "serve.cpp", "exit.cpp"]
+HOST_SOURCES = ["sage_api.cpp", "register.cpp", "exec.cpp", "pool.cpp", "util.cpp", "serve.cpp", "exit.cpp",
+                "selftest.cpp"]
 
 
 def _run(cmd):
@@ -73,5 +74,36 @@ def build(verbose: bool = False) -> str:
     return os.path.join(LIB, "libsage.so")
 
 
+def build_sanitized() -> str:
+    """The host self-test driver (csrc/selftest_main.cpp) over the library's
+    host sources compiled by g++ with AddressSanitizer and
+    UndefinedBehaviorSanitizer; the runtime kernels' object from build()
+    is linked unchanged (device code carries no sanitizer).  Returns the
+    executable's path (lib/sage_selftest_san)."""
+    obj = os.path.join(LIB, "obj")
+    krt = os.path.join(obj, "kernels_rt.o")
+    if not os.path.exists(krt):
+        build()
+    san = os.path.join(obj, "san")
+    os.makedirs(san, exist_ok=True)
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    flags = ["-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", "-D__HIP_PLATFORM_AMD__", f"-I{rocm}/include",
+             "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fPIC"]
+    jobs, objs = [], []
+    for src in HOST_SOURCES + ["selftest_main.cpp"]:
+        o = os.path.join(san, src + ".o")
+        objs.append(o)
+        jobs.append(["g++", *flags, "-c", os.path.join(CSRC, src), "-o", o])
+    with ThreadPoolExecutor(max_workers=min(8, len(jobs))) as ex:
+        list(ex.map(_run, jobs))
+    exe = os.path.join(LIB, "sage_selftest_san")
+    _run(["g++", "-fsanitize=address,undefined", *objs, krt, "-o", exe, f"-L{rocm}/lib", f"-Wl,-rpath,{rocm}/lib",
+          "-lamdhip64", "-lpthread", "-ldl"])
+    return exe
+
+
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    if "--sanitized" in sys.argv:
+        print(build_sanitized())
+    else:
+        print(build(verbose="-v" in sys.argv))

@@ -53,6 +53,20 @@ sage_status guard(const std::function<void()>& body);
 hipError_t launch_fp64k(const void* data, uint64_t nbytes, uint64_t* out, int max_groups, hipStream_t s);
 hipError_t launch_blkcopy(const BlkOp* ops, uint32_t n, uint32_t* result, int max_groups, hipStream_t s);
 
+// Allocation-failure injection (SAGE_FAULT_ALLOC_AFTER=N): after N device
+// allocations of the pool arena and the workspace cache have succeeded,
+// every later one fails as if the device were out of memory.  Off (-1) by
+// default.
+struct AllocFault {
+  int64_t left = -1;
+  bool fail_now() {
+    if (left < 0) return false;
+    if (left == 0) return true;
+    left--;
+    return false;
+  }
+};
+
 // --------------------------------------------------- device memory caching
 // Size-binned cache of hipMalloc blocks for workspaces and private copies;
 // memory returns to the bin on put() and to HIP only at close.
@@ -64,6 +78,7 @@ class DevCache {
   size_t held() const { return held_; }
   size_t in_use() const { return in_use_; }
   static size_t round(size_t n);
+  AllocFault* fault = nullptr;
 
  private:
   std::map<size_t, std::vector<void*>> free_;
@@ -155,7 +170,9 @@ class FpIndex {
 
 class Pool {
  public:
-  void init(uint64_t budget_slots, size_t seg_slots);
+  // host_standin: slot addresses are stand-ins that are never dereferenced
+  // and no device memory is allocated (host-only self-test)
+  void init(uint64_t budget_slots, size_t seg_slots, bool host_standin = false);
   void destroy();
   uint8_t* addr(uint32_t slot) const {
     return segs_[slot >> seg_shift_] + (uint64_t)(slot & (seg_slots_ - 1)) * kBlock;
@@ -187,9 +204,11 @@ class Pool {
   std::vector<HostBuf> hbufs;
   std::deque<std::pair<uint32_t, uint64_t>> host_lru;  // (class, demotion number), in demotion order
   uint64_t host_bytes = 0, demotions = 0;
+  AllocFault* fault = nullptr;
 
  private:
   bool grow_arena();
+  bool standin_ = false;
   std::vector<uint8_t*> segs_;
   size_t seg_slots_ = 16384;  // slot ids of segment k start at k * seg_slots_ (a power of two)
   uint32_t seg_shift_ = 14;
@@ -423,6 +442,7 @@ struct Ctx {
   std::string last_launch;                   // kernels and tiles of the last MLP launch
   bool test_fp_const = false;                // force every fingerprint equal (collision test)
   uint64_t dev_chunk = kDevChunkBytes;       // registration chunk of device-resident sources
+  AllocFault alloc_fault;                    // SAGE_FAULT_ALLOC_AFTER
   uint64_t test_fp_value = 0;
 
   bool is_pinned(const void* p, size_t n) const;

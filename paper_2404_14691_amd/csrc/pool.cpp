@@ -75,8 +75,9 @@ void FpIndex::clear() {
 }
 
 // ---------------------------------------------------------------- Pool
-void Pool::init(uint64_t budget_slots, size_t seg_slots) {
+void Pool::init(uint64_t budget_slots, size_t seg_slots, bool host_standin) {
   budget = budget_slots;
+  standin_ = host_standin;
   // a power-of-two stride, so that a slot's segment and offset are a shift
   // and a mask; a segment still holds no more slots than the budget leaves
   seg_shift_ = 0;
@@ -85,7 +86,8 @@ void Pool::init(uint64_t budget_slots, size_t seg_slots) {
 }
 
 void Pool::destroy() {
-  for (uint8_t* s : segs_) (void)hipFree(s);
+  if (!standin_)
+    for (uint8_t* s : segs_) (void)hipFree(s);
   for (HostBuf& h : hbufs)
     if (h.p) (void)hipHostFree(h.p);
   for (auto& kv : spare_host_) (void)hipHostFree(kv.second);
@@ -109,7 +111,10 @@ bool Pool::grow_arena() {
   if (cap >= budget) return false;
   const uint64_t n = std::min<uint64_t>(seg_slots_, budget - cap);
   uint8_t* p = nullptr;
-  if (hipMalloc(&p, n * kBlock) != hipSuccess) {
+  if (standin_) {
+    // host self-test: distinct, never dereferenced segment addresses
+    p = reinterpret_cast<uint8_t*>((uint64_t)(segs_.size() + 1) << 40);
+  } else if ((fault && fault->fail_now()) || hipMalloc(&p, n * kBlock) != hipSuccess) {
     (void)hipGetLastError();
     budget = used_;  // the device is full: the budget stops at what is held
     return false;

@@ -258,6 +258,13 @@ sage_status sage_open(int device, const sage_config* cfg, sage_ctx** out) {
     tune_load(c);
     c.worker.start(device);
     if (const char* e = std::getenv("SAGE_TILE")) c.force_tile = e;
+    if (const char* e = std::getenv("SAGE_FAULT_ALLOC_AFTER")) {
+      const long long v = std::strtoll(e, nullptr, 0);
+      if (v < 0) fail(SAGE_EINVAL, "SAGE_FAULT_ALLOC_AFTER must be >= 0");
+      c.alloc_fault.left = v;
+    }
+    c.pool.fault = &c.alloc_fault;
+    c.cache.fault = &c.alloc_fault;
     if (const char* e = std::getenv("SAGE_DEV_CHUNK_BYTES")) {
       const uint64_t v = std::strtoull(e, nullptr, 0);
       if (v < kBlock || v % kBlock) fail(SAGE_EINVAL, "SAGE_DEV_CHUNK_BYTES must be a positive multiple of 65536");

@@ -61,7 +61,7 @@ void* DevCache::get(size_t n) {
     p = it->second.back();
     it->second.pop_back();
   } else {
-    hipError_t e = hipMalloc(&p, r);
+    hipError_t e = fault && fault->fail_now() ? hipErrorOutOfMemory : hipMalloc(&p, r);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       // give cached blocks back to HIP and retry once
@@ -71,7 +71,7 @@ void* DevCache::get(size_t n) {
           held_ -= kv.first;
         }
       free_.clear();
-      e = hipMalloc(&p, r);
+      e = fault && fault->fail_now() ? hipErrorOutOfMemory : hipMalloc(&p, r);
       if (e != hipSuccess) {
         (void)hipGetLastError();
         fail(SAGE_ENOMEM, "device allocation of %zu bytes failed", r);

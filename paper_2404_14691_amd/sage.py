@@ -138,6 +138,7 @@ _sigs = {
                                      C.POINTER(C.c_double), C.c_size_t, C.c_uint32, C.c_char_p, C.c_size_t]),
     "sage_selftest_setup_overlap": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_int,
                                               C.POINTER(C.c_double)]),
+    "sage_selftest_pool": (C.c_int, [C.c_uint64, C.c_uint32, C.c_uint32, C.POINTER(C.c_uint32)]),
     "sage_serve_start": (C.c_int, [_P, C.c_uint32]),
     "sage_serve_stop": (C.c_int, [_P]),
     "sage_submit": (C.c_int, [_P, C.c_uint64, C.c_uint32, _P, C.c_size_t, _P, C.c_size_t, C.c_uint32,
@@ -429,6 +430,14 @@ def sage_selftest_setup_overlap(load_ms: float, host_ms: float, copy_ms: float, 
 
 
 # ------------------------------------------------------------------ serving
+def sage_selftest_pool(seed: int, n_ops: int, budget_slots: int) -> int:
+    """Operations run before the first failed invariant (n_ops: none failed);
+    raises SageError with the reason on a failure."""
+    at = C.c_uint32()
+    _check(_lib.sage_selftest_pool(seed, n_ops, budget_slots, C.byref(at)), "sage_selftest_pool")
+    return at.value
+
+
 def sage_serve_start(ctx: int, max_rows: int = 0) -> None:
     _check(_lib.sage_serve_start(ctx, max_rows), "sage_serve_start")
 

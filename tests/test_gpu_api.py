@@ -197,3 +197,37 @@ def test_mlp_graph_after_stencil_grows_the_flight_metadata(sage_ctx_factory, tor
     assert np.array_equal(y0, y1)
     S.fn_release(ctx, inv)
     S.fn_release(ctx, rinv)
+
+
+@pytest.mark.parametrize("share", [1, 0])
+def test_allocation_failure_gives_enomem_without_side_effects(sage_ctx_factory, torch_cuda, monkeypatch, share):
+    """SAGE_FAULT_ALLOC_AFTER=0: every pool-arena and workspace allocation
+    fails as if the device were full.  With sharing, registration cannot
+    place its blocks and returns ENOMEM leaving no function, class or byte
+    behind; without sharing, the private copy of fn_setup fails with ENOMEM
+    and no invocation or reference remains.  A context without the knob runs
+    the same work."""
+    from paper_2404_14691_amd import sage as S
+    w = synth.shared_mlp_bf16_functions(n_fns=1, layers=2, width=256, share_frac=0.0, seed=34).blobs[0]
+    desc = S.mlp_desc(S.SAGE_MLP_BF16, 2, 256)
+    monkeypatch.setenv("SAGE_FAULT_ALLOC_AFTER", "0")
+    ctx = sage_ctx_factory(share=share)
+    st0 = S.sage_get_stats(ctx)
+    if share:
+        assert _status(S.fn_register, ctx, desc, [S.make_blob(w)]) == S.SAGE_ENOMEM
+    else:
+        fn = S.fn_register(ctx, desc, [S.make_blob(w)])
+        assert _status(S.fn_setup, ctx, fn, 3) == S.SAGE_ENOMEM
+        S.fn_unregister(ctx, fn)
+    st1 = S.sage_get_stats(ctx)
+    for k in ("logical_bytes", "unique_bytes", "classes", "resident_bytes", "refcount_sum", "live_setups",
+              "h2d_bytes", "workspace_bytes"):
+        assert st1[k] == st0[k], k
+    monkeypatch.delenv("SAGE_FAULT_ALLOC_AFTER")
+    ok = sage_ctx_factory(share=share)
+    fn = S.fn_register(ok, desc, [S.make_blob(w)])
+    inv = S.fn_setup(ok, fn, 3)
+    y = np.zeros((3, 256), dtype=np.float32)
+    S.fn_invoke(ok, inv, synth.bf16_inputs(3, 256, 34, 0), y)
+    assert np.isfinite(y).all() and np.abs(y).sum() > 0
+    S.fn_release(ok, inv)
