@@ -278,6 +278,22 @@ sage_status fn_invoke_batch(sage_ctx* ctx, size_t n, const sage_inv* invs, const
                             const size_t* in_bytes, void* const* out, const size_t* out_bytes,
                             uint32_t io_flags);
 
+/* fn_invoke for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * MLP kinds only, device I/O only (in/out are device addresses, as with
+ * SAGE_IO_DEVICE_IN | SAGE_IO_DEVICE_OUT); same output bits as fn_invoke.
+ * The body's metadata and activations live in one fixed scratch array per
+ * GPU (kept by the library until the process ends) instead of buffers the
+ * library allocates: at most 512 rows, and batch x width x 2 (BF16) or
+ * x 4 (FP32) <= 4 MiB; larger invocations give SAGE_EINVAL before any work.
+ * No hipMalloc / hipFree; eager launches; the tile plan comes from timings
+ * the context already measured (none yet: a fixed tile shape).  Blocking.
+ * Every call on one GPU, from any context, uses the same scratch: calls that
+ * overlap on one GPU (two contexts on two threads) race; calls on one
+ * context are serialised by its mutex.  ESTATE while the serving loop runs. */
+sage_status fn_invoke_noalloc(sage_ctx* ctx, sage_inv inv, const void* in, size_t in_bytes, void* out,
+                              size_t out_bytes);
+
 /* End an invocation: drop its block references (blocks reaching zero stay
  * resident until evicted: first exit stage, section "Multi-stage Resource
  * Exit") and free its private buffers.  ESTATE if already released. */

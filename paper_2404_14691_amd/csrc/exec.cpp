@@ -70,7 +70,7 @@ struct MlpPlan {
   double cost_ms = 0;                // predicted layer time
 };
 uint32_t shape_grid(const Ctx& c, const TileShape& ts);
-MlpPlan plan_mlp(Ctx& c, uint32_t W, const std::vector<uint32_t>& m);
+MlpPlan plan_mlp(Ctx& c, uint32_t W, const std::vector<uint32_t>& m, bool may_tune = true);
 
 void flights_init(Ctx& c) {
   c.flights.resize(std::max<uint32_t>(1, c.cfg.inflight_groups));
@@ -171,7 +171,11 @@ static void launch_kernel(hipFunction_t k, uint32_t grid, uint32_t threads, hipS
 // group's full row tiles, and a thin tile shape over the ragged last row
 // tiles of some groups, when that removes a nearly empty last wave of large
 // tiles (see plan_mlp).  Both cover disjoint outputs of the same row space.
-int launch_mlp_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, int flight) {
+//
+// With `ext` the metadata and the activations live in the caller's buffers
+// instead of the flight's (nothing is allocated): device I/O only, eager
+// launches (no graph), no autotuning, no kernel timing.
+int launch_mlp_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, int flight, const ExtScratch* ext) {
   const sage_fn_desc& d = calls[0].inv->fn->d;
   const uint32_t W = d.width, L = d.layers;
   const bool bf16 = d.kind == SAGE_MLP_BF16;
@@ -197,26 +201,46 @@ int launch_mlp_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, int fl
     for (size_t i : members[g]) gm[g] += calls[i].inv->batch;
   for (uint32_t m : gm) M += m;
 
+  const bool host_in = !(io & SAGE_IO_DEVICE_IN), host_out = !(io & SAGE_IO_DEVICE_OUT);
+  if (ext) {
+    if (host_in || host_out) fail(SAGE_EINVAL, "caller-scratch launches take device I/O only");
+    if (kMetaTabOff + (size_t)M * 16 > ext->meta_cap || 2 * (size_t)M * W * es_act > ext->ws_cap)
+      fail(SAGE_EINVAL, "%u rows of width %u exceed the scratch buffer", M, W);
+  }
   MlpPlan plan;
-  if (bf16) plan = plan_mlp(c, W, gm);
+  if (bf16) plan = plan_mlp(c, W, gm, ext == nullptr);
 
   const int fi = take_flight(c, flight);
   Flight& F = c.flights[fi];
-  bool moved = false;
-  moved |= ensure(&F.d_meta, &F.h_meta, &F.meta_cap, kMetaTabOff + (size_t)M * 16);
-  moved |= ensure(&F.ws, nullptr, &F.ws_cap, 2 * (size_t)M * W * es_act);
-  // graphs hold meta/workspace addresses and the row capacity
-  const size_t rows_cap = (F.meta_cap - kMetaTabOff) / 16;
-  if (moved) drop_graphs(F);
-  const bool host_in = !(io & SAGE_IO_DEVICE_IN), host_out = !(io & SAGE_IO_DEVICE_OUT);
-  if (host_in) ensure(&F.d_in, &F.h_in, &F.in_cap, (size_t)M * W * es_in);
-  if (host_out) ensure(&F.d_out, &F.h_out, &F.out_cap, (size_t)M * W * 4);
+  uint8_t *d_meta, *h_meta, *ws;
+  size_t meta_cap, ws_cap;
+  if (ext) {
+    d_meta = ext->d_meta;
+    h_meta = ext->h_meta;
+    meta_cap = ext->meta_cap;
+    ws = ext->ws;
+    ws_cap = ext->ws_cap;
+  } else {
+    bool moved = false;
+    moved |= ensure(&F.d_meta, &F.h_meta, &F.meta_cap, kMetaTabOff + (size_t)M * 16);
+    moved |= ensure(&F.ws, nullptr, &F.ws_cap, 2 * (size_t)M * W * es_act);
+    // graphs hold meta/workspace addresses and the row capacity
+    if (moved) drop_graphs(F);
+    if (host_in) ensure(&F.d_in, &F.h_in, &F.in_cap, (size_t)M * W * es_in);
+    if (host_out) ensure(&F.d_out, &F.h_out, &F.out_cap, (size_t)M * W * 4);
+    d_meta = F.d_meta;
+    h_meta = F.h_meta;
+    meta_cap = F.meta_cap;
+    ws = F.ws;
+    ws_cap = F.ws_cap;
+  }
+  const size_t rows_cap = (meta_cap - kMetaTabOff) / 16;
 
-  GemmHdr* hdr = reinterpret_cast<GemmHdr*>(F.h_meta);
-  GemmGroup* grp = reinterpret_cast<GemmGroup*>(F.h_meta + kMetaGroupsOff);
-  GemmHdr* thdr = reinterpret_cast<GemmHdr*>(F.h_meta + kMetaTailOff);
-  GemmGroup* tgrp = reinterpret_cast<GemmGroup*>(F.h_meta + kMetaTailOff + kMetaGroupsOff);
-  uint64_t* in_tab = reinterpret_cast<uint64_t*>(F.h_meta + kMetaTabOff);
+  GemmHdr* hdr = reinterpret_cast<GemmHdr*>(h_meta);
+  GemmGroup* grp = reinterpret_cast<GemmGroup*>(h_meta + kMetaGroupsOff);
+  GemmHdr* thdr = reinterpret_cast<GemmHdr*>(h_meta + kMetaTailOff);
+  GemmGroup* tgrp = reinterpret_cast<GemmGroup*>(h_meta + kMetaTailOff + kMetaGroupsOff);
+  uint64_t* in_tab = reinterpret_cast<uint64_t*>(h_meta + kMetaTabOff);
   uint64_t* out_tab = in_tab + rows_cap;
   uint32_t row = 0, tiles = 0, ttiles = 0, ng = 0, nt = 0;
   F.deliver.clear();
@@ -279,12 +303,12 @@ int launch_mlp_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, int fl
     }
   }
   if (fed) HIPX(hipStreamWaitEvent(s, c.reload_done, 0));
-  HIPX(hipMemcpyAsync(F.d_meta, F.h_meta, kMetaGroupsOff + ng * sizeof(GemmGroup), hipMemcpyHostToDevice, s));
+  HIPX(hipMemcpyAsync(d_meta, h_meta, kMetaGroupsOff + ng * sizeof(GemmGroup), hipMemcpyHostToDevice, s));
   if (split)
-    HIPX(hipMemcpyAsync(F.d_meta + kMetaTailOff, F.h_meta + kMetaTailOff, kMetaGroupsOff + nt * sizeof(GemmGroup),
+    HIPX(hipMemcpyAsync(d_meta + kMetaTailOff, h_meta + kMetaTailOff, kMetaGroupsOff + nt * sizeof(GemmGroup),
                         hipMemcpyHostToDevice, s));
-  HIPX(hipMemcpyAsync(F.d_meta + kMetaTabOff, in_tab, (size_t)M * 8, hipMemcpyHostToDevice, s));
-  HIPX(hipMemcpyAsync(F.d_meta + kMetaTabOff + rows_cap * 8, out_tab, (size_t)M * 8, hipMemcpyHostToDevice, s));
+  HIPX(hipMemcpyAsync(d_meta + kMetaTabOff, in_tab, (size_t)M * 8, hipMemcpyHostToDevice, s));
+  HIPX(hipMemcpyAsync(d_meta + kMetaTabOff + rows_cap * 8, out_tab, (size_t)M * 8, hipMemcpyHostToDevice, s));
   if (host_in) HIPX(hipMemcpyAsync(F.d_in, F.h_in, (size_t)M * W * es_in, hipMemcpyHostToDevice, s));
 
   Module* mod = calls[0].inv->fn->mod;
@@ -293,19 +317,19 @@ int launch_mlp_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, int fl
   const uint32_t grid = bf16 ? shape_grid(c, *ms) : (uint32_t)c.cus * 4;
   const uint32_t threads = bf16 ? ms->threads : 256;
   const uint32_t tgrid = split ? shape_grid(c, *plan.tail) : 0, tthreads = split ? plan.tail->threads : 0;
-  const GemmHdr* d_hdr = reinterpret_cast<const GemmHdr*>(F.d_meta);
-  const GemmGroup* d_grp = reinterpret_cast<const GemmGroup*>(F.d_meta + kMetaGroupsOff);
-  const GemmHdr* d_thdr = reinterpret_cast<const GemmHdr*>(F.d_meta + kMetaTailOff);
-  const GemmGroup* d_tgrp = reinterpret_cast<const GemmGroup*>(F.d_meta + kMetaTailOff + kMetaGroupsOff);
-  const uint64_t* d_in_tab = reinterpret_cast<const uint64_t*>(F.d_meta + kMetaTabOff);
+  const GemmHdr* d_hdr = reinterpret_cast<const GemmHdr*>(d_meta);
+  const GemmGroup* d_grp = reinterpret_cast<const GemmGroup*>(d_meta + kMetaGroupsOff);
+  const GemmHdr* d_thdr = reinterpret_cast<const GemmHdr*>(d_meta + kMetaTailOff);
+  const GemmGroup* d_tgrp = reinterpret_cast<const GemmGroup*>(d_meta + kMetaTailOff + kMetaGroupsOff);
+  const uint64_t* d_in_tab = reinterpret_cast<const uint64_t*>(d_meta + kMetaTabOff);
   const uint64_t* d_out_tab = d_in_tab + rows_cap;
-  const size_t half = F.ws_cap / 2;
+  const size_t half = ws_cap / 2;
   auto layer_args = [&](uint32_t l) {
     LayerArgs la{};
     la.a_tab = l == 0 ? d_in_tab : nullptr;
-    la.a_base = F.ws + ((l + 1) % 2) * half;
+    la.a_base = ws + ((l + 1) % 2) * half;
     la.c_tab = l == L - 1 ? d_out_tab : nullptr;
-    la.c_base = F.ws + (l % 2) * half;
+    la.c_base = ws + (l % 2) * half;
     la.w_off = (uint64_t)l * W * W * es_in;
     la.N = W;
     la.K = W;
@@ -322,8 +346,8 @@ int launch_mlp_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, int fl
   };
   const char* tname = bf16 ? "ggemm_bf16" : "mlp_f32";
   // a gated launch's span includes copy waits: it is not timed, nor captured
-  const int tok = gated.empty() ? c.timer.start(tname, s, L) : -1;
-  if (c.cfg.batch && gated.empty()) {
+  const int tok = gated.empty() && !ext ? c.timer.start(tname, s, L) : -1;
+  if (c.cfg.batch && gated.empty() && !ext) {
     const GraphKey key{kname + (split ? std::string("+") + plan.tail->name : std::string()) + (tiles ? "" : "/tail"),
                        L, W};
     auto it = F.graphs.find(key);
@@ -614,7 +638,10 @@ static MlpPlan plan_from(const std::map<std::string, TuneEntry>& tune, uint32_t 
   return best;
 }
 
-MlpPlan plan_mlp(Ctx& c, uint32_t W, const std::vector<uint32_t>& m) {
+// may_tune = false: plan from the full-wave times already measured for W
+// (none: the 128 x 128 shape, which fits every supported width); every
+// shape gives the same bits, so only the speed depends on it.
+MlpPlan plan_mlp(Ctx& c, uint32_t W, const std::vector<uint32_t>& m, bool may_tune) {
   MlpPlan best;
   best.split.assign(m.size(), 0);
   if (!c.force_tile.empty()) {
@@ -627,6 +654,16 @@ MlpPlan plan_mlp(Ctx& c, uint32_t W, const std::vector<uint32_t>& m) {
     for (const TileShape* t : {best.main, best.tail})
       if (t && !fits(*t, W)) fail(SAGE_EINVAL, "tile %s does not fit width %u", t->name, W);
     return best;
+  }
+  if (!may_tune) {
+    bool any = false;
+    for (const auto& ts : kShapes) any |= fits(ts, W) && c.tune.count(tune_key(W, ts)) > 0;
+    if (!any) {
+      best.main = &shape_of("ggemm_bf16_128x128");
+      if (!fits(*best.main, W)) fail(SAGE_EINVAL, "tile %s does not fit width %u", best.main->name, W);
+      return best;
+    }
+    return plan_from(c.tune, (uint32_t)c.cus, W, m);
   }
   tune_width(c, W);
   return plan_from(c.tune, (uint32_t)c.cus, W, m);

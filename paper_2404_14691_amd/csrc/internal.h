@@ -53,6 +53,18 @@ sage_status guard(const std::function<void()>& body);
 hipError_t launch_fp64k(const void* data, uint64_t nbytes, uint64_t* out, int max_groups, hipStream_t s);
 hipError_t launch_blkcopy(const BlkOp* ops, uint32_t n, uint32_t* result, int max_groups, hipStream_t s);
 
+// Fixed device scratch of fn_invoke_noalloc: one array per GPU in the
+// library's code object, never freed.  Layout: [metadata: kNoAllocMetaBytes]
+// [activations: 2 x kNoAllocActBytes, ping-pong].  Limits: kNoAllocRows rows,
+// rows x width x activation element size <= kNoAllocActBytes.
+constexpr size_t kNoAllocMetaBytes = 64u << 10;
+constexpr size_t kNoAllocActBytes = 4u << 20;
+constexpr size_t kNoAllocScratchBytes = kNoAllocMetaBytes + 2 * kNoAllocActBytes;
+constexpr uint32_t kNoAllocRows = 512;
+// Device address of the current device's scratch array (looked up once per
+// device; `device` must be current).
+hipError_t noalloc_scratch(int device, uint8_t** out);
+
 // Allocation-failure injection (SAGE_FAULT_ALLOC_AFTER=N): after N device
 // allocations of the pool arena and the workspace cache have succeeded,
 // every later one fails as if the device were out of memory.  Off (-1) by
@@ -443,6 +455,8 @@ struct Ctx {
   bool test_fp_const = false;                // force every fingerprint equal (collision test)
   uint64_t dev_chunk = kDevChunkBytes;       // registration chunk of device-resident sources
   AllocFault alloc_fault;                    // SAGE_FAULT_ALLOC_AFTER
+  uint8_t* na_scratch = nullptr;             // device address of this GPU's fn_invoke_noalloc scratch
+  uint8_t* na_hmeta = nullptr;               // pinned host mirror of its metadata part
   uint64_t test_fp_value = 0;
 
   bool is_pinned(const void* p, size_t n) const;
@@ -486,8 +500,18 @@ struct Call {
   void* out;
   size_t out_bytes;
 };
+// Caller-provided device metadata / activation buffers and their pinned
+// host mirror for the metadata (fn_invoke_noalloc).
+struct ExtScratch {
+  uint8_t* d_meta;
+  uint8_t* h_meta;
+  size_t meta_cap;
+  uint8_t* ws;
+  size_t ws_cap;
+};
 // Launch a group on flight `flight` (-1: the next one, waiting if busy).
-int launch_mlp_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, int flight = -1);
+int launch_mlp_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, int flight = -1,
+                     const ExtScratch* ext = nullptr);
 int launch_stencil_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, int flight = -1);
 void finish_flight(Ctx& c, int flight);
 void flights_init(Ctx& c);

@@ -5,7 +5,9 @@
 // loads issued before any use, one workgroup per block (grid-stride).
 #include <hip/hip_runtime.h>
 
-#include "layout.h"
+#include <mutex>
+
+#include "internal.h"
 
 namespace sage {
 
@@ -164,6 +166,28 @@ __global__ __launch_bounds__(256) void blkcopy_kernel(const BlkOp* __restrict__ 
       if (has1) block_op(op1, result + o + 1, t);
     }
   }
+}
+
+// Scratch of fn_invoke_noalloc (metadata + activations), a fixed array in
+// every GPU's copy of this code object.  Host code never passes `scratch`
+// itself (on the host it is only a stand-in symbol): it passes the device
+// address that noalloc_scratch looked up for the current device.
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+hipError_t noalloc_scratch(int device, uint8_t** out) {
+  static std::mutex mu;
+  static uint8_t* addr[64] = {};
+  if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[device] = static_cast<uint8_t*>(p);
+  }
+  *out = addr[device];
+  return hipSuccess;
 }
 
 hipError_t launch_fp64k(const void* data, uint64_t nbytes, uint64_t* out, int max_groups, hipStream_t s) {

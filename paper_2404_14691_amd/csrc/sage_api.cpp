@@ -254,6 +254,10 @@ sage_status sage_open(int device, const sage_config* cfg, sage_ctx** out) {
     c.pool.init(budget, (size_t)std::min<uint64_t>(16384, budget));
     ring_init(c);
     if (c.cfg.share) HIPX(hipMalloc((void**)&c.rstage_dev, kReloadStageBlocks * kBlock));  // reload staging
+    // fn_invoke_noalloc: this GPU's fixed scratch (looked up with the device
+    // current) and a pinned mirror of its metadata part
+    HIPX(noalloc_scratch(device, &c.na_scratch));
+    HIPX(hipHostMalloc((void**)&c.na_hmeta, kNoAllocMetaBytes, hipHostMallocDefault));
     flights_init(c);
     tune_load(c);
     c.worker.start(device);
@@ -316,6 +320,8 @@ sage_status sage_close(sage_ctx* p) {
       if (c.reg_dops) (void)hipFree(c.reg_dops);
       if (c.reg_dres) (void)hipFree(c.reg_dres);
       if (c.rstage_dev) (void)hipFree(c.rstage_dev);
+      if (c.na_hmeta) (void)hipHostFree(c.na_hmeta);
+      c.na_hmeta = nullptr;
       for (hipEvent_t e : c.rstage_ev) (void)hipEventDestroy(e);
       c.deferred_dev.clear();
       c.deferred_host.clear();
@@ -546,6 +552,43 @@ sage_status fn_invoke_batch(sage_ctx* p, size_t n, const sage_inv* ids, const vo
     }
     const double t0 = now_ms();
     run_calls(c, calls, io);
+    c.t_invoke += now_ms() - t0;
+  });
+}
+
+// fn_invoke for callers that cannot allocate: the body's metadata and
+// activations live in the GPU's fixed scratch array instead of the flight's
+// buffers, launches are eager, and the tile plan comes from timings already
+// measured (no autotuning).  Calls on one GPU share that scratch.
+sage_status fn_invoke_noalloc(sage_ctx* p, sage_inv id, const void* in, size_t in_bytes, void* out,
+                              size_t out_bytes) {
+  return guard([&] {
+    Ctx& c = ctx_of(p);
+    if (!in || !out) fail(SAGE_EINVAL, "null buffer");
+    std::lock_guard<std::recursive_mutex> lk(c.mu);
+    if (c.serve) fail(SAGE_ESTATE, "the serving loop owns the launch flights: use sage_submit");
+    HIPX(hipSetDevice(c.device));
+    Inv& v = inv_of(c, id);
+    const sage_fn_desc& d = v.fn->d;
+    if (is_grid(d.kind)) fail(SAGE_EINVAL, "fn_invoke_noalloc runs the MLP kinds only");
+    if (in_bytes != in_bytes_for(d, v.batch) || out_bytes != out_bytes_for(d, v.batch))
+      fail(SAGE_EINVAL, "in/out bytes %zu/%zu, expected %zu/%zu", in_bytes, out_bytes, in_bytes_for(d, v.batch),
+           out_bytes_for(d, v.batch));
+    check_aligned(in, "device input");
+    check_aligned(out, "device output");
+    const size_t act = in_elem_size(d);
+    if (v.batch > kNoAllocRows || (size_t)v.batch * d.width * act > kNoAllocActBytes)
+      fail(SAGE_EINVAL,
+           "batch %u x width %u exceeds the fixed scratch of fn_invoke_noalloc: at most %u rows and "
+           "rows x width x %zu <= %zu bytes",
+           v.batch, d.width, kNoAllocRows, act, kNoAllocActBytes);
+    const ExtScratch ext{c.na_scratch, c.na_hmeta, kNoAllocMetaBytes, c.na_scratch + kNoAllocMetaBytes,
+                         2 * kNoAllocActBytes};
+    const double t0 = now_ms();
+    const std::vector<Call> calls{Call{&v, in, in_bytes, out, out_bytes}};
+    const int fl = launch_mlp_group(c, calls, SAGE_IO_DEVICE_IN | SAGE_IO_DEVICE_OUT, -1, &ext);
+    finish_flight(c, fl);
+    c.invocations++;
     c.t_invoke += now_ms() - t0;
   });
 }

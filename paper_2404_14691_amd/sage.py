@@ -114,6 +114,7 @@ _sigs = {
     "fn_invoke": (C.c_int, [_P, C.c_uint64, _P, C.c_size_t, _P, C.c_size_t, C.c_uint32]),
     "fn_invoke_batch": (C.c_int, [_P, C.c_size_t, C.POINTER(C.c_uint64), C.POINTER(_P), C.POINTER(C.c_size_t),
                                   C.POINTER(_P), C.POINTER(C.c_size_t), C.c_uint32]),
+    "fn_invoke_noalloc": (C.c_int, [_P, C.c_uint64, _P, C.c_size_t, _P, C.c_size_t]),
     "fn_release": (C.c_int, [_P, C.c_uint64]),
     "fn_setup_batch": (C.c_int, [_P, C.c_size_t, C.POINTER(C.c_uint64), C.POINTER(C.c_uint32),
                                  C.POINTER(C.c_uint64), C.POINTER(C.c_size_t), C.POINTER(C.c_double)]),
@@ -283,6 +284,13 @@ def fn_invoke_batch(ctx: int, invs, inputs, outputs, io_flags: int = 0) -> None:
     ip, ib = side(inputs, bool(io_flags & SAGE_IO_DEVICE_IN))
     op, ob = side(outputs, bool(io_flags & SAGE_IO_DEVICE_OUT))
     _check(_lib.fn_invoke_batch(ctx, n, ids, ip, ib, op, ob, io_flags), "fn_invoke_batch")
+
+
+def fn_invoke_noalloc(ctx: int, inv: int, inp, out) -> None:
+    """inp/out: (device address, nbytes) tuples."""
+    ip, ib = _io_ptr(inp, True)
+    op, ob = _io_ptr(out, True)
+    _check(_lib.fn_invoke_noalloc(ctx, inv, ip, ib, op, ob), "fn_invoke_noalloc")
 
 
 def fn_release(ctx: int, inv: int) -> None:
