@@ -150,11 +150,16 @@ def plain_step(S, ctx, wl):
     return setup_ms
 
 
+# the BF16 GEMM kernels end where the FP32 layer kernel's section of the file begins
+GEMM_END_MARKER = b"// ---------------------------------------------------------------- FP32 MLP"
+
+
 def gemm_sources_digest():
     h = hashlib.sha256()
     for f in GEMM_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+            data = fh.read()
+        h.update(data.split(GEMM_END_MARKER)[0])
     return h.hexdigest()[:16]
 
 
@@ -453,6 +458,167 @@ def host_sourced(S, torch, wl, shared_steps=10, naive_requests=64):
     return res
 
 
+def cold_setup_ab(S, wl, pairs=20):
+    """Parallelized setup against serialized setup on cold contexts (section
+    "Effectiveness of parallelized setup mechanism"): each sample opens a new
+    context, so registering a function loads its code object (hipModuleLoad)
+    and allocates its block table on one thread while its 256 MiB of weights
+    move from pageable host memory through the staging ring on the other; the
+    serial mode runs the two branches one after the other.  Modes alternate
+    (ABBA) within one process; reported: medians, interquartile ranges and
+    the median of the paired differences."""
+    desc = S.mlp_desc(S.SAGE_MLP_BF16, wl.layers, wl.width)
+    blob = wl.host_blobs[0]
+    res = {"parallel": [], "serial": []}
+    code_ms = {"parallel": [], "serial": []}
+    for p in range(pairs):
+        order = ("parallel", "serial") if p % 2 == 0 else ("serial", "parallel")
+        for mode in order:
+            cfg = S.sage_config_default()
+            cfg.pool_budget_bytes = 1 << 30
+            cfg.serial_setup = 1 if mode == "serial" else 0
+            ctx = S.sage_open(0, cfg)
+            try:
+                st0 = S.sage_get_stats(ctx)
+                t0 = time.perf_counter()
+                fn = S.fn_register(ctx, desc, [S.make_blob(blob)])
+                res[mode].append((time.perf_counter() - t0) * 1e3)
+                st1 = S.sage_get_stats(ctx)
+                code_ms[mode].append(st1["t_module_ms"] - st0["t_module_ms"])
+                S.fn_unregister(ctx, fn)
+            finally:
+                S.sage_close(ctx)
+    diff = [s_ - p_ for s_, p_ in zip(res["serial"], res["parallel"])]
+
+    def summ(v):
+        q = np.percentile(v, [25, 50, 75])
+        return {"median": round(float(q[1]), 3), "iqr": [round(float(q[0]), 3), round(float(q[2]), 3)]}
+    return {"what": "cold-context fn_register of one 256 MiB BF16 MLP from pageable host memory (code object "
+                    "load + block table beside the staged data), ms",
+            "samples_per_mode": pairs, "parallel": summ(res["parallel"]), "serial": summ(res["serial"]),
+            "serial_minus_parallel": summ(diff),
+            "module_load_ms": {m: round(float(np.median(v)), 3) for m, v in code_ms.items()}}
+
+
+def serving_leg(S, torch, rate=1000.0, duration=10.0, plain_prefix_s=0.25, budget_frac=0.5):
+    """Serving at the over-HBM regime of the Poisson workload, shared against
+    plain on one arrival trace.
+
+    16 BF16 MLP functions of width 4096 (sizes lognormal 64 MiB..4 GiB, 20 %
+    of blocks from a common pool), sources in pinned host memory, so every
+    reload after an eviction crosses the host link; pool budget half of the
+    unique bytes (the functions' read-only data cannot all stay in HBM);
+    Poisson arrivals at `rate` for `duration` s, Zipf(1) popularity, batch
+    U[1,64], each request with its own seeded input.  Shared: pool +
+    references + eviction + continuous batching, reloads issued without
+    waiting (the launch waits for them).  Plain: the same loop with a private
+    copy of the function's weights per request, on the first `plain_prefix_s`
+    seconds of the same trace (its queue grows without bound at this rate).
+    The plain requests' outputs are compared bit for bit with the same
+    requests' outputs in the shared run."""
+    from paper_2404_14691_amd import synth
+    W, maxrows = 4096, 64
+    wl = synth.serving_workload(rate=rate, duration=duration, seed=1000)
+    layers = wl.layers
+    sizes = [l * W * W * 2 for l in layers]
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    per = 32768
+    common = (torch.randn((max(sizes) // 65536, per), generator=g, device="cuda") / 64.0).to(torch.bfloat16)
+    dev_blobs = []
+    for nbytes in sizes:
+        nb = nbytes // 65536
+        b = (torch.randn((nb, per), generator=g, device="cuda") / 64.0).to(torch.bfloat16)
+        share = torch.rand(nb, generator=g, device="cuda") < wl.overlap_frac
+        b[share] = common[:nb][share]
+        dev_blobs.append(b)
+    del common
+    n = len(wl.arrivals)
+    rows = np.asarray(wl.batch, dtype=np.int64)
+    row0 = np.concatenate([[0], np.cumsum(rows)[:-1]])
+    total_rows = int(rows.sum())
+    x = torch.randn((total_rows, W), generator=g, device="cuda").to(torch.bfloat16)
+    y_shared = torch.empty((total_rows, W), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    io = S.SAGE_IO_DEVICE_IN | S.SAGE_IO_DEVICE_OUT
+    logical = sum(sizes)
+
+    def run(share, reqs, y, budget):
+        cfg = S.sage_config_default()
+        cfg.share = share
+        cfg.pool_budget_bytes = budget
+        cfg.progressive = 1 if share else 0
+        ctx = S.sage_open(0, cfg)
+        host = []
+        try:
+            for b in dev_blobs:
+                a = S.pinned_array(ctx, (b.numel(),), np.uint16)
+                torch.from_numpy(a.view(np.int16)).copy_(b.view(torch.int16).reshape(-1))
+                host.append(a)
+            fns = [S.fn_register(ctx, S.mlp_desc(S.SAGE_MLP_BF16, l, W), [S.make_blob(a)])
+                   for l, a in zip(layers, host)]
+            st = S.sage_get_stats(ctx)
+            S.sage_serve_start(ctx)
+            ev0 = st["evictions"]
+            ids = []
+            t0 = time.perf_counter()
+            for i in reqs:
+                while time.perf_counter() - t0 < wl.arrivals[i]:
+                    pass
+                r, b = int(row0[i]), int(rows[i])
+                ids.append(S.sage_submit(ctx, fns[int(wl.fn[i])], b, (x.data_ptr() + r * W * 2, b * W * 2),
+                                         (y.data_ptr() + r * W * 4, b * W * 4), io))
+            for r in ids:
+                S.sage_wait(ctx, r, 600000)
+            rep = S.sage_serve_stats(ctx)
+            S.sage_serve_stop(ctx)
+            st1 = S.sage_get_stats(ctx)
+            for f in fns:
+                S.fn_unregister(ctx, f)
+            for a in host:
+                S.sage_host_free(ctx, a.ctypes.data)
+        finally:
+            S.sage_close(ctx)
+        return {"requests": len(reqs), "completed": int(rep["completed"]), "failed": int(rep["failed"]),
+                "throughput": round(rep["throughput"], 1),
+                "setup_ms": {"p50": round(rep["setup_p50_ms"], 3), "p99": round(rep["setup_p99_ms"], 3)},
+                "e2e_ms": {"p50": round(rep["e2e_p50_ms"], 3), "p99": round(rep["e2e_p99_ms"], 3)},
+                "launches": int(rep["launches"]), "evictions": int(st1["evictions"] - ev0),
+                "reloads": int(st1["reloads"] - st["reloads"]), "h2d_ro_bytes": int(st1["h2d_bytes"])}, st
+
+    # unique bytes of the 16 functions (a registration pass), then the budget
+    cfg = S.sage_config_default()
+    cfg.pool_budget_bytes = 1 << 40
+    ctx = S.sage_open(0, cfg)
+    try:
+        fns = [S.fn_register(ctx, S.mlp_desc(S.SAGE_MLP_BF16, l, W),
+                             [S.make_blob(b.data_ptr(), b.numel() * 2, where=S.SAGE_SRC_DEVICE)])
+               for l, b in zip(layers, dev_blobs)]
+        unique = S.sage_get_stats(ctx)["unique_bytes"]
+    finally:
+        S.sage_close(ctx)
+    budget = int(unique * budget_frac) // 65536 * 65536
+    shared, _ = run(1, list(range(n)), y_shared, budget)
+    log(f"serving shared: {shared}")
+    prefix = [i for i in range(n) if wl.arrivals[i] < plain_prefix_s]
+    y_plain = torch.full((total_rows, W), float("nan"), dtype=torch.float32, device="cuda")
+    plain, _ = run(0, prefix, y_plain, 1 << 20)
+    log(f"serving plain: {plain}")
+    last = int(row0[prefix[-1]] + rows[prefix[-1]]) if prefix else 0
+    same = bool(torch.equal(y_plain[:last], y_shared[:last])) if last else None
+    del x, y_shared, y_plain, dev_blobs
+    torch.cuda.empty_cache()
+    return {"workload": f"Poisson {rate:.0f} req/s for {duration:.0f} s over 16 BF16 MLP functions (width 4096, "
+                        f"{logical / 2**30:.2f} GiB logical, {unique / 2**30:.2f} GiB unique, 20% block overlap), "
+                        f"batch U[1,64], Zipf(1) popularity, sources in pinned host memory, distinct inputs",
+            "pool_budget_bytes": budget, "budget_note": f"{budget_frac:.0%} of unique bytes: not all read-only "
+                                                         f"data fits, so admission evicts and reloads over the host link",
+            "shared_batched": shared,
+            "plain": dict(plain, trace=f"the first {plain_prefix_s} s of the same trace ({len(prefix)} requests)"),
+            "plain_outputs_equal_shared": same,
+            "duration_note": f"{duration:.0f} s per rate rather than 60 s, to keep the default run within minutes"}
+
+
 def _host_cpu():
     """(BLAS threads, nproc, CPU model) of this host."""
     try:
@@ -588,6 +754,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-kernels", action="store_true", help="skip the standalone 4 GiB kernel bandwidth runs")
     ap.add_argument("--no-host-link", action="store_true", help="skip the host-memory registration runs")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--only-shared", action="store_true",
                     help="time the shared+batched steps only (for counter runs); no plain path or extras")
     ap.add_argument("--workload", default="sharing",
@@ -720,14 +887,23 @@ def main():
         "kernels": {
             "fp64k": {"avg_ms": round(f_ms / max(f_n, 1), 5), "launches": f_n, "steps": warm_steps,
                       "GB/s": round(fp_bytes * warm_steps / max(f_ms * 1e-3, 1e-12) / 1e9, 1)},
-            "blkcopy": {"avg_ms": round(b_ms / max(b_n, 1), 5), "launches": b_n, "steps": warm_steps},
+            # every block of a registration is either COPYed into a new slot or
+            # VERIFYed against its class: 2 x 64 KiB moved per block either way
+            "blkcopy": {"avg_ms": round(b_ms / max(b_n, 1), 5), "launches": b_n, "steps": warm_steps,
+                        "GB/s": round(2 * sum(b.numel() for b in wl.dev_blobs) * warm_steps / max(b_ms * 1e-3, 1e-12)
+                                      / 1e9, 1)},
             "ggemm_bf16": {"avg_ms": round(gemm_avg_ms, 5), "launches": g_n}},
         "kernels_standalone_4GiB": standalone,
         "host_ms_per_step": host,
     }
+    if not args.no_serving and not args.only_shared:
+        log("serving leg ...")
+        line["serving_host_sourced"] = serving_leg(S, torch)
     if not args.no_host_link and not args.only_shared:
         log("host-sourced shared vs plain ...")
         line["host_sourced"] = host_sourced(S, torch, wl)
+        line["host_sourced"]["cold_setup_ab"] = cold_setup_ab(S, wl)
+        log(f"cold setup A/B: {line['host_sourced']['cold_setup_ab']}")
         log("host-link registration runs ...")
         line["host_link_not_headline"] = host_link(S, torch, wl)
         log(f"host link: {line['host_link_not_headline']}")

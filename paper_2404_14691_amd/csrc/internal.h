@@ -292,7 +292,7 @@ struct Fn {
   hipEvent_t ready = nullptr;         // data of the function is in place
   std::vector<hipEvent_t> seg;        // progressive reload: layer l's blocks are in place
   uint32_t block_len(uint32_t b) const;
-  const uint8_t* block_src(uint32_t b, bool* dev) const;
+  const uint8_t* block_src(uint32_t b, bool* dev, bool* pinned = nullptr) const;
 };
 
 struct Inv {

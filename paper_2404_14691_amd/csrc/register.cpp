@@ -191,9 +191,10 @@ uint32_t Fn::block_len(uint32_t b) const {
   return (uint32_t)std::min<uint64_t>(kBlock, srcs[i].n - off);
 }
 
-const uint8_t* Fn::block_src(uint32_t b, bool* dev) const {
+const uint8_t* Fn::block_src(uint32_t b, bool* dev, bool* pinned) const {
   size_t i = std::upper_bound(blob_first.begin(), blob_first.end(), b) - blob_first.begin() - 1;
   *dev = srcs[i].dev;
+  if (pinned) *pinned = srcs[i].pinned;
   return srcs[i].p + (uint64_t)(b - blob_first[i]) * kBlock;
 }
 
@@ -308,11 +309,11 @@ void register_shared(Ctx& c, Fn& f) {
     HIPX(hipEventSynchronize(R.ev[ch.slot]));  // e.g. a progressive reload still reading the slot
     ring_reserve(c, ch.slot, ch.nblk);
     const Src& src = f.srcs[ch.blob];
-    // device chunks are fingerprinted one after another on one stream, so
-    // the first chunk's fingerprints arrive first instead of all at once
-    // (they only share HBM bandwidth); staged chunks keep their slot's stream
-    // for the host-to-device copies
-    hipStream_t s = src.dev ? c.streams[0] : stream_of(ch.slot);
+    // device chunks are fingerprinted on the control stream, one after
+    // another and after the previous registration's COPY: the HBM-bound
+    // kernels run one at a time at full bandwidth instead of sharing it;
+    // staged chunks keep their slot's stream for the host-to-device copies
+    hipStream_t s = src.dev ? c.ctl : stream_of(ch.slot);
     if (src.dev) {
       ch.data = src.p + ch.off;
     } else {
@@ -670,19 +671,21 @@ void reload_classes(Ctx& c, Fn& f, const std::vector<uint32_t>& missing_in) {
   // failure takes them out again, so that no later setup reads them
   try {
     // where each class comes from: 0 device source, 1 host cache (pinned,
-    // whole blocks), 2 registered host source (through pinned staging)
+    // whole blocks), 2 registered pageable host source (through pinned
+    // staging), 3 registered pinned host source, a whole block (by DMA like
+    // the host cache; a short last block takes the staged way)
     std::vector<uint8_t> kind(n);
     std::vector<const uint8_t*> src(n);
     size_t n_host = 0, n_page = 0;
     for (size_t j = 0; j < n; j++) {
       const Class& k = P.cls[missing[j]];
-      bool dev = false;
+      bool dev = false, pinned = false;
       if (k.hbuf != kNone) {
         kind[j] = 1;
         src[j] = P.hbufs[k.hbuf].p + (uint64_t)k.hoff * kBlock;
       } else {
-        src[j] = f.block_src(first.at(missing[j]), &dev);
-        kind[j] = dev ? 0 : 2;
+        src[j] = f.block_src(first.at(missing[j]), &dev, &pinned);
+        kind[j] = dev ? 0 : pinned && k.len == kBlock ? 3 : 2;
       }
       n_host += kind[j] != 0;
       n_page += kind[j] == 2;
@@ -804,7 +807,7 @@ void reload_classes(Ctx& c, Fn& f, const std::vector<uint32_t>& missing_in) {
           };
           for (size_t q = bt.j0; q < bt.j1; q++) {
             if (!kind[q]) continue;
-            const uint8_t* from = kind[q] == 1 ? src[q] : pinned_at[q - bt.j0];
+            const uint8_t* from = kind[q] == 2 ? pinned_at[q - bt.j0] : src[q];
             if (!(run_n && from == run_src + run_n * kBlock && stage_at[q] == run_at + run_n)) {
               flush();
               run_src = from;

@@ -132,6 +132,36 @@ static void serve_loop(Ctx& c, Serve& S) {
         std::vector<Call> calls;
         uint32_t rows = 0;
         const Req* key = nullptr;
+        // Residency-aware order: the oldest admissible request leads the
+        // launch whatever it costs; the others join only while their
+        // function's read-only data is all resident, so one launch triggers
+        // at most one reload and a cold function's requests wait to be
+        // served together by one reload instead of each evicting the others'
+        // blocks (cache replacement with the processing order adjusted,
+        // section "Other Lessons Learned").
+        std::unordered_map<uint64_t, bool> warm;
+        uint64_t warm_epoch = c.pool.epoch;
+        auto is_warm = [&](uint64_t id) {
+          if (!c.cfg.share) return true;
+          if (warm_epoch != c.pool.epoch) {
+            warm.clear();
+            warm_epoch = c.pool.epoch;
+          }
+          auto it = warm.find(id);
+          if (it != warm.end()) return it->second;
+          const Fn& f = find_fn(c, id);
+          bool w = f.live > 0 || f.resident_epoch == c.pool.epoch;
+          if (!w) {
+            w = true;
+            for (uint32_t cl : f.distinct)
+              if (c.pool.cls[cl].slot == kNone) {
+                w = false;
+                break;
+              }
+          }
+          warm.emplace(id, w);
+          return w;
+        };
         for (auto it = pending.begin(); it != pending.end();) {
           Req& r = **it;
           bool drop = false;
@@ -140,7 +170,7 @@ static void serve_loop(Ctx& c, Serve& S) {
             r.st = SAGE_ENOTFOUND;
             r.err = "function " + std::to_string(r.fn) + " was unregistered while the request was queued";
             drop = true;
-          } else if (!key || (same_shape(c, *key, r) && rows + r.batch <= S.max_rows)) {
+          } else if (!key || (same_shape(c, *key, r) && rows + r.batch <= S.max_rows && is_warm(r.fn))) {
             const sage_status st = guard([&] { r.inv = setup_internal(c, r.fn, r.batch); });
             if (st == SAGE_OK) {
               r.t_setup = Clock::now();

@@ -123,3 +123,65 @@ def test_unregister_while_queued_fails_the_request(sage_ctx_factory, torch_cuda)
         S.sage_submit(ctx, f1, 3, x1, y1)
     assert e.value.status == S.SAGE_ESTATE
     S.fn_release(ctx, hold)
+
+
+def test_serving_width_4096_host_sources_vs_oracle(sage_ctx_factory, torch_cuda):
+    """Serving at width 4096 from pinned host sources with a pool of half the
+    unique bytes (every eviction reloads over the host link, reloads issued
+    without waiting): each request's output in the mix equals its solo
+    output bit for bit, and sampled outputs match the float64 oracle."""
+    from paper_2404_14691_amd import sage as S
+    W = 4096
+    layers = [2, 3, 1, 4]
+    blobs = synth.serving_blobs(layers, W, 0.2, seed=5)
+    ctx0 = sage_ctx_factory(pool_budget_bytes=1 << 30)
+    f0 = [S.fn_register(ctx0, S.mlp_desc(S.SAGE_MLP_BF16, l, W), [S.make_blob(b)]) for l, b in zip(layers, blobs)]
+    unique = S.sage_get_stats(ctx0)["unique_bytes"]
+    for f in f0:
+        S.fn_unregister(ctx0, f)
+    budget = unique // 2 // 65536 * 65536
+    assert budget >= max(layers) * W * W * 2           # the largest function still fits alone
+    ctx = sage_ctx_factory(pool_budget_bytes=budget, progressive=1)
+    srcs = []
+    for b in blobs:
+        a = S.pinned_array(ctx, b.shape, b.dtype)
+        a[:] = b
+        srcs.append(a)
+    fns = [S.fn_register(ctx, S.mlp_desc(S.SAGE_MLP_BF16, l, W), [S.make_blob(a)]) for l, a in zip(layers, srcs)]
+    rng = np.random.default_rng(5)
+    reqs = [(int(rng.integers(0, len(layers))), int(rng.integers(1, 9))) for _ in range(48)]
+    xs = [synth.bf16_inputs(b, W, 5, i) for i, (_, b) in enumerate(reqs)]
+    solo = []
+    for (f, b), x in zip(reqs, xs):
+        inv = S.fn_setup(ctx, fns[f], b)
+        y = np.zeros((b, W), dtype=np.float32)
+        S.fn_invoke(ctx, inv, x, y)
+        S.fn_release(ctx, inv)
+        solo.append(y)
+    ev0 = S.sage_get_stats(ctx)["evictions"]
+    S.sage_serve_start(ctx)
+    outs = [np.full((b, W), np.nan, dtype=np.float32) for _, b in reqs]
+    ids = []
+    for i, ((f, b), x) in enumerate(zip(reqs, xs)):
+        ids.append(S.sage_submit(ctx, fns[f], b, x, outs[i]))
+        if i % 5 == 2:
+            time.sleep(0.003)
+    infos = [S.sage_wait(ctx, r, 60000) for r in ids]
+    S.sage_serve_stop(ctx)
+    assert all(i["status"] == 0 for i in infos)
+    for y, o in zip(solo, outs):
+        assert np.array_equal(y, o)
+    st = S.sage_get_stats(ctx)
+    assert st["evictions"] > ev0 and st["refcount_sum"] == 0
+    picks = sorted(set(int(k) for k in rng.choice(len(reqs), 6, replace=False)))
+    wref = {}
+    for k in picks:
+        f, b = reqs[k]
+        if f not in wref:
+            wref[f] = OM.bf16_to_f64(blobs[f]).reshape(layers[f], W, W)
+        ref = OM.mlp_forward(OM.bf16_to_f64(xs[k]), wref[f])
+        assert OM.normwise_error(outs[k], ref) <= 2e-2, k
+    for f in fns:
+        S.fn_unregister(ctx, f)
+    for a in srcs:
+        S.sage_host_free(ctx, a.ctypes.data)
