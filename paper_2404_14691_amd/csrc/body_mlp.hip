@@ -717,13 +717,8 @@ extern "C" __global__ __launch_bounds__(256) void mlp_f32_layer(const GemmHdr* _
   const uint32_t t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const uint32_t K = la.K;
   const bool relu = la.flags & kRelu;
-  // the header and the first group record are independent loads: issued
-  // together, a one-group launch (the usual case at a few rows) reaches its
-  // block-table and row-table loads one round trip earlier
-  const GemmHdr h = *hdr;
-  const GemmGroup g0 = groups[0];
-  for (uint32_t tile = blockIdx.x; tile < h.total_tiles; tile += gridDim.x) {
-    const GemmGroup gr = h.n_groups == 1 ? g0 : groups[find_group(groups, h.n_groups, tile)];
+  for (uint32_t tile = blockIdx.x; tile < hdr->total_tiles; tile += gridDim.x) {
+    const GemmGroup gr = groups[find_group(groups, hdr->n_groups, tile)];
     const uint32_t n = (tile - gr.tile_start) * 8 + wave * 2;
     const uint64_t* wtab = reinterpret_cast<const uint64_t*>(gr.wtab);
     const uint64_t off0 = la.w_off + (uint64_t)n * K * 4, off1 = off0 + (uint64_t)K * 4;

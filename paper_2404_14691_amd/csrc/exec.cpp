@@ -314,7 +314,9 @@ int launch_mlp_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, int fl
   Module* mod = calls[0].inv->fn->mod;
   hipFunction_t kfn = mod->get(kname.c_str());
   hipFunction_t tfn = split ? mod->get(plan.tail->name) : nullptr;
-  const uint32_t grid = bf16 ? shape_grid(c, *ms) : (uint32_t)c.cus * 4;
+  // the FP32 layer: one workgroup per tile up to four per CU (grid-stride
+  // beyond), so that a few-row launch does not dispatch idle workgroups
+  const uint32_t grid = bf16 ? shape_grid(c, *ms) : std::max<uint32_t>(1, std::min<uint32_t>(tiles, c.cus * 4));
   const uint32_t threads = bf16 ? ms->threads : 256;
   const uint32_t tgrid = split ? shape_grid(c, *plan.tail) : 0, tthreads = split ? plan.tail->threads : 0;
   const GemmHdr* d_hdr = reinterpret_cast<const GemmHdr*>(d_meta);
@@ -348,7 +350,9 @@ int launch_mlp_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, int fl
   // a gated launch's span includes copy waits: it is not timed, nor captured
   const int tok = gated.empty() && !ext ? c.timer.start(tname, s, L) : -1;
   if (c.cfg.batch && gated.empty() && !ext) {
-    const GraphKey key{kname + (split ? std::string("+") + plan.tail->name : std::string()) + (tiles ? "" : "/tail"),
+    // the FP32 layer's grid follows its tile count: part of the key
+    const GraphKey key{kname + (split ? std::string("+") + plan.tail->name : std::string()) + (tiles ? "" : "/tail") +
+                           (bf16 ? std::string() : "/" + std::to_string(grid)),
                        L, W};
     auto it = F.graphs.find(key);
     if (it == F.graphs.end()) {

@@ -165,6 +165,60 @@ def test_f32_mlp_vs_oracle(sage_ctx_factory, torch_cuda):
         assert np.array_equal(a, b)
 
 
+def test_f32_scattered_block_table_same_bits(sage_ctx_factory, torch_cuda):
+    """FP32 weights read through a scattered block table: a second function
+    whose every other block repeats the first function's blocks points half
+    its table at the first function's slots.  Both functions alone, together
+    in one launch (two groups; rows staged back to back, or from separate
+    device buffers), with device and host I/O, and from private copies
+    (share=0) give the same bits, within tolerance of the float64 oracle."""
+    from paper_2404_14691_amd import sage as S
+    torch = torch_cuda
+    W, L = 512, 3
+    rng = np.random.default_rng(7)
+    w0 = (rng.standard_normal((L, W, W)) / np.sqrt(W)).astype(np.float32)
+    w1 = (rng.standard_normal((L, W, W)) / np.sqrt(W)).astype(np.float32)
+    per = 65536 // 4
+    f0, f1 = w0.reshape(-1, per), w1.reshape(-1, per)
+    f1[::2] = f0[::2]                               # shared blocks: f1's slots are not back to back
+    xs = [rng.standard_normal((b, W)).astype(np.float32) for b in (8, 5)]
+    outs = {}
+    for share in (1, 0):
+        ctx = sage_ctx_factory(share=share, pool_budget_bytes=64 << 20)
+        fns = [S.fn_register(ctx, S.mlp_desc(S.SAGE_MLP_F32, L, W), [S.make_blob(w)]) for w in (w0, w1)]
+        solo = []
+        for fn, x in zip(fns, xs):
+            inv = S.fn_setup(ctx, fn, len(x))
+            y = np.zeros((len(x), W), dtype=np.float32)
+            S.fn_invoke(ctx, inv, x, y)
+            dx = torch.from_numpy(x).cuda()
+            dy = torch.zeros((len(x), W), dtype=torch.float32, device="cuda")
+            torch.cuda.synchronize()
+            S.fn_invoke(ctx, inv, (dx.data_ptr(), dx.numel() * 4), (dy.data_ptr(), dy.numel() * 4),
+                        S.SAGE_IO_DEVICE_IN | S.SAGE_IO_DEVICE_OUT)
+            assert np.array_equal(dy.cpu().numpy(), y)
+            S.fn_release(ctx, inv)
+            solo.append(y)
+        invs = [S.fn_setup(ctx, fn, len(x)) for fn, x in zip(fns, xs)]
+        ys = [np.zeros((len(x), W), dtype=np.float32) for x in xs]
+        S.fn_invoke_batch(ctx, invs, xs, ys)
+        # device I/O from separate buffers: rows not back to back, read through the row tables
+        dxs = [torch.from_numpy(x).cuda() for x in xs]
+        dys = [torch.zeros((len(x), W), dtype=torch.float32, device="cuda") for x in xs]
+        torch.cuda.synchronize()
+        S.fn_invoke_batch(ctx, invs, [(t.data_ptr(), t.numel() * 4) for t in dxs],
+                          [(t.data_ptr(), t.numel() * 4) for t in dys], S.SAGE_IO_DEVICE_IN | S.SAGE_IO_DEVICE_OUT)
+        for inv in invs:
+            S.fn_release(ctx, inv)
+        for a, b, c in zip(solo, ys, dys):
+            assert np.array_equal(a, b) and np.array_equal(a, c.cpu().numpy())
+        outs[share] = solo
+    for a, b in zip(outs[1], outs[0]):
+        assert np.array_equal(a, b)
+    for w, x, y in zip((w0, w1), xs, outs[1]):
+        assert OM.normwise_error(y, OM.mlp_forward(x, w.astype(np.float64))) <= F32_TOL
+
+
 def test_f32_mlp_full_size_sixteen_invocations(sage_ctx_factory, torch_cuda):
     """2-layer FP32 MLP of width 2048, 16 sequential invocations of 8 rows,
     each with its own input: every output element vs the float64 oracle."""
