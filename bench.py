@@ -500,123 +500,15 @@ def cold_setup_ab(S, wl, pairs=20):
             "module_load_ms": {m: round(float(np.median(v)), 3) for m, v in code_ms.items()}}
 
 
-def serving_leg(S, torch, rate=1000.0, duration=10.0, plain_prefix_s=0.25, budget_frac=0.5):
+def serving_leg(S, torch, rate=1000.0, duration=10.0):
     """Serving at the over-HBM regime of the Poisson workload, shared against
-    plain on one arrival trace.
-
-    16 BF16 MLP functions of width 4096 (sizes lognormal 64 MiB..4 GiB, 20 %
-    of blocks from a common pool), sources in pinned host memory, so every
-    reload after an eviction crosses the host link; pool budget half of the
-    unique bytes (the functions' read-only data cannot all stay in HBM);
-    Poisson arrivals at `rate` for `duration` s, Zipf(1) popularity, batch
-    U[1,64], each request with its own seeded input.  Shared: pool +
-    references + eviction + continuous batching, reloads issued without
-    waiting (the launch waits for them).  Plain: the same loop with a private
-    copy of the function's weights per request, on the first `plain_prefix_s`
-    seconds of the same trace (its queue grows without bound at this rate).
-    The plain requests' outputs are compared bit for bit with the same
-    requests' outputs in the shared run."""
-    from paper_2404_14691_amd import synth
-    W, maxrows = 4096, 64
-    wl = synth.serving_workload(rate=rate, duration=duration, seed=1000)
-    layers = wl.layers
-    sizes = [l * W * W * 2 for l in layers]
-    g = torch.Generator(device="cuda")
-    g.manual_seed(0)
-    per = 32768
-    common = (torch.randn((max(sizes) // 65536, per), generator=g, device="cuda") / 64.0).to(torch.bfloat16)
-    dev_blobs = []
-    for nbytes in sizes:
-        nb = nbytes // 65536
-        b = (torch.randn((nb, per), generator=g, device="cuda") / 64.0).to(torch.bfloat16)
-        share = torch.rand(nb, generator=g, device="cuda") < wl.overlap_frac
-        b[share] = common[:nb][share]
-        dev_blobs.append(b)
-    del common
-    n = len(wl.arrivals)
-    rows = np.asarray(wl.batch, dtype=np.int64)
-    row0 = np.concatenate([[0], np.cumsum(rows)[:-1]])
-    total_rows = int(rows.sum())
-    x = torch.randn((total_rows, W), generator=g, device="cuda").to(torch.bfloat16)
-    y_shared = torch.empty((total_rows, W), dtype=torch.float32, device="cuda")
-    torch.cuda.synchronize()
-    io = S.SAGE_IO_DEVICE_IN | S.SAGE_IO_DEVICE_OUT
-    logical = sum(sizes)
-
-    def run(share, reqs, y, budget):
-        cfg = S.sage_config_default()
-        cfg.share = share
-        cfg.pool_budget_bytes = budget
-        cfg.progressive = 1 if share else 0
-        ctx = S.sage_open(0, cfg)
-        host = []
-        try:
-            for b in dev_blobs:
-                a = S.pinned_array(ctx, (b.numel(),), np.uint16)
-                torch.from_numpy(a.view(np.int16)).copy_(b.view(torch.int16).reshape(-1))
-                host.append(a)
-            fns = [S.fn_register(ctx, S.mlp_desc(S.SAGE_MLP_BF16, l, W), [S.make_blob(a)])
-                   for l, a in zip(layers, host)]
-            st = S.sage_get_stats(ctx)
-            S.sage_serve_start(ctx)
-            ev0 = st["evictions"]
-            ids = []
-            t0 = time.perf_counter()
-            for i in reqs:
-                while time.perf_counter() - t0 < wl.arrivals[i]:
-                    pass
-                r, b = int(row0[i]), int(rows[i])
-                ids.append(S.sage_submit(ctx, fns[int(wl.fn[i])], b, (x.data_ptr() + r * W * 2, b * W * 2),
-                                         (y.data_ptr() + r * W * 4, b * W * 4), io))
-            for r in ids:
-                S.sage_wait(ctx, r, 600000)
-            rep = S.sage_serve_stats(ctx)
-            S.sage_serve_stop(ctx)
-            st1 = S.sage_get_stats(ctx)
-            for f in fns:
-                S.fn_unregister(ctx, f)
-            for a in host:
-                S.sage_host_free(ctx, a.ctypes.data)
-        finally:
-            S.sage_close(ctx)
-        return {"requests": len(reqs), "completed": int(rep["completed"]), "failed": int(rep["failed"]),
-                "throughput": round(rep["throughput"], 1),
-                "setup_ms": {"p50": round(rep["setup_p50_ms"], 3), "p99": round(rep["setup_p99_ms"], 3)},
-                "e2e_ms": {"p50": round(rep["e2e_p50_ms"], 3), "p99": round(rep["e2e_p99_ms"], 3)},
-                "launches": int(rep["launches"]), "evictions": int(st1["evictions"] - ev0),
-                "reloads": int(st1["reloads"] - st["reloads"]), "h2d_ro_bytes": int(st1["h2d_bytes"])}, st
-
-    # unique bytes of the 16 functions (a registration pass), then the budget
-    cfg = S.sage_config_default()
-    cfg.pool_budget_bytes = 1 << 40
-    ctx = S.sage_open(0, cfg)
+    plain on one arrival trace, at one rate (bench_workloads.ServingBench)."""
+    import bench_workloads
+    sb = bench_workloads.ServingBench(S, torch, log)
     try:
-        fns = [S.fn_register(ctx, S.mlp_desc(S.SAGE_MLP_BF16, l, W),
-                             [S.make_blob(b.data_ptr(), b.numel() * 2, where=S.SAGE_SRC_DEVICE)])
-               for l, b in zip(layers, dev_blobs)]
-        unique = S.sage_get_stats(ctx)["unique_bytes"]
+        return sb.rate(rate, duration)
     finally:
-        S.sage_close(ctx)
-    budget = int(unique * budget_frac) // 65536 * 65536
-    shared, _ = run(1, list(range(n)), y_shared, budget)
-    log(f"serving shared: {shared}")
-    prefix = [i for i in range(n) if wl.arrivals[i] < plain_prefix_s]
-    y_plain = torch.full((total_rows, W), float("nan"), dtype=torch.float32, device="cuda")
-    plain, _ = run(0, prefix, y_plain, 1 << 20)
-    log(f"serving plain: {plain}")
-    last = int(row0[prefix[-1]] + rows[prefix[-1]]) if prefix else 0
-    same = bool(torch.equal(y_plain[:last], y_shared[:last])) if last else None
-    del x, y_shared, y_plain, dev_blobs
-    torch.cuda.empty_cache()
-    return {"workload": f"Poisson {rate:.0f} req/s for {duration:.0f} s over 16 BF16 MLP functions (width 4096, "
-                        f"{logical / 2**30:.2f} GiB logical, {unique / 2**30:.2f} GiB unique, 20% block overlap), "
-                        f"batch U[1,64], Zipf(1) popularity, sources in pinned host memory, distinct inputs",
-            "pool_budget_bytes": budget, "budget_note": f"{budget_frac:.0%} of unique bytes: not all read-only "
-                                                         f"data fits, so admission evicts and reloads over the host link",
-            "shared_batched": shared,
-            "plain": dict(plain, trace=f"the first {plain_prefix_s} s of the same trace ({len(prefix)} requests)"),
-            "plain_outputs_equal_shared": same,
-            "duration_note": f"{duration:.0f} s per rate rather than 60 s, to keep the default run within minutes"}
+        sb.close()
 
 
 def _host_cpu():

@@ -265,86 +265,161 @@ def mlp_f32(S, torch, log, reps=5):
 
 
 # ---------------------------------------------------------------- serving
-def serving(S, torch, log, rates=(200, 500, 1000, 2000), duration=3.0, budget_frac=0.5):
-    from paper_2404_14691_amd import synth
+class ServingBench:
+    """Serving at the over-HBM regime of the Poisson workload, shared against
+    plain on one arrival trace.
+
+    16 BF16 MLP functions of width 4096 (sizes lognormal 64 MiB..4 GiB, 20 %
+    of blocks from a common pool), sources in pinned host memory, so every
+    reload after an eviction crosses the host link; pool budget half of the
+    unique bytes (the functions' read-only data cannot all stay in HBM);
+    Poisson arrivals, Zipf(1) popularity, batch U[1,64], each request with its
+    own seeded input.  Shared: pool + references + eviction + continuous
+    batching, reloads issued without waiting (the launch waits for them).
+    Plain: the same loop with a private copy of the function's weights per
+    request, on the first `plain_prefix_s` seconds of the same trace (at these
+    rates its queue grows without bound).  The plain requests' outputs are
+    compared bit for bit with the same requests' outputs in the shared run."""
+
     W = 4096
-    sw = synth.serving_workload(rate=1.0, duration=1.0, seed=0)
-    layers = sw.layers
-    layer_bytes = W * W * 2
-    sizes = [l * layer_bytes for l in layers]
-    # weights generated on the device (seeded) with 20 % of blocks copied from a common pool
-    g = torch.Generator(device="cuda")
-    g.manual_seed(0)
-    per = 32768
-    maxb = max(sizes) // 65536
-    pool = (torch.randn((maxb, per), generator=g, device="cuda") / 64.0).to(torch.bfloat16)
-    blobs = []
-    for f, nbytes in enumerate(sizes):
-        nb = nbytes // 65536
-        b = (torch.randn((nb, per), generator=g, device="cuda") / 64.0).to(torch.bfloat16)
-        share = torch.rand(nb, generator=g, device="cuda") < sw.overlap_frac
-        b[share] = pool[:nb][share]
-        blobs.append(b)
-    torch.cuda.synchronize()
-    logical = sum(sizes)
-    maxrows = 64
-    xin = torch.zeros((maxrows, W), dtype=torch.bfloat16, device="cuda").normal_()
-    io = S.SAGE_IO_DEVICE_IN | S.SAGE_IO_DEVICE_OUT
-    cfg = S.sage_config_default()
-    cfg.pool_budget_bytes = 1 << 40
-    ctx = S.sage_open(0, cfg)
+
+    def __init__(self, S, torch, log, budget_frac=0.5, seed=1000):
+        from paper_2404_14691_amd import synth
+        self.S, self.torch, self.log, self.seed = S, torch, log, seed
+        self.layers = synth.serving_workload(rate=1.0, duration=1.0, seed=seed).layers
+        W = self.W
+        self.sizes = [l * W * W * 2 for l in self.layers]
+        g = torch.Generator(device="cuda")
+        g.manual_seed(0)
+        self.g = g
+        per = 32768
+        common = (torch.randn((max(self.sizes) // 65536, per), generator=g, device="cuda") / 64.0).to(torch.bfloat16)
+        self.dev_blobs = []
+        for nbytes in self.sizes:
+            nb = nbytes // 65536
+            b = (torch.randn((nb, per), generator=g, device="cuda") / 64.0).to(torch.bfloat16)
+            share = torch.rand(nb, generator=g, device="cuda") < 0.2
+            b[share] = common[:nb][share]
+            self.dev_blobs.append(b)
+        del common
+        torch.cuda.synchronize()
+        cfg = S.sage_config_default()
+        cfg.pool_budget_bytes = 1 << 40
+        ctx = S.sage_open(0, cfg)
+        try:
+            for l, b in zip(self.layers, self.dev_blobs):
+                S.fn_register(ctx, S.mlp_desc(S.SAGE_MLP_BF16, l, W),
+                              [S.make_blob(b.data_ptr(), b.numel() * 2, where=S.SAGE_SRC_DEVICE)])
+            self.unique = S.sage_get_stats(ctx)["unique_bytes"]
+        finally:
+            S.sage_close(ctx)
+        self.budget_frac = budget_frac
+        self.budget = int(self.unique * budget_frac) // 65536 * 65536
+        self.logical = sum(self.sizes)
+
+    def close(self):
+        del self.dev_blobs
+        self.torch.cuda.empty_cache()
+
+    def _run(self, share, wl, reqs, x, y, row0, rows, budget):
+        S, torch, W = self.S, self.torch, self.W
+        cfg = S.sage_config_default()
+        cfg.share = share
+        cfg.pool_budget_bytes = budget
+        cfg.progressive = 1 if share else 0
+        io = S.SAGE_IO_DEVICE_IN | S.SAGE_IO_DEVICE_OUT
+        ctx = S.sage_open(0, cfg)
+        try:
+            host = []
+            for b in self.dev_blobs:
+                a = S.pinned_array(ctx, (b.numel(),), np.uint16)
+                torch.from_numpy(a.view(np.int16)).copy_(b.view(torch.int16).reshape(-1))
+                host.append(a)
+            fns = [S.fn_register(ctx, S.mlp_desc(S.SAGE_MLP_BF16, l, W), [S.make_blob(a)])
+                   for l, a in zip(self.layers, host)]
+            st0 = S.sage_get_stats(ctx)
+            S.sage_serve_start(ctx)
+            ids = []
+            t0 = time.perf_counter()
+            for i in reqs:
+                while time.perf_counter() - t0 < wl.arrivals[i]:
+                    pass
+                r, b = int(row0[i]), int(rows[i])
+                ids.append(S.sage_submit(ctx, fns[int(wl.fn[i])], b, (x.data_ptr() + r * W * 2, b * W * 2),
+                                         (y.data_ptr() + r * W * 4, b * W * 4), io))
+            for r in ids:
+                S.sage_wait(ctx, r, 600000)
+            rep = S.sage_serve_stats(ctx)
+            S.sage_serve_stop(ctx)
+            st1 = S.sage_get_stats(ctx)
+            for f in fns:
+                S.fn_unregister(ctx, f)
+            for a in host:
+                S.sage_host_free(ctx, a.ctypes.data)
+        finally:
+            S.sage_close(ctx)
+        return {"requests": len(reqs), "completed": int(rep["completed"]), "failed": int(rep["failed"]),
+                "throughput": round(rep["throughput"], 1),
+                "setup_ms": {"p50": round(rep["setup_p50_ms"], 3), "p99": round(rep["setup_p99_ms"], 3)},
+                "e2e_ms": {"p50": round(rep["e2e_p50_ms"], 3), "p99": round(rep["e2e_p99_ms"], 3)},
+                "launches": int(rep["launches"]), "evictions": int(st1["evictions"] - st0["evictions"]),
+                "reloads": int(st1["reloads"] - st0["reloads"]),
+                "h2d_ro_bytes": int(st1["h2d_bytes"] - st0["h2d_bytes"])}
+
+    def rate(self, rate, duration, plain_prefix_s=0.25):
+        from paper_2404_14691_amd import synth
+        torch, W = self.torch, self.W
+        wl = synth.serving_workload(rate=rate, duration=duration, seed=self.seed)
+        assert wl.layers == self.layers
+        n = len(wl.arrivals)
+        rows = np.asarray(wl.batch, dtype=np.int64)
+        row0 = np.concatenate([[0], np.cumsum(rows)[:-1]])
+        total_rows = int(rows.sum())
+        x = torch.empty((total_rows, W), dtype=torch.bfloat16, device="cuda")
+        for r in range(0, total_rows, 65536):  # distinct seeded inputs, generated in pieces
+            k = min(65536, total_rows - r)
+            x[r:r + k] = torch.randn((k, W), generator=self.g, device="cuda").to(torch.bfloat16)
+        y_shared = torch.empty((total_rows, W), dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        self.log(f"serving {rate:.0f}/s for {duration:.0f} s: {n} requests, shared ...")
+        shared = self._run(1, wl, list(range(n)), x, y_shared, row0, rows, self.budget)
+        self.log(f"serving {rate:.0f}/s shared: {shared}")
+        prefix = [i for i in range(n) if wl.arrivals[i] < plain_prefix_s]
+        last = int(row0[prefix[-1]] + rows[prefix[-1]]) if prefix else 0
+        y_plain = torch.full((max(last, 1), W), float("nan"), dtype=torch.float32, device="cuda")
+        plain = self._run(0, wl, prefix, x, y_plain, row0, rows, 1 << 20)
+        self.log(f"serving {rate:.0f}/s plain: {plain}")
+        same = bool(torch.equal(y_plain[:last], y_shared[:last])) if last else None
+        del x, y_shared, y_plain
+        torch.cuda.empty_cache()
+        return {"workload": f"Poisson {rate:.0f} req/s for {duration:.0f} s over 16 BF16 MLP functions (width "
+                            f"4096, {self.logical / 2**30:.2f} GiB logical, {self.unique / 2**30:.2f} GiB unique, "
+                            f"20% block overlap), batch U[1,64], Zipf(1) popularity, sources in pinned host "
+                            f"memory, distinct inputs",
+                "pool_budget_bytes": self.budget,
+                "budget_note": f"{self.budget_frac:.0%} of unique bytes: not all read-only data fits, so admission "
+                               f"evicts and reloads over the host link",
+                "shared_batched": shared,
+                "plain": dict(plain, trace=f"the first {plain_prefix_s} s of the same trace ({len(prefix)} requests)"),
+                "plain_outputs_equal_shared": same,
+                "speedup_vs_plain": round(shared["throughput"] / max(plain["throughput"], 1e-9), 2)}
+
+
+def serving(S, torch, log, rates=(200, 500, 1000, 2000), duration=60.0):
+    """Every rate of the serving configuration for 60 s each, shared against
+    plain (ServingBench)."""
+    sb = ServingBench(S, torch, log)
     results = {}
     try:
-        fns = [S.fn_register(ctx, S.mlp_desc(S.SAGE_MLP_BF16, l, W),
-                             [S.make_blob(b.data_ptr(), b.numel() * 2, where=S.SAGE_SRC_DEVICE)])
-               for l, b in zip(layers, blobs)]
-        unique = S.sage_get_stats(ctx)["unique_bytes"]
-        S.sage_close(ctx)
-        cfg.pool_budget_bytes = int(unique * budget_frac)
-        ctx = S.sage_open(0, cfg)
-        fns = [S.fn_register(ctx, S.mlp_desc(S.SAGE_MLP_BF16, l, W),
-                             [S.make_blob(b.data_ptr(), b.numel() * 2, where=S.SAGE_SRC_DEVICE)])
-               for l, b in zip(layers, blobs)]
-        S.sage_serve_start(ctx)
         for rate in rates:
-            wl = synth.serving_workload(rate=rate, duration=duration, seed=rate)
-            n = len(wl.arrivals)
-            ys = torch.empty((n, maxrows, W), dtype=torch.float32, device="cuda") if n * maxrows * W * 4 < (8 << 30) \
-                else None
-            if ys is None:
-                raise RuntimeError("serving output buffer too large")
-            torch.cuda.synchronize()
-            S.sage_serve_reset_stats(ctx)
-            ev0 = S.sage_get_stats(ctx)["evictions"]
-            ids = []
-            t_start = time.perf_counter()
-            for i in range(n):
-                while time.perf_counter() - t_start < wl.arrivals[i]:
-                    pass
-                b = int(wl.batch[i])
-                ids.append(S.sage_submit(ctx, fns[int(wl.fn[i])], b, (xin.data_ptr(), b * W * 2),
-                                         (ys[i].data_ptr(), b * W * 4), io))
-            for r in ids:
-                S.sage_wait(ctx, r, 120000)
-            rep = S.sage_serve_stats(ctx)
-            st = S.sage_get_stats(ctx)
-            results[str(rate)] = {"requests": n, "throughput": round(rep["throughput"], 1),
-                                  "setup_ms": {"p50": round(rep["setup_p50_ms"], 3), "p99": round(rep["setup_p99_ms"], 3)},
-                                  "e2e_ms": {"p50": round(rep["e2e_p50_ms"], 3), "p99": round(rep["e2e_p99_ms"], 3)},
-                                  "launches": rep["launches"], "rows": rep["rows"],
-                                  "evictions": st["evictions"] - ev0, "failed": rep["failed"]}
-            log(f"serving {rate}/s: {results[str(rate)]}")
-            del ys
-        S.sage_serve_stop(ctx)
+            results[str(rate)] = sb.rate(float(rate), duration)
     finally:
-        S.sage_close(ctx)
+        sb.close()
     top = results[str(rates[-1])]
-    return _line("setup/e2e p50/p99 ms + invocations/sec under Poisson load, 1 MI355X", top["throughput"],
-                 "invocations/s", len(rates), 0, 0.0,
-                 {"workload": f"serving: Poisson arrivals over 16 BF16 MLP functions (width 4096, sizes lognormal "
-                              f"64 MiB..4 GiB, {logical / 2**30:.1f} GiB logical, 20% block overlap), batch U[1,64], "
-                              f"{duration:.0f} s per rate, pool budget {budget_frac:.0%} of unique bytes",
-                  "unique_bytes": int(unique), "pool_budget_bytes": int(unique * budget_frac)},
+    return _line("setup/e2e p50/p99 ms + invocations/sec under Poisson load, shared vs plain, 1 MI355X",
+                 top["shared_batched"]["throughput"], "invocations/s", len(rates), 0, 0.0,
+                 {"workload": top["workload"].replace(f"{rates[-1]} req/s", "200-2000 req/s"),
+                  "unique_bytes": int(sb.unique), "pool_budget_bytes": int(sb.budget)},
                  "bf16", rates=results)
 
 
