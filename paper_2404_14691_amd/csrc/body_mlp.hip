@@ -708,10 +708,14 @@ SAGE_GGEMM6(ggemm6_bf16_256x128, 256, 128, 64, 64, 4, false)
 constexpr uint32_t kF32KC = 2048;                       // K per chunk
 typedef __attribute__((address_space(1))) const f32x4 g_f32x4;
 
-extern "C" __global__ __launch_bounds__(256) void mlp_f32_layer(const GemmHdr* __restrict__ hdr,
-                                                                const GemmGroup* __restrict__ groups,
-                                                                LayerArgs la) {
-  __shared__ __attribute__((aligned(16))) float xs[8][kF32KC];
+// CPW output columns per wave (4 CPW per workgroup): 2 gives fewer
+// workgroups that each read the 8 input rows once for 8 columns, 1 twice as
+// many workgroups (two per CU at 8 rows of width 2048) with half the weight
+// rows each.  The K order of a column is the same in both.
+template <int CPW>
+__device__ __forceinline__ void mlp_f32_body(const GemmHdr* __restrict__ hdr, const GemmGroup* __restrict__ groups,
+                                             const LayerArgs& la, float (*xs)[kF32KC]) {
+  static_assert(CPW == 1 || CPW == 2, "one or two columns per wave");
   constexpr int WPL = kF32KC / 256;                     // float4 per lane per weight row per chunk
   constexpr int XPR = kF32KC / 4 / 256;                 // float4 per thread per staged row per chunk
   const uint32_t t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -719,11 +723,12 @@ extern "C" __global__ __launch_bounds__(256) void mlp_f32_layer(const GemmHdr* _
   const bool relu = la.flags & kRelu;
   for (uint32_t tile = blockIdx.x; tile < hdr->total_tiles; tile += gridDim.x) {
     const GemmGroup gr = groups[find_group(groups, hdr->n_groups, tile)];
-    const uint32_t n = (tile - gr.tile_start) * 8 + wave * 2;
+    const uint32_t n = (tile - gr.tile_start) * (4 * CPW) + wave * CPW;
     const uint64_t* wtab = reinterpret_cast<const uint64_t*>(gr.wtab);
     const uint64_t off0 = la.w_off + (uint64_t)n * K * 4, off1 = off0 + (uint64_t)K * 4;
     const float* w0 = reinterpret_cast<const float*>(wtab[off0 >> kBlockShift] + (off0 & (kBlock - 1)));
-    const float* w1 = reinterpret_cast<const float*>(wtab[off1 >> kBlockShift] + (off1 & (kBlock - 1)));
+    // (with one column per wave there is no second row: off1 would be past the blob for the last column)
+    const float* w1 = CPW == 2 ? reinterpret_cast<const float*>(wtab[off1 >> kBlockShift] + (off1 & (kBlock - 1))) : w0;
     for (uint32_t r0 = 0; r0 < gr.m; r0 += 8) {
       const uint32_t nr = gr.m - r0 < 8 ? gr.m - r0 : 8;
       // the rows' addresses once per row block; loads are not branched
@@ -748,7 +753,7 @@ extern "C" __global__ __launch_bounds__(256) void mlp_f32_layer(const GemmHdr* _
         for (int j = 0; j < WPL; j++) {
           const uint32_t k = 4 * lane + 256 * j < kn ? 4 * lane + 256 * j : kn - 4;
           wa[j] = *(g_f32x4*)(uintptr_t)(w0 + kc + k);
-          wb[j] = *(g_f32x4*)(uintptr_t)(w1 + kc + k);
+          if constexpr (CPW == 2) wb[j] = *(g_f32x4*)(uintptr_t)(w1 + kc + k);
         }
         // rows r0 .. r0 + nr - 1, columns kc .. kc + kn - 1: float4 q = t + 256 m of each row
         const uint32_t q4 = kn / 4;
@@ -779,10 +784,12 @@ extern "C" __global__ __launch_bounds__(256) void mlp_f32_layer(const GemmHdr* _
                 acc0[i] = fmaf(a.y, wa[j].y, acc0[i]);
                 acc0[i] = fmaf(a.z, wa[j].z, acc0[i]);
                 acc0[i] = fmaf(a.w, wa[j].w, acc0[i]);
-                acc1[i] = fmaf(a.x, wb[j].x, acc1[i]);
-                acc1[i] = fmaf(a.y, wb[j].y, acc1[i]);
-                acc1[i] = fmaf(a.z, wb[j].z, acc1[i]);
-                acc1[i] = fmaf(a.w, wb[j].w, acc1[i]);
+                if constexpr (CPW == 2) {
+                  acc1[i] = fmaf(a.x, wb[j].x, acc1[i]);
+                  acc1[i] = fmaf(a.y, wb[j].y, acc1[i]);
+                  acc1[i] = fmaf(a.z, wb[j].z, acc1[i]);
+                  acc1[i] = fmaf(a.w, wb[j].w, acc1[i]);
+                }
               }
             }
           }
@@ -794,7 +801,7 @@ extern "C" __global__ __launch_bounds__(256) void mlp_f32_layer(const GemmHdr* _
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
           acc0[i] += __shfl_xor(acc0[i], o, 64);
-          acc1[i] += __shfl_xor(acc1[i], o, 64);
+          if constexpr (CPW == 2) acc1[i] += __shfl_xor(acc1[i], o, 64);
         }
       }
       if (lane == 0) {
@@ -806,9 +813,23 @@ extern "C" __global__ __launch_bounds__(256) void mlp_f32_layer(const GemmHdr* _
             v1 = v1 > 0.f ? v1 : 0.f;
           }
           crow[n] = v0;
-          crow[n + 1] = v1;
+          if constexpr (CPW == 2) crow[n + 1] = v1;
         }
       }
     }
   }
+}
+
+extern "C" __global__ __launch_bounds__(256) void mlp_f32_layer(const GemmHdr* __restrict__ hdr,
+                                                                const GemmGroup* __restrict__ groups,
+                                                                LayerArgs la) {
+  __shared__ __attribute__((aligned(16))) float xs[8][kF32KC];
+  mlp_f32_body<2>(hdr, groups, la, xs);
+}
+
+extern "C" __global__ __launch_bounds__(256) void mlp_f32_layer_c4(const GemmHdr* __restrict__ hdr,
+                                                                   const GemmGroup* __restrict__ groups,
+                                                                   LayerArgs la) {
+  __shared__ __attribute__((aligned(16))) float xs[8][kF32KC];
+  mlp_f32_body<1>(hdr, groups, la, xs);
 }

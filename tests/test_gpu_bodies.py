@@ -309,3 +309,32 @@ def test_relax_rejects_read_only_blobs(sage_ctx_factory, torch_cuda):
         S.fn_register(ctx, S.relax_desc(8, 4, 4, 1, 0.5), [S.make_blob(blob)])
     with pytest.raises(S.SageError):
         S.fn_register(ctx, S.relax_desc(6, 4, 4, 1, 0.5), [])  # nx not a multiple of 4
+
+
+def test_f32_four_and_eight_columns_per_workgroup_same_bits(sage_ctx_factory, torch_cuda, monkeypatch):
+    """The FP32 layer with one column per wave (SAGE_F32_COLS=4) walks each
+    column's K in the same order as with two: the same bits, one group and
+    two groups (the last column of the last layer included)."""
+    from paper_2404_14691_amd import sage as S
+    W, L = 1024, 2
+    rng = np.random.default_rng(8)
+    ws = [(rng.standard_normal((L, W, W)) / np.sqrt(W)).astype(np.float32) for _ in range(2)]
+    xs = [rng.standard_normal((b, W)).astype(np.float32) for b in (8, 11)]
+    outs = {}
+    for cols in ("8", "4"):
+        monkeypatch.setenv("SAGE_F32_COLS", cols)
+        ctx = sage_ctx_factory(pool_budget_bytes=64 << 20)
+        fns = [S.fn_register(ctx, S.mlp_desc(S.SAGE_MLP_F32, L, W), [S.make_blob(w)]) for w in ws]
+        invs = [S.fn_setup(ctx, f, len(x)) for f, x in zip(fns, xs)]
+        ys = [np.zeros((len(x), W), dtype=np.float32) for x in xs]
+        S.fn_invoke_batch(ctx, invs, xs, ys)
+        solo = np.zeros((len(xs[0]), W), dtype=np.float32)
+        S.fn_invoke(ctx, invs[0], xs[0], solo)
+        for inv in invs:
+            S.fn_release(ctx, inv)
+        assert np.array_equal(solo, ys[0])
+        outs[cols] = ys
+    for a, b in zip(outs["8"], outs["4"]):
+        assert np.array_equal(a, b)
+    for w, x, y in zip(ws, xs, outs["4"]):
+        assert OM.normwise_error(y, OM.mlp_forward(x, w.astype(np.float64))) <= F32_TOL
