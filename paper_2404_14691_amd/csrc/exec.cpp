@@ -379,8 +379,11 @@ int launch_mlp_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, int fl
 
 // ------------------------------------------------------------ stencil group
 // All calls share one coefficient table.  Every field of every call is
-// swept together; the sweep's output goes to the call's output buffer on
-// the last sweep and alternates with a scratch field before it.
+// swept together.  The sweeps run as passes of two (stencil7_fused2: u0 read
+// and u2 written once per two sweeps), after one single sweep
+// (stencil7_sweep2) when their number is odd; a pass's output goes to the
+// call's output buffer on the last pass and alternates with a scratch field
+// before it.
 int launch_stencil_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, int flight) {
   const sage_fn_desc& d = calls[0].inv->fn->d;
   const uint64_t cells = (uint64_t)d.nx * d.ny * d.nz, fbytes = cells * 4;
@@ -396,6 +399,14 @@ int launch_stencil_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, in
   bool fed = false;
   for (const Call& cl : calls) fed = fed || reload_feeds(c, *cl.inv->fn);
   if (fed) HIPX(hipStreamWaitEvent(s, c.reload_done, 0));
+  std::vector<uint32_t> pass;  // sweeps per pass
+  if (c.stencil_fuse) {
+    if (S % 2) pass.push_back(1);
+    for (uint32_t i = 0; i < S / 2; i++) pass.push_back(2);
+  } else {
+    pass.assign(S, 1);
+  }
+  const uint32_t P = (uint32_t)pass.size();
   // the flight's captured MLP graphs hold the meta buffer's address and row
   // capacity: a move makes them stale
   if (ensure(&F.d_meta, &F.h_meta, &F.meta_cap, (size_t)std::max<uint32_t>(S, 1) * 2 * nf * 8)) drop_graphs(F);
@@ -422,11 +433,12 @@ int launch_stencil_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, in
       const uint8_t* fin = in + b * fbytes;
       uint8_t* fout = out + b * fbytes;
       uint8_t* scratch = (uint8_t*)v.ws + b * fbytes;
-      for (uint32_t sw = 1; sw <= S; sw++) {
-        const uint8_t* r = sw == 1 ? fin : (((S - (sw - 1)) % 2 == 0) ? fout : scratch);
-        uint8_t* w = ((S - sw) % 2 == 0) ? fout : scratch;
-        tab[(size_t)(sw - 1) * 2 * nf + fidx] = (uint64_t)r;
-        tab[(size_t)(sw - 1) * 2 * nf + nf + fidx] = (uint64_t)w;
+      const uint8_t* r = fin;
+      for (uint32_t k = 0; k < P; k++) {
+        uint8_t* w = ((P - 1 - k) % 2 == 0) ? fout : scratch;
+        tab[(size_t)k * 2 * nf + fidx] = (uint64_t)r;
+        tab[(size_t)k * 2 * nf + nf + fidx] = (uint64_t)w;
+        r = w;
       }
       io_fields.push_back({fin, fout});
       fidx++;
@@ -437,27 +449,32 @@ int launch_stencil_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, in
   if (S == 0) {
     for (auto& p : io_fields) HIPX(hipMemcpyAsync(p.second, p.first, fbytes, hipMemcpyDeviceToDevice, s));
   } else {
-    HIPX(hipMemcpyAsync(F.d_meta, F.h_meta, (size_t)S * 2 * nf * 8, hipMemcpyHostToDevice, s));
-    StencilArgs sa{};
-    sa.ctab = ctab;
-    sa.coef = d.coef;
-    sa.nx = d.nx;
-    sa.ny = d.ny;
-    sa.nz = d.nz;
-    sa.n_fields = nf;
-    sa.tiles_x = (d.nx + kStencil2TX - 1) / kStencil2TX;
-    sa.tiles_y = (d.ny + kStencil2TY - 1) / kStencil2TY;
-    sa.tiles_z = (d.nz + kStencil2TZ - 1) / kStencil2TZ;
-    sa.spatial_tiles = sa.tiles_x * sa.tiles_y * sa.tiles_z;
-    const uint64_t groups = (uint64_t)((sa.spatial_tiles + 7) / 8) * 8 * nf;
-    if (groups > 0x7FFFFFFFull) fail(SAGE_EINVAL, "stencil launch too large");
-    hipFunction_t k = calls[0].inv->fn->mod->get("stencil7_sweep2");
+    HIPX(hipMemcpyAsync(F.d_meta, F.h_meta, (size_t)P * 2 * nf * 8, hipMemcpyHostToDevice, s));
+    Module* mod = calls[0].inv->fn->mod;
+    hipFunction_t k1 = mod->get("stencil7_sweep2");
+    hipFunction_t k2 = mod->get("stencil7_fused2");
+    // the timer counts sweeps: a pass of two is two units of its time
     const int tok = c.timer.start("stencil7", s, S);
-    for (uint32_t sw = 0; sw < S; sw++) {
-      sa.src = reinterpret_cast<const uint64_t*>(F.d_meta) + (size_t)sw * 2 * nf;
+    for (uint32_t k = 0; k < P; k++) {
+      const bool fused = pass[k] == 2;
+      StencilArgs sa{};
+      sa.ctab = ctab;
+      sa.coef = d.coef;
+      sa.nx = d.nx;
+      sa.ny = d.ny;
+      sa.nz = d.nz;
+      sa.n_fields = nf;
+      sa.tiles_x = (d.nx + kStencil2TX - 1) / kStencil2TX;
+      const uint32_t rows = fused ? kStencil2TY - 2 : kStencil2TY;  // output rows per tile
+      sa.tiles_y = (d.ny + rows - 1) / rows;
+      sa.tiles_z = (d.nz + kStencil2TZ - 1) / kStencil2TZ;
+      sa.spatial_tiles = sa.tiles_x * sa.tiles_y * sa.tiles_z;
+      const uint64_t groups = (uint64_t)((sa.spatial_tiles + 7) / 8) * 8 * nf;
+      if (groups > 0x7FFFFFFFull) fail(SAGE_EINVAL, "stencil launch too large");
+      sa.src = reinterpret_cast<const uint64_t*>(F.d_meta) + (size_t)k * 2 * nf;
       sa.dst = sa.src + nf;
       void* params[] = {&sa};
-      HIPX(hipModuleLaunchKernel(k, (uint32_t)groups, 1, 1, 1024, 1, 1, 0, s, params, nullptr));
+      HIPX(hipModuleLaunchKernel(fused ? k2 : k1, (uint32_t)groups, 1, 1, 1024, 1, 1, 0, s, params, nullptr));
     }
     c.timer.stop(tok, s);
   }

@@ -456,6 +456,7 @@ struct Ctx {
   uint64_t dev_chunk = kDevChunkBytes;       // registration chunk of device-resident sources
   AllocFault alloc_fault;                    // SAGE_FAULT_ALLOC_AFTER
   uint32_t f32_cols = 4;                     // output columns per workgroup of the FP32 layer (4, or 8: SAGE_F32_COLS)
+  bool stencil_fuse = true;                  // sweeps in passes of two (SAGE_STENCIL_FUSE=0: one per pass)
   uint8_t* na_scratch = nullptr;             // device address of this GPU's fn_invoke_noalloc scratch
   uint8_t* na_hmeta = nullptr;               // pinned host mirror of its metadata part
   uint64_t test_fp_value = 0;

@@ -269,6 +269,7 @@ sage_status sage_open(int device, const sage_config* cfg, sage_ctx** out) {
     }
     c.pool.fault = &c.alloc_fault;
     c.cache.fault = &c.alloc_fault;
+    if (const char* e = std::getenv("SAGE_STENCIL_FUSE")) c.stencil_fuse = std::strtol(e, nullptr, 0) != 0;
     if (const char* e = std::getenv("SAGE_F32_COLS")) {
       c.f32_cols = (uint32_t)std::strtoul(e, nullptr, 0);
       if (c.f32_cols != 4 && c.f32_cols != 8) fail(SAGE_EINVAL, "SAGE_F32_COLS must be 4 or 8");

@@ -184,9 +184,9 @@ def test_mlp_graph_after_stencil_grows_the_flight_metadata(sage_ctx_factory, tor
     y0 = np.zeros((b, width), dtype=np.float32)
     inv = S.fn_setup(ctx, fn, b)
     S.fn_invoke(ctx, inv, x, y0)
-    # 8 fields x 9000 sweeps x 2 addresses x 8 bytes = 1.15 MB of field tables
+    # 8 fields x 9000 passes of two sweeps x 2 addresses x 8 bytes = 1.15 MB of field tables
     shape = (4, 4, 8)
-    relax = S.fn_register(ctx, S.relax_desc(shape[2], shape[1], shape[0], 9000, 0.5), [])
+    relax = S.fn_register(ctx, S.relax_desc(shape[2], shape[1], shape[0], 18000, 0.5), [])
     rinv = S.fn_setup(ctx, relax, 8)
     u0 = np.stack([synth.stencil_field(0, j, seed=33, shape=shape) for j in range(8)])
     u = np.zeros_like(u0)

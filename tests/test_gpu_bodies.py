@@ -258,6 +258,40 @@ def test_stencil_vs_oracle(sage_ctx_factory, torch_cuda, shape, sweeps):
                 assert np.array_equal(o[j], f[j])
 
 
+@pytest.mark.parametrize("shape,sweeps", [((70, 33, 300), 4), ((9, 20, 64), 5), ((66, 17, 260), 2), ((4, 5, 8), 3)])
+def test_stencil_two_sweeps_per_pass_same_bits(sage_ctx_factory, torch_cuda, monkeypatch, shape, sweeps):
+    """Sweeps fused in passes of two (u1 kept on chip, tiles overlapping by a
+    row and a cell) give the bits of one sweep per pass, across x tiles
+    (ragged at nx = 300, 260), y tiles of 14 rows and z tiles of 64 planes,
+    with a coefficient grid and with a constant coefficient."""
+    from paper_2404_14691_amd import sage as S
+    nz, ny, nx = shape
+    c = np.random.default_rng(6).uniform(0.1, 1.0, shape).astype(np.float32)
+    fields = np.stack([synth.stencil_field(0, j, seed=6, shape=shape) for j in range(2)])
+    outs = {}
+    for fuse in ("1", "0"):
+        monkeypatch.setenv("SAGE_STENCIL_FUSE", fuse)
+        ctx = sage_ctx_factory(pool_budget_bytes=64 << 20)
+        res = []
+        kinds = [(S.relax_desc(nx, ny, nz, sweeps, 0.6), [])]
+        if nx & (nx - 1) == 0:  # the coefficient-grid kind needs a power-of-two nx
+            kinds.insert(0, (S.stencil_desc(nx, ny, nz, sweeps), [S.make_blob(c)]))
+        for desc, blobs in kinds:
+            fn = S.fn_register(ctx, desc, blobs)
+            inv = S.fn_setup(ctx, fn, 2)
+            out = np.zeros_like(fields)
+            S.fn_invoke(ctx, inv, fields, out)
+            S.fn_release(ctx, inv)
+            S.fn_unregister(ctx, fn)
+            res.append(out)
+        outs[fuse] = res
+    for a, b in zip(outs["1"], outs["0"]):
+        assert np.array_equal(a, b)
+    cg = np.full(shape, 0.6, dtype=np.float32)
+    for j in range(2):
+        assert OS.normwise_error(outs["1"][-1][j], OS.jacobi7(fields[j], cg, sweeps)) <= F32_TOL
+
+
 def test_stencil_zero_coefficient_identity(sage_ctx_factory, torch_cuda):
     from paper_2404_14691_amd import sage as S
     ctx = sage_ctx_factory()
