@@ -25,6 +25,22 @@
  *    unregistered handle gives SAGE_ESTATE / SAGE_ENOTFOUND.
  *  - One sage_ctx per GPU.  Its calls are serialised by an internal mutex
  *    and may come from any thread.
+ *
+ * Environment variables read by sage_open (tests and measurements; none is
+ * needed in normal use):
+ *    SAGE_TILE=<shape>[+<shape>]  fixed BF16 GEMM tile shape (and thin tail
+ *                                 shape) instead of the planner's choice
+ *    SAGE_DEV_CHUNK_BYTES=<n>     registration chunk of device-resident
+ *                                 sources (default 1 GiB; a multiple of 64 KiB)
+ *    SAGE_F32_COLS=4|8            output columns per workgroup of the FP32
+ *                                 MLP layer (default 4; same bits either way)
+ *    SAGE_STENCIL_FUSE=0|1        Jacobi sweeps in passes of two (default 1;
+ *                                 same bits either way)
+ *    SAGE_FAULT_ALLOC_AFTER=<n>   after n device allocations of the pool
+ *                                 arena and workspace cache, every later one
+ *                                 fails as if the device were full (ENOMEM paths)
+ *    SAGE_TEST_FP_CONST=<v>       every fingerprint reads as v (forces
+ *                                 collisions: the byte VERIFY decides)
  */
 #ifndef SAGE_H
 #define SAGE_H
