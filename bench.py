@@ -719,6 +719,10 @@ def main():
         setup_shared = [x for r in res for x in r[0]]
         g_ms, g_n = S.sage_timing_get(ctx, "ggemm_bf16")
         plan = S.sage_last_launch(ctx)
+        # the MFMA ceiling of the main tile shape at the clock this load sustains
+        # (outside the timed region; context for the roofline, not part of a step)
+        ceil_us, ceil_ghz = S.sage_mfma_ceiling(ctx, wl.width, 20)
+        ceil_cus = torch.cuda.get_device_properties(0).multi_processor_count  # one workgroup per CU
         # ---- plain
         if args.only_shared:
             p_elapsed, setup_plain = None, []
@@ -741,6 +745,14 @@ def main():
     gemm_avg_ms = g_ms / max(g_n, 1)
     achieved = flops_launch / (gemm_avg_ms * 1e-3) / 1e12
     traffic = traffic_record(plan)
+    ceil_flops = 2.0 * ceil_cus * 256 * 256 * wl.width
+    ceil_tflops = ceil_flops / (ceil_us * 1e-6) / 1e12
+    mfma_ceiling = {
+        "what": "the main 256x256 tile shape without its global loads (LDS ring filled once with random BF16; "
+                "same fragment reads, MFMAs, barriers), one tile per CU (sage_mfma_ceiling)",
+        "us_per_launch": round(ceil_us, 2), "achieved": round(ceil_tflops, 1),
+        "frac_of_peak": round(ceil_tflops / BF16_PEAK_TFLOPS, 4), "shader_ghz": round(ceil_ghz, 3),
+        "layer_frac_of_ceiling": round(achieved / ceil_tflops, 4)}
     fp_bytes = (sum(b.numel() for b in wl.dev_blobs) + 8 * sum(b.numel() for b in wl.dev_blobs) // 65536)
     line = {
         "metric": METRIC,
@@ -773,6 +785,7 @@ def main():
                      "frac": round(achieved / BF16_PEAK_TFLOPS, 4),
                      "traffic": traffic["hbm_bytes_per_layer"] if traffic else None,
                      "kernel": "grouped BF16 GEMM layer: " + plan, "avg_launch_ms": round(gemm_avg_ms, 5),
+                     "mfma_ceiling": mfma_ceiling,
                      "launch": "one layer (main launch + thin-tile tail launch when split)",
                      "flop_per_launch": flops_launch,
                      "traffic_source": os.path.relpath(TRAFFIC_RECORD, ROOT) if traffic else None},

@@ -411,6 +411,19 @@ sage_status sage_timing_reset(sage_ctx* ctx);
  * can leave the others untimed.  The name is copied; EINVAL for an unknown
  * name. */
 sage_status sage_timing_only(sage_ctx* ctx, const char* kernel);
+/* Measurement support, not part of the path (no passage of the paper): the
+ * compute-side ceiling of the grouped GEMM's main tile shape.  Runs one
+ * workgroup per CU, each doing what the main kernel does for one 256 x 256
+ * tile of depth k (k / 32 slices; per slice, every wave reads its 12 operand
+ * fragments from a four-stage LDS ring and issues its 32 MFMAs, with the
+ * main kernel's barrier schedule) except the global loads: the ring is
+ * filled once with random BF16 values.  reps launches back to back on the
+ * context's control stream.  *us_per_launch is the mean time per launch
+ * (HIP events); *shader_ghz the median over workgroups of the shader clock
+ * during the last launch (s_memtime against the 100 MHz reference counter).
+ * EINVAL unless k is a positive multiple of 32 up to 65536 and
+ * 1 <= reps <= 1000; ENOMEM if the small workspace cannot be had. */
+sage_status sage_mfma_ceiling(sage_ctx* ctx, uint32_t k, uint32_t reps, double* us_per_launch, double* shader_ghz);
 /* Describe the last MLP body launch of this context as text, e.g.
  * "ggemm6p_bf16_256x256:256+ggemm3t_bf16_32x32:384" (kernel:tiles per layer;
  * a second term is the thin-tile launch over split-off ragged row tiles).

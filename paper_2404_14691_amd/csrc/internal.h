@@ -52,6 +52,7 @@ sage_status guard(const std::function<void()>& body);
 // ------------------------------------------------------------ kernels (rt)
 hipError_t launch_fp64k(const void* data, uint64_t nbytes, uint64_t* out, int max_groups, hipStream_t s);
 hipError_t launch_blkcopy(const BlkOp* ops, uint32_t n, uint32_t* result, int max_groups, hipStream_t s);
+hipError_t launch_mfma_ceiling(uint32_t grid, uint32_t k_slices, float* out, unsigned long long* clk, hipStream_t s);
 
 // Fixed device scratch of fn_invoke_noalloc: one array per GPU in the
 // library's code object, never freed.  Layout: [metadata: kNoAllocMetaBytes]

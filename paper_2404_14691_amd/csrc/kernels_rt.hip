@@ -168,6 +168,92 @@ __global__ __launch_bounds__(256) void blkcopy_kernel(const BlkOp* __restrict__ 
   }
 }
 
+// Measurement kernel, not on the path: the grouped BF16 GEMM's main tile
+// shape (256 x 256, 8 waves, wave tile 128 x 64, v_mfma_f32_16x16x32_bf16
+// over K slices of 32, two wave groups alternating LDS and matrix phases at
+// raised matrix-phase priority) with its global loads taken out.  The
+// four-stage LDS ring (64 B of each of 512 rows per stage, the same swizzle)
+// is filled once with random BF16 values of activation and weight scale, and
+// every slice reads its fragments from the next stage, so operand values
+// change from slice to slice as in a real layer (the MFMA rate and the
+// clock the chip sustains depend on them).  Its time bounds what the main
+// shape reaches on this chip with this data.  Each workgroup also records
+// its shader-clock and 100 MHz reference-clock counts, whose ratio is that
+// clock.
+typedef __bf16 ceil_bf16x8 __attribute__((ext_vector_type(8)));
+typedef float ceil_f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void ceil_sync() {
+  __builtin_amdgcn_sched_barrier(0);
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// a random BF16: random sign and 7-bit fraction, exponent in [e0, e0 + 7)
+__device__ __forceinline__ uint32_t ceil_bf16(uint32_t h, uint32_t e0) {
+  return ((h >> 31) << 15) | ((e0 + (h >> 8) % 7u) << 7) | (h & 0x7Fu);
+}
+
+__global__ __launch_bounds__(512, 1) void mfma_ceiling_kernel(uint32_t k_slices, float* __restrict__ out,
+                                                             unsigned long long* __restrict__ clk) {
+  constexpr uint32_t kRow = 64, kStage = 512 * kRow, kAStage = 256 * kRow;
+  __shared__ __attribute__((aligned(1024))) uint8_t lds[4 * kStage];
+  const uint32_t t = threadIdx.x, lane = t & 63;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  const uint32_t wm = wave / 4, wn = wave % 4;
+  const bool lag = wave >= 4;  // waves w and w + 4 share a SIMD
+  for (uint32_t w = t; w < 4 * kStage / 4; w += 512) {
+    uint32_t h = (w + 1) * 0x9E3779B9u ^ blockIdx.x * 0x85EBCA6Bu;
+    h ^= h >> 16;
+    h *= 0x7FEB352Du;
+    h ^= h >> 15;
+    h *= 0x846CA68Bu;
+    h ^= h >> 16;
+    const uint32_t e0 = (w * 4) % kStage < kAStage ? 120u : 114u;  // A rows ~[2^-7, 1), W rows 64 x smaller
+    reinterpret_cast<uint32_t*>(lds)[w] = ceil_bf16(h, e0) | (ceil_bf16(h * 0x27D4EB2Du, e0) << 16);
+  }
+  __syncthreads();
+  auto sw = [](uint32_t r, uint32_t c) { return r * kRow + ((c ^ ((r >> 1) & 3)) << 4); };
+  ceil_f32x4 acc[8][4];
+#pragma unroll
+  for (int i = 0; i < 8; i++)
+#pragma unroll
+    for (int j = 0; j < 4; j++) acc[i][j] = ceil_f32x4{0.f, 0.f, 0.f, 0.f};
+  const unsigned long long c0 = __builtin_amdgcn_s_memtime(), r0 = __builtin_amdgcn_s_memrealtime();
+  ceil_sync();
+  if (lag) ceil_sync();
+  const uint32_t chunk = lane >> 4;
+  for (uint32_t kt = 0; kt < k_slices; kt++) {
+    const uint8_t* st = lds + (kt % 4) * kStage;
+    ceil_bf16x8 af[8], bfr[4];
+#pragma unroll
+    for (int i = 0; i < 8; i++) af[i] = *reinterpret_cast<const ceil_bf16x8*>(st + sw(wm * 128 + i * 16 + (lane & 15), chunk));
+#pragma unroll
+    for (int j = 0; j < 4; j++)
+      bfr[j] = *reinterpret_cast<const ceil_bf16x8*>(st + kAStage + sw(wn * 64 + j * 16 + (lane & 15), chunk));
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+    ceil_sync();
+    __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+    for (int i = 0; i < 8; i++)
+#pragma unroll
+      for (int j = 0; j < 4; j++) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    __builtin_amdgcn_s_setprio(0);
+    ceil_sync();
+  }
+  if (!lag) ceil_sync();
+  float sum = 0.f;
+#pragma unroll
+  for (int i = 0; i < 8; i++)
+#pragma unroll
+    for (int j = 0; j < 4; j++) sum += acc[i][j][0] + acc[i][j][1] + acc[i][j][2] + acc[i][j][3];
+  out[blockIdx.x * 512u + t] = sum;
+  if (t == 0) {
+    clk[2 * blockIdx.x] = __builtin_amdgcn_s_memtime() - c0;
+    clk[2 * blockIdx.x + 1] = __builtin_amdgcn_s_memrealtime() - r0;
+  }
+}
+
 // Scratch of fn_invoke_noalloc (metadata + activations), a fixed array in
 // every GPU's copy of this code object.  Host code never passes `scratch`
 // itself (on the host it is only a stand-in symbol): it passes the device
@@ -204,6 +290,11 @@ hipError_t launch_blkcopy(const BlkOp* ops, uint32_t n, uint32_t* result, int ma
   const uint32_t pairs = (n + 1) / 2;
   const uint32_t grid = pairs < (uint32_t)max_groups ? pairs : (uint32_t)max_groups;
   hipLaunchKernelGGL(blkcopy_kernel, dim3(grid), dim3(256), 0, s, ops, n, result);
+  return hipGetLastError();
+}
+
+hipError_t launch_mfma_ceiling(uint32_t grid, uint32_t k_slices, float* out, unsigned long long* clk, hipStream_t s) {
+  hipLaunchKernelGGL(mfma_ceiling_kernel, dim3(grid), dim3(512), 0, s, k_slices, out, clk);
   return hipGetLastError();
 }
 

@@ -759,6 +759,42 @@ sage_status sage_timing_get(sage_ctx* p, const char* kernel, double* total_ms, u
   });
 }
 
+sage_status sage_mfma_ceiling(sage_ctx* p, uint32_t k, uint32_t reps, double* us_per_launch, double* shader_ghz) {
+  return guard([&] {
+    Ctx& c = ctx_of(p);
+    if (!us_per_launch || !shader_ghz) fail(SAGE_EINVAL, "null argument");
+    if (k == 0 || k % 32 || k > 65536 || reps == 0 || reps > 1000) fail(SAGE_EINVAL, "k %u or reps %u out of range", k, reps);
+    std::lock_guard<std::recursive_mutex> lk(c.mu);
+    const uint32_t grid = (uint32_t)c.cus;
+    float* out = static_cast<float*>(c.cache.get((size_t)grid * 512 * sizeof(float)));
+    auto* clk = static_cast<unsigned long long*>(c.cache.get((size_t)grid * 2 * sizeof(unsigned long long)));
+    hipStream_t s = c.ctl;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPX(hipEventCreate(&e0));
+    HIPX(hipEventCreate(&e1));
+    HIPX(launch_mfma_ceiling(grid, k / 32, out, clk, s));  // warm-up
+    HIPX(hipEventRecord(e0, s));
+    for (uint32_t r = 0; r < reps; r++) HIPX(launch_mfma_ceiling(grid, k / 32, out, clk, s));
+    HIPX(hipEventRecord(e1, s));
+    HIPX(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPX(hipEventElapsedTime(&ms, e0, e1));
+    std::vector<unsigned long long> h((size_t)grid * 2);
+    HIPX(hipMemcpyAsync(h.data(), clk, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIPX(hipStreamSynchronize(s));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c.cache.put(out);
+    c.cache.put(clk);
+    std::vector<double> ghz;
+    for (uint32_t g = 0; g < grid; g++)
+      if (h[2 * g + 1]) ghz.push_back((double)h[2 * g] / (double)h[2 * g + 1] * 0.1);  // reference clock 100 MHz
+    std::sort(ghz.begin(), ghz.end());
+    *us_per_launch = (double)ms * 1e3 / reps;
+    *shader_ghz = ghz.empty() ? 0.0 : ghz[ghz.size() / 2];
+  });
+}
+
 sage_status sage_timing_only(sage_ctx* p, const char* kernel) {
   return guard([&] {
     Ctx& c = ctx_of(p);

@@ -129,6 +129,7 @@ _sigs = {
     "sage_blkcopy": (C.c_int, [_P, _P, C.c_size_t, _P, _P]),
     "sage_timing_enable": (C.c_int, [_P, C.c_int]),
     "sage_timing_get": (C.c_int, [_P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]),
+    "sage_mfma_ceiling": (C.c_int, [_P, C.c_uint32, C.c_uint32, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "sage_timing_reset": (C.c_int, [_P]),
     "sage_timing_only": (C.c_int, [_P, C.c_char_p]),
     "sage_last_launch": (C.c_int, [_P, C.c_char_p, C.c_size_t]),
@@ -392,6 +393,13 @@ def sage_timing_get(ctx: int, kernel: str):
     _check(_lib.sage_timing_get(ctx, kernel.encode(), C.byref(ms), C.byref(n)), "sage_timing_get")
     return ms.value, n.value
 
+
+
+def sage_mfma_ceiling(ctx: int, k: int, reps: int = 20):
+    """(us per launch, shader GHz) of the main GEMM tile shape without its global loads."""
+    us, ghz = C.c_double(), C.c_double()
+    _check(_lib.sage_mfma_ceiling(ctx, k, reps, C.byref(us), C.byref(ghz)), "sage_mfma_ceiling")
+    return us.value, ghz.value
 
 def sage_timing_reset(ctx: int) -> None:
     _check(_lib.sage_timing_reset(ctx), "sage_timing_reset")

@@ -83,3 +83,20 @@ def test_blkcopy_copy_and_verify(sage_ctx_factory, torch_cuda):
     S.sage_blkcopy(ctx, dv.data_ptr(), 4, res.data_ptr(), stream)
     torch.cuda.synchronize()
     assert res.cpu().tolist() == [0, 0, 1, 1]
+
+
+def test_mfma_ceiling_measurement(sage_ctx_factory, torch_cuda):
+    """The compute-side ceiling measurement of the main GEMM tile runs,
+    reports a positive time and a plausible shader clock, and scales with K;
+    bad arguments are EINVAL."""
+    from paper_2404_14691_amd import sage as S
+    ctx = sage_ctx_factory()
+    us_4k, ghz = S.sage_mfma_ceiling(ctx, 4096, 5)
+    us_1k, _ = S.sage_mfma_ceiling(ctx, 1024, 5)
+    assert us_4k > 0 and us_1k > 0
+    assert 0.5 < ghz < 3.0, ghz
+    assert us_4k > 2 * us_1k  # four times the MFMAs: well over twice the time
+    for k, reps in ((0, 1), (33, 1), (4096, 0), (4096, 1001)):
+        with pytest.raises(S.SageError) as e:
+            S.sage_mfma_ceiling(ctx, k, reps)
+        assert e.value.status == S.SAGE_EINVAL
