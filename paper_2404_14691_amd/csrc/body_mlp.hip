@@ -712,17 +712,25 @@ typedef __attribute__((address_space(1))) const f32x4 g_f32x4;
 // workgroups that each read the 8 input rows once for 8 columns, 1 twice as
 // many workgroups (two per CU at 8 rows of width 2048) with half the weight
 // rows each.  The K order of a column is the same in both.
-template <int CPW>
+// ONE: the launch has a single group, passed by value (its block table
+// `wtab1` and row count `m1`, row0 and first tile 0): the header and group
+// record are not read, which takes two dependent loads off the way to the
+// weights.
+template <int CPW, bool ONE>
 __device__ __forceinline__ void mlp_f32_body(const GemmHdr* __restrict__ hdr, const GemmGroup* __restrict__ groups,
-                                             const LayerArgs& la, float (*xs)[kF32KC]) {
+                                             const LayerArgs& la, float (*xs)[kF32KC], const uint64_t* wtab1,
+                                             uint32_t m1) {
   static_assert(CPW == 1 || CPW == 2, "one or two columns per wave");
   constexpr int WPL = kF32KC / 256;                     // float4 per lane per weight row per chunk
   constexpr int XPR = kF32KC / 4 / 256;                 // float4 per thread per staged row per chunk
   const uint32_t t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const uint32_t K = la.K;
   const bool relu = la.flags & kRelu;
-  for (uint32_t tile = blockIdx.x; tile < hdr->total_tiles; tile += gridDim.x) {
-    const GemmGroup gr = groups[find_group(groups, hdr->n_groups, tile)];
+  const uint32_t total_tiles = ONE ? la.N / (4 * CPW) : hdr->total_tiles;
+  for (uint32_t tile = blockIdx.x; tile < total_tiles; tile += gridDim.x) {
+    GemmGroup gr;
+    if (ONE) gr = GemmGroup{reinterpret_cast<uint64_t>(wtab1), m1, 0, 0, 0};
+    else gr = groups[find_group(groups, hdr->n_groups, tile)];
     const uint32_t n = (tile - gr.tile_start) * (4 * CPW) + wave * CPW;
     const uint64_t* wtab = reinterpret_cast<const uint64_t*>(gr.wtab);
     const uint64_t off0 = la.w_off + (uint64_t)n * K * 4, off1 = off0 + (uint64_t)K * 4;
@@ -820,16 +828,19 @@ __device__ __forceinline__ void mlp_f32_body(const GemmHdr* __restrict__ hdr, co
   }
 }
 
+// wtab1 non-null: the launch's only group, by value (see ONE above)
 extern "C" __global__ __launch_bounds__(256) void mlp_f32_layer(const GemmHdr* __restrict__ hdr,
                                                                 const GemmGroup* __restrict__ groups,
-                                                                LayerArgs la) {
+                                                                LayerArgs la, const uint64_t* wtab1, uint32_t m1) {
   __shared__ __attribute__((aligned(16))) float xs[8][kF32KC];
-  mlp_f32_body<2>(hdr, groups, la, xs);
+  if (wtab1) mlp_f32_body<2, true>(hdr, groups, la, xs, wtab1, m1);
+  else mlp_f32_body<2, false>(hdr, groups, la, xs, wtab1, m1);
 }
 
 extern "C" __global__ __launch_bounds__(256) void mlp_f32_layer_c4(const GemmHdr* __restrict__ hdr,
                                                                    const GemmGroup* __restrict__ groups,
-                                                                   LayerArgs la) {
+                                                                   LayerArgs la, const uint64_t* wtab1, uint32_t m1) {
   __shared__ __attribute__((aligned(16))) float xs[8][kF32KC];
-  mlp_f32_body<1>(hdr, groups, la, xs);
+  if (wtab1) mlp_f32_body<1, true>(hdr, groups, la, xs, wtab1, m1);
+  else mlp_f32_body<1, false>(hdr, groups, la, xs, wtab1, m1);
 }

@@ -160,6 +160,19 @@ static void launch_kernel(hipFunction_t k, uint32_t grid, uint32_t threads, hipS
   HIPX(hipModuleLaunchKernel(k, grid, 1, 1, threads, 1, 1, 0, s, params, nullptr));
 }
 
+// The FP32 layer also takes its only group by value (wtab1 null: read the
+// groups from the header as the BF16 kernels do).
+static void launch_f32(hipFunction_t k, uint32_t grid, uint32_t threads, hipStream_t s, const GemmHdr* hdr,
+                       const GemmGroup* groups, const LayerArgs& la, const uint64_t* wtab1, uint32_t m1) {
+  const GemmHdr* h = hdr;
+  const GemmGroup* g = groups;
+  LayerArgs a = la;
+  const uint64_t* w = wtab1;
+  uint32_t m = m1;
+  void* params[] = {&h, &g, &a, &w, &m};
+  HIPX(hipModuleLaunchKernel(k, grid, 1, 1, threads, 1, 1, 0, s, params, nullptr));
+}
+
 // ---------------------------------------------------------------- MLP group
 // All calls share kind, width and depth.  Rows of the calls of one weight
 // table (one function, or one private copy) are packed into one group; the
@@ -338,18 +351,24 @@ int launch_mlp_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, int fl
     la.flags = (l + 1 < L ? kRelu : 0u) | (l + 1 == L ? kOutF32 : 0u);
     return la;
   };
+  // a one-function FP32 launch passes its group by value; a graph would
+  // keep those arguments, so such launches are not captured
+  const bool f32_one = !bf16 && ng == 1;
+  const uint64_t* one_tab = f32_one ? reinterpret_cast<const uint64_t*>(grp[0].wtab) : nullptr;
+  const uint32_t one_m = f32_one ? grp[0].m : 0;
   auto layers = [&](hipStream_t st) {
     for (uint32_t l = 0; l < L; l++) {
       for (Fn* g : gated) HIPX(hipStreamWaitEvent(st, g->seg[l], 0));
       const LayerArgs la = layer_args(l);
-      if (tiles) launch_kernel(kfn, grid, threads, st, d_hdr, d_grp, la);
+      if (!bf16) launch_f32(kfn, grid, threads, st, d_hdr, d_grp, la, one_tab, one_m);
+      else if (tiles) launch_kernel(kfn, grid, threads, st, d_hdr, d_grp, la);
       if (split) launch_kernel(tfn, tgrid, tthreads, st, d_thdr, d_tgrp, la);
     }
   };
   const char* tname = bf16 ? "ggemm_bf16" : "mlp_f32";
   // a gated launch's span includes copy waits: it is not timed, nor captured
   const int tok = gated.empty() && !ext ? c.timer.start(tname, s, L) : -1;
-  if (c.cfg.batch && gated.empty() && !ext) {
+  if (c.cfg.batch && gated.empty() && !ext && !f32_one) {
     // the FP32 layer's grid follows its tile count: part of the key
     const GraphKey key{kname + (split ? std::string("+") + plan.tail->name : std::string()) + (tiles ? "" : "/tail") +
                            (bf16 ? std::string() : "/" + std::to_string(grid)),

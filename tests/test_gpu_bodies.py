@@ -348,7 +348,9 @@ def test_relax_rejects_read_only_blobs(sage_ctx_factory, torch_cuda):
 def test_f32_four_and_eight_columns_per_workgroup_same_bits(sage_ctx_factory, torch_cuda, monkeypatch):
     """The FP32 layer with one column per wave (SAGE_F32_COLS=4) walks each
     column's K in the same order as with two: the same bits, one group and
-    two groups (the last column of the last layer included)."""
+    two groups (the last column of the last layer included).  A one-group
+    launch passes its group by value, a two-group one reads the groups from
+    the launch header: the solo run against the batch compares the two."""
     from paper_2404_14691_amd import sage as S
     W, L = 1024, 2
     rng = np.random.default_rng(8)
