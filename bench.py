@@ -8,14 +8,18 @@ uniform on 1..32 and BF16 N(0,1) inputs.  Sources and inputs are resident in
 HBM before the timed region.
 
 One step = the whole path over one batch of 256 requests:
-  shared+batched: fn_register x4 (fingerprint + dedup into the pool),
-                  fn_setup x256, one fn_invoke_batch (grouped GEMM per layer
-                  from a hipGraph), fn_release x256, fn_unregister x4;
-  plain:          fn_register x4 (code only), then per request a private
-                  copy of the weights (fn_setup), one launch sequence
-                  (fn_invoke), fn_release.
+  shared+batched: fn_register_batch of the 4 functions (fingerprint + dedup
+                  into the pool, each function's fingerprints overlapping
+                  the previous one's classification), fn_setup x256, one
+                  fn_invoke_batch (grouped GEMM per layer from a hipGraph),
+                  fn_release x256, fn_unregister x4;
+  plain:          the same registration call (code only), then per request
+                  a private copy of the weights (fn_setup), one launch
+                  sequence (fn_invoke), fn_release.
 Setup latency of a request = its fn_setup time, plus its function's
-fn_register time for the first request of each function (a cold start).
+registration time (the library's time from the previous function's
+registration to its own) for the first request of each function (a cold
+start).
 
 Prints one JSON line.
 """
@@ -101,13 +105,12 @@ class Workload:
 
 
 def register_all(S, ctx, wl):
-    fns, reg_ms = [], []
+    """The step's functions in one fn_register_batch call (each function's
+    fingerprints run while the host classifies the previous one); per
+    function, the library's time since the previous one was registered."""
     desc = S.mlp_desc(S.SAGE_MLP_BF16, wl.layers, wl.width)
-    for d in wl.dev_blobs:
-        t0 = time.perf_counter()
-        fns.append(S.fn_register(ctx, desc, [S.make_blob(d.data_ptr(), d.numel(), where=S.SAGE_SRC_DEVICE)]))
-        reg_ms.append((time.perf_counter() - t0) * 1e3)
-    return fns, reg_ms
+    srcs = [[S.make_blob(d.data_ptr(), d.numel(), where=S.SAGE_SRC_DEVICE)] for d in wl.dev_blobs]
+    return S.fn_register_batch(ctx, [desc] * len(srcs), srcs)
 
 
 def shared_step(S, ctx, wl, want_stats=False):
@@ -287,10 +290,10 @@ def host_sourced(S, torch, wl, shared_steps=10, naive_requests=64):
     host memory (pinned, from sage_host_alloc, and pageable), inputs read from
     and outputs written to host memory.
 
-    shared+batched step: fn_register x4 from the host sources (pipelined
-      H2D + fingerprint + dedup), fn_setup x256 (one call), one grouped
-      fn_invoke_batch, fn_release x256, fn_unregister x4;
-    plain step: fn_register x4 (code only), then per request fn_setup (a
+    shared+batched step: fn_register_batch of the 4 functions from the host
+      sources (pipelined H2D + fingerprint + dedup), fn_setup x256 (one
+      call), one grouped fn_invoke_batch, fn_release x256, fn_unregister x4;
+    plain step: the same registration call (code only), then per request fn_setup (a
       private copy of its function's 256 MiB through the same pipelined H2D),
       fn_invoke (one launch sequence), fn_release;
     naive plain: plain with one staging slot on one stream and the code
@@ -298,7 +301,8 @@ def host_sourced(S, torch, wl, shared_steps=10, naive_requests=64):
 
     Setup latency of a request is the library's own clock for its fn_setup
     (fn_setup_batch with per-request times) on both paths, plus its
-    function's fn_register wall time for the first request of each function.
+    function's registration time (library clock) for the first request of
+    each function.
     Throughput_perf follows the paper's eq. (1): the achieved invocation rate
     over the rate if each invocation cost only its computation time T_comp,
     here the mean device time of one invocation's body run alone (the plain
@@ -327,12 +331,7 @@ def host_sourced(S, torch, wl, shared_steps=10, naive_requests=64):
         return srcs, srcs
 
     def register(ctx, srcs):
-        fns, reg_ms = [], []
-        for a in srcs:
-            t0 = time.perf_counter()
-            fns.append(S.fn_register(ctx, desc, [S.make_blob(a)]))
-            reg_ms.append((time.perf_counter() - t0) * 1e3)
-        return fns, reg_ms
+        return S.fn_register_batch(ctx, [desc] * len(srcs), [[S.make_blob(a)] for a in srcs])
 
     def shared_step(ctx, srcs, want_pool=False):
         fns, reg_ms = register(ctx, srcs)

@@ -235,6 +235,20 @@ void sage_host_free(sage_ctx* ctx, void* p);
  * EIO (code object), EHIP. */
 sage_status fn_register(sage_ctx* ctx, const sage_fn_desc* desc, const sage_blob* blobs,
                         size_t n_blobs, sage_fn* out);
+/* Register n functions as fn_register would one after another (same
+ * classes, same errors), pipelined across functions (the setup parallelism
+ * of section "Parallelizing data and context" carried across a batch; the
+ * paper defines no batch call): while the host classifies function i's
+ * blocks, the fingerprints of function i + 1's device sources already run.
+ * Function i takes descs[i] and blobs[i][0 .. n_blobs[i]).  On success
+ * out[i] is function i's handle and, when register_ms is not NULL,
+ * register_ms[i] the time from the previous function's registration (the
+ * call's start for i = 0) to function i's (milliseconds).  All or nothing:
+ * on an error no function of the batch stays registered and out is not
+ * written.  n = 0 does nothing.  Errors: those of fn_register, EINVAL
+ * (null arrays). */
+sage_status fn_register_batch(sage_ctx* ctx, size_t n, const sage_fn_desc* descs, const sage_blob* const* blobs,
+                              const size_t* n_blobs, sage_fn* out, double* register_ms);
 
 /* Drop a function.  EBUSY while it has live setups.  Blocks no other
  * registered function uses leave the pool.  Returns after every copy that

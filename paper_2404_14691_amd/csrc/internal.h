@@ -274,6 +274,16 @@ struct Src {
   bool pinned;
 };
 
+// One chunk of a registration's read-only data: staged through a ring slot
+// (host sources) or fingerprinted in place (device sources).
+struct RegChunk {
+  uint32_t blob;
+  uint64_t off, bytes;
+  uint32_t first, nblk;
+  int slot;
+  const uint8_t* data;  // device address of the chunk's bytes
+};
+
 struct Fn {
   uint64_t id = 0;
   sage_fn_desc d{};
@@ -292,6 +302,7 @@ struct Fn {
   Module* mod = nullptr;
   hipEvent_t ready = nullptr;         // data of the function is in place
   std::vector<hipEvent_t> seg;        // progressive reload: layer l's blocks are in place
+  std::vector<RegChunk> pre;          // chunks whose fingerprints went out ahead of the registration
   uint32_t block_len(uint32_t b) const;
   const uint8_t* block_src(uint32_t b, bool* dev, bool* pinned = nullptr) const;
 };
@@ -351,6 +362,7 @@ struct Ring {
   std::vector<uint32_t*> dres_c;
   std::vector<hipEvent_t> ev;           // fingerprints (then VERIFY results) of the slot's chunk
   std::vector<hipEvent_t> ev_c;         // the slot's last in-flight COPY
+  std::vector<uint8_t> held;            // the slot holds a chunk fingerprinted ahead of its registration
   std::vector<size_t> cap;  // blocks the fp/op/result buffers of each slot hold
   size_t ops_cap = 0;
 };
@@ -482,6 +494,14 @@ void unload_module(Ctx& c, Module& m);
 void advance_exit(Ctx& c);                 // multi-stage exit of idle data and code
 void flights_drop_graphs(Ctx& c);          // finish every flight and drop its captured graphs
 void register_shared(Ctx& c, Fn& f);
+// Fingerprint a device-source function's chunks ahead of its registration
+// (fn_register_batch: while the host classifies the previous function).
+// The chunks keep their ring slots (held) until register_shared processes
+// them.  false (nothing issued) unless sharing is on, every source is on
+// the device and enough slots are free.
+bool register_prefetch(Ctx& c, Fn& f);
+// Give back the slots of a prefetch that will not be registered.
+void register_drop_prefetch(Ctx& c, Fn& f);
 void copy_private(Ctx& c, Fn& f, uint8_t* dst, hipStream_t s);
 void reload_classes(Ctx& c, Fn& f, const std::vector<uint32_t>& missing);
 void refresh_table(Ctx& c, Fn& f);

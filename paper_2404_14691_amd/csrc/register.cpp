@@ -19,6 +19,7 @@ void ring_init(Ctx& c) {
   const size_t nblk = R.chunk / kBlock;
   R.ops_cap = nblk;
   R.cap.assign(R.slots, nblk);
+  R.held.assign(R.slots, 0);
   for (size_t i = 0; i < R.slots; i++) {
     uint8_t *h = nullptr, *d = nullptr;
     uint64_t *dfp = nullptr, *hfp = nullptr;
@@ -199,15 +200,82 @@ const uint8_t* Fn::block_src(uint32_t b, bool* dev, bool* pinned) const {
 }
 
 // ------------------------------------------------------- register (shared)
-namespace {
-struct Chunk {
-  uint32_t blob;
-  uint64_t off, bytes;
-  uint32_t first, nblk;
-  int slot;
-  const uint8_t* data;  // device address of the chunk's bytes
-};
-}  // namespace
+using Chunk = RegChunk;
+
+// The chunks of a registration: device sources in chunks of up to
+// `dev_chunk` bytes (fingerprinted in place; their VERIFY / COPY work waits
+// for the whole registration), host sources in ring-slot chunks.
+static std::vector<Chunk> make_chunks(const Ctx& c, const Fn& f) {
+  std::vector<Chunk> chunks;
+  for (uint32_t b = 0; b < f.srcs.size(); b++) {
+    const uint64_t step = f.srcs[b].dev ? std::max<uint64_t>(std::min<uint64_t>(f.srcs[b].n, c.dev_chunk), 1)
+                                        : c.ring.chunk;
+    for (uint64_t off = 0; off < f.srcs[b].n; off += step) {
+      Chunk ch{};
+      ch.blob = b;
+      ch.off = off;
+      ch.bytes = std::min<uint64_t>(step, f.srcs[b].n - off);
+      ch.first = f.blob_first[b] + (uint32_t)(off / kBlock);
+      ch.nblk = (uint32_t)((ch.bytes + kBlock - 1) / kBlock);
+      ch.slot = -1;
+      chunks.push_back(ch);
+    }
+  }
+  return chunks;
+}
+
+// Fingerprints of a device-source chunk into ring slot `slot`, in place, on
+// the control stream: one after another and after the previous
+// registration's COPY, so the HBM-bound kernels run one at a time at full
+// bandwidth instead of sharing it.
+static void issue_dev_chunk(Ctx& c, const Fn& f, Chunk& ch, int slot) {
+  Ring& R = c.ring;
+  ch.slot = slot;
+  HIPX(hipEventSynchronize(R.ev[slot]));  // e.g. a progressive reload still reading the slot
+  ring_reserve(c, slot, ch.nblk);
+  ch.data = f.srcs[ch.blob].p + ch.off;
+  hipStream_t s = c.ctl;
+  const int tok = c.timer.start("fp64k", s, 1);
+  HIPX(launch_fp64k(ch.data, ch.bytes, R.dfp[slot], c.max_groups_stream(), s));
+  c.timer.stop(tok, s);
+  HIPX(hipMemcpyAsync(R.hfp[slot], R.dfp[slot], ch.nblk * 8, hipMemcpyDeviceToHost, s));
+  HIPX(hipEventRecord(R.ev[slot], s));
+}
+
+bool register_prefetch(Ctx& c, Fn& f) {
+  Ring& R = c.ring;
+  if (!c.cfg.share || f.srcs.empty() || !f.pre.empty()) return false;
+  for (const Src& sr : f.srcs)
+    if (!sr.dev) return false;
+  std::vector<Chunk> chunks = make_chunks(c, f);
+  std::vector<int> avail;
+  for (int s = (int)R.slots; s-- > 0;)
+    if (!R.held[s]) avail.push_back(s);
+  // one slot stays free for the registration that runs meanwhile
+  if (chunks.empty() || chunks.size() + 1 > avail.size()) return false;
+  try {
+    for (Chunk& ch : chunks) {
+      const int slot = avail.back();
+      avail.pop_back();
+      R.held[slot] = 1;
+      issue_dev_chunk(c, f, ch, slot);
+    }
+  } catch (...) {
+    (void)hipStreamSynchronize(c.ctl);
+    for (const Chunk& ch : chunks)
+      if (ch.slot >= 0) R.held[ch.slot] = 0;
+    throw;
+  }
+  f.pre = std::move(chunks);
+  return true;
+}
+
+void register_drop_prefetch(Ctx& c, Fn& f) {
+  if (f.pre.empty()) return;
+  (void)hipStreamSynchronize(c.ctl);  // the fingerprints write the slots' buffers
+  for (const Chunk& ch : f.pre) c.ring.held[ch.slot] = 0;
+  f.pre.clear();
+}
 
 // The data branch of fn_register with sharing on.  Chunks stream through
 // the ring: H2D (or the device source in place) -> fingerprints -> D2H, up
@@ -227,23 +295,11 @@ struct Chunk {
 void register_shared(Ctx& c, Fn& f) {
   Pool& P = c.pool;
   Ring& R = c.ring;
-  std::vector<Chunk> chunks;
-  for (uint32_t b = 0; b < f.srcs.size(); b++) {
-    // device sources need no staging: they are fingerprinted in large chunks
-    // in place, and their VERIFY / COPY work waits for the whole registration
-    const uint64_t step = f.srcs[b].dev ? std::max<uint64_t>(std::min<uint64_t>(f.srcs[b].n, c.dev_chunk), 1)
-                                        : R.chunk;
-    for (uint64_t off = 0; off < f.srcs[b].n; off += step) {
-      Chunk ch{};
-      ch.blob = b;
-      ch.off = off;
-      ch.bytes = std::min<uint64_t>(step, f.srcs[b].n - off);
-      ch.first = f.blob_first[b] + (uint32_t)(off / kBlock);
-      ch.nblk = (uint32_t)((ch.bytes + kBlock - 1) / kBlock);
-      ch.slot = -1;
-      chunks.push_back(ch);
-    }
-  }
+  // chunks fingerprinted ahead (register_prefetch) are already in flight,
+  // each in the slot it holds
+  const size_t n_pre = f.pre.size();
+  std::vector<Chunk> chunks = n_pre ? std::move(f.pre) : make_chunks(c, f);
+  f.pre.clear();
   f.cls.assign(f.n_blocks, kNone);
   f.fps.assign(f.n_blocks, 0);
   std::vector<uint32_t> created;
@@ -251,8 +307,9 @@ void register_shared(Ctx& c, Fn& f) {
   // stamped and never chosen as eviction victims while it runs
   const uint32_t mark = P.new_mark();
   auto protect = [&](uint32_t cl) { return P.cls[cl].mark == mark; };
-  std::vector<int> free_slots;
-  for (int s = (int)R.slots; s-- > 0;) free_slots.push_back(s);
+  std::vector<int> free_slots;  // not held by a chunk fingerprinted ahead (this function's or the next one's)
+  for (int s = (int)R.slots; s-- > 0;)
+    if (!R.held[s]) free_slots.push_back(s);
 
   auto stream_of = [&](int slot) { return c.streams[slot % c.streams.size()]; };
 
@@ -304,28 +361,26 @@ void register_shared(Ctx& c, Fn& f) {
   }
 
   auto issue = [&](Chunk& ch) {
-    ch.slot = free_slots.back();
+    const int slot = free_slots.back();
     free_slots.pop_back();
+    const Src& src = f.srcs[ch.blob];
+    if (src.dev) {
+      issue_dev_chunk(c, f, ch, slot);
+      return;
+    }
+    ch.slot = slot;
     HIPX(hipEventSynchronize(R.ev[ch.slot]));  // e.g. a progressive reload still reading the slot
     ring_reserve(c, ch.slot, ch.nblk);
-    const Src& src = f.srcs[ch.blob];
-    // device chunks are fingerprinted on the control stream, one after
-    // another and after the previous registration's COPY: the HBM-bound
-    // kernels run one at a time at full bandwidth instead of sharing it;
     // staged chunks keep their slot's stream for the host-to-device copies
-    hipStream_t s = src.dev ? c.ctl : stream_of(ch.slot);
-    if (src.dev) {
-      ch.data = src.p + ch.off;
-    } else {
-      HIPX(hipStreamWaitEvent(s, R.ev_c[ch.slot], 0));  // the slot's last COPY has read its data
-      const uint8_t* hsrc = src.p + ch.off;
-      if (!src.pinned) {
-        fill_parallel(c, R.host[ch.slot], hsrc, ch.bytes);
-        hsrc = R.host[ch.slot];
-      }
-      HIPX(hipMemcpyAsync(R.dev[ch.slot], hsrc, ch.bytes, hipMemcpyHostToDevice, s));
-      ch.data = R.dev[ch.slot];
+    hipStream_t s = stream_of(ch.slot);
+    HIPX(hipStreamWaitEvent(s, R.ev_c[ch.slot], 0));  // the slot's last COPY has read its data
+    const uint8_t* hsrc = src.p + ch.off;
+    if (!src.pinned) {
+      fill_parallel(c, R.host[ch.slot], hsrc, ch.bytes);
+      hsrc = R.host[ch.slot];
     }
+    HIPX(hipMemcpyAsync(R.dev[ch.slot], hsrc, ch.bytes, hipMemcpyHostToDevice, s));
+    ch.data = R.dev[ch.slot];
     const int tok = c.timer.start("fp64k", s, 1);
     HIPX(launch_fp64k(ch.data, ch.bytes, R.dfp[ch.slot], c.max_groups_stream(), s));
     c.timer.stop(tok, s);
@@ -553,15 +608,17 @@ void register_shared(Ctx& c, Fn& f) {
   try {
     std::deque<size_t> inflight;
     size_t next = 0;
+    for (; next < n_pre; next++) inflight.push_back(next);
     while (next < chunks.size() || !inflight.empty()) {
       while (next < chunks.size() && !free_slots.empty()) {
         issue(chunks[next]);
         inflight.push_back(next++);
       }
-      Chunk& ch = chunks[inflight.front()];
+      const size_t i = inflight.front();
       inflight.pop_front();
-      process(ch);
-      free_slots.push_back(ch.slot);
+      process(chunks[i]);
+      if (i < n_pre) R.held[chunks[i].slot] = 0;
+      free_slots.push_back(chunks[i].slot);
     }
     start_deferred();
     count_in();  // optimistic for the deferred VERIFYs: corrected above if one fails
@@ -569,6 +626,7 @@ void register_shared(Ctx& c, Fn& f) {
   } catch (...) {
     for (hipStream_t s : c.streams) (void)hipStreamSynchronize(s);
     (void)hipStreamSynchronize(c.ctl);
+    for (size_t i = 0; i < n_pre; i++) R.held[chunks[i].slot] = 0;  // prefetched chunks not processed yet
     if (counted)
       for (uint32_t cl : f.cls) P.cls[cl].members--;
     for (uint32_t cl : created) P.drop_class(cl);

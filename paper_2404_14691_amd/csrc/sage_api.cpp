@@ -362,6 +362,79 @@ void sage_host_free(sage_ctx* p, void* q) {
 }
 
 // ------------------------------------------------------------- functions
+// A function's record before its data is in: sources, block count, ready
+// event and (sharing on) its block table from the device cache.
+static std::unique_ptr<Fn> new_fn(Ctx& c, const sage_fn_desc& desc, const sage_blob* blobs, size_t n_blobs) {
+  auto f = std::make_unique<Fn>();
+  f->id = c.next_id++;
+  f->d = desc;
+  uint32_t first = 0;
+  for (size_t i = 0; i < n_blobs; i++) {
+    const sage_blob& b = blobs[i];
+    const bool dev = b.where == SAGE_SRC_DEVICE;
+    f->srcs.push_back(Src{(const uint8_t*)b.src, b.nbytes, dev, !dev && c.is_pinned(b.src, b.nbytes)});
+    f->blob_first.push_back(first);
+    first += (uint32_t)((b.nbytes + kBlock - 1) / kBlock);
+    f->ro_bytes += b.nbytes;
+  }
+  f->n_blocks = first;
+  HIPX(hipEventCreateWithFlags(&f->ready, hipEventDisableTiming));
+  // the block table comes from the device cache (no hipMalloc/hipFree per function)
+  if (c.cfg.share) {
+    try {
+      f->d_table = (uint64_t*)c.cache.get(std::max<size_t>(8, (size_t)f->n_blocks * 8));
+    } catch (...) {
+      (void)hipEventDestroy(f->ready);
+      throw;
+    }
+  }
+  return f;
+}
+
+// Release what a record that is not (or no longer) being registered holds.
+static void drop_fn_shell(Ctx& c, Fn& F) {
+  register_drop_prefetch(c, F);
+  if (F.d_table) c.cache.put(F.d_table);
+  F.d_table = nullptr;
+  if (F.ready) (void)hipEventDestroy(F.ready);
+  F.ready = nullptr;
+}
+
+// The two setup branches of a registration: code (module) and data (the
+// blobs).  On failure the record's resources are released.  Returns the
+// code branch's time.
+static double register_fn(Ctx& c, Fn& F) {
+  double t_code = 0;
+  auto code = [&] {
+    const double t0 = now_ms();
+    F.mod = load_module(c, F.d.kind);
+    t_code = now_ms() - t0;
+  };
+  auto data = [&] {
+    if (c.cfg.share) register_shared(c, F);
+  };
+  try {
+    run_two_branches(code, data, c.cfg.serial_setup != 0, &c.worker);
+    if (c.cfg.share) refresh_table(c, F);
+    HIPX(hipEventRecord(F.ready, c.ctl));
+  } catch (...) {
+    (void)hipStreamSynchronize(c.ctl);
+    drop_fn_shell(c, F);
+    throw;
+  }
+  return t_code;
+}
+
+static sage_fn commit_fn(Ctx& c, std::unique_ptr<Fn> f, double t_code, double ms) {
+  const sage_fn id = f->id;
+  c.logical += f->ro_bytes;
+  c.registrations++;
+  c.t_code += t_code;
+  c.t_register += ms;
+  c.fns[id] = std::move(f);
+  return id;
+}
+
 sage_status fn_register(sage_ctx* p, const sage_fn_desc* desc, const sage_blob* blobs, size_t n_blobs,
                         sage_fn* out) {
   return guard([&] {
@@ -372,49 +445,64 @@ sage_status fn_register(sage_ctx* p, const sage_fn_desc* desc, const sage_blob* 
     HIPX(hipSetDevice(c.device));
     validate(*desc, blobs, n_blobs);
     advance_exit(c);
-    auto f = std::make_unique<Fn>();
-    f->id = c.next_id++;
-    f->d = *desc;
-    uint32_t first = 0;
-    for (size_t i = 0; i < n_blobs; i++) {
-      const sage_blob& b = blobs[i];
-      const bool dev = b.where == SAGE_SRC_DEVICE;
-      f->srcs.push_back(Src{(const uint8_t*)b.src, b.nbytes, dev, !dev && c.is_pinned(b.src, b.nbytes)});
-      f->blob_first.push_back(first);
-      first += (uint32_t)((b.nbytes + kBlock - 1) / kBlock);
-      f->ro_bytes += b.nbytes;
-    }
-    f->n_blocks = first;
-    HIPX(hipEventCreateWithFlags(&f->ready, hipEventDisableTiming));
-    Fn& F = *f;
-    // the block table comes from the device cache (no hipMalloc/hipFree per function)
-    if (c.cfg.share) F.d_table = (uint64_t*)c.cache.get(std::max<size_t>(8, (size_t)F.n_blocks * 8));
-    // code branch: module; data branch: the blobs
-    double t_code = 0;
-    auto code = [&] {
-      const double t0 = now_ms();
-      F.mod = load_module(c, F.d.kind);
-      t_code = now_ms() - t0;
-    };
-    auto data = [&] {
-      if (c.cfg.share) register_shared(c, F);
-    };
+    auto f = new_fn(c, *desc, blobs, n_blobs);
+    const double t_code = register_fn(c, *f);
+    *out = commit_fn(c, std::move(f), t_code, now_ms() - t_start);
+  });
+}
+
+// Unregister a function with no live setups.
+static void unregister_fn(Ctx& c, sage_fn id) {
+  Fn& f = fn_of(c, id);
+  for (size_t i = 0; i < c.flights.size(); i++) finish_flight(c, (int)i);
+  // copies from f's sources or host-cache copies may still be in flight;
+  // the caller may free the sources on return
+  HIPX(hipEventSynchronize(f.ready));
+  settle_reloads(c, true);
+  Pool& P = c.pool;
+  for (uint32_t cl : f.cls) P.cls[cl].members--;
+  for (uint32_t cl : f.distinct)
+    if (P.cls[cl].members == 0) P.drop_class(cl);
+  c.logical -= f.ro_bytes;
+  if (f.d_table) c.cache.put(f.d_table);
+  (void)hipEventDestroy(f.ready);
+  for (hipEvent_t e : f.seg) (void)hipEventDestroy(e);
+  c.fns.erase(id);
+}
+
+sage_status fn_register_batch(sage_ctx* p, size_t n, const sage_fn_desc* descs, const sage_blob* const* blobs,
+                              const size_t* n_blobs, sage_fn* out, double* register_ms) {
+  return guard([&] {
+    Ctx& c = ctx_of(p);
+    if (n == 0) return;
+    if (!descs || !blobs || !n_blobs || !out) fail(SAGE_EINVAL, "null argument");
+    std::lock_guard<std::recursive_mutex> lk(c.mu);
+    double t = now_ms();
+    HIPX(hipSetDevice(c.device));
+    for (size_t i = 0; i < n; i++) validate(descs[i], blobs[i], n_blobs[i]);
+    advance_exit(c);
+    std::vector<std::unique_ptr<Fn>> fs;
+    std::vector<sage_fn> ids;
     try {
-      run_two_branches(code, data, c.cfg.serial_setup != 0, &c.worker);
-      if (c.cfg.share) refresh_table(c, F);
-      HIPX(hipEventRecord(F.ready, c.ctl));
+      for (size_t i = 0; i < n; i++) fs.push_back(new_fn(c, descs[i], blobs[i], n_blobs[i]));
+      // each function's device-source fingerprints go out before the
+      // previous function's host classification, so the two overlap
+      register_prefetch(c, *fs[0]);
+      for (size_t i = 0; i < n; i++) {
+        if (i + 1 < n) register_prefetch(c, *fs[i + 1]);
+        const double t_code = register_fn(c, *fs[i]);
+        const double t1 = now_ms();
+        if (register_ms) register_ms[i] = t1 - t;
+        ids.push_back(commit_fn(c, std::move(fs[i]), t_code, t1 - t));
+        t = t1;
+      }
     } catch (...) {
-      (void)hipStreamSynchronize(c.ctl);
-      if (F.d_table) c.cache.put(F.d_table);
-      (void)hipEventDestroy(F.ready);
+      for (auto& f : fs)
+        if (f) drop_fn_shell(c, *f);
+      for (sage_fn id : ids) unregister_fn(c, id);  // all or nothing
       throw;
     }
-    c.logical += F.ro_bytes;
-    c.registrations++;
-    c.t_code += t_code;
-    c.t_register += now_ms() - t_start;
-    *out = F.id;
-    c.fns[F.id] = std::move(f);
+    for (size_t i = 0; i < n; i++) out[i] = ids[i];
   });
 }
 
@@ -425,20 +513,7 @@ sage_status fn_unregister(sage_ctx* p, sage_fn id) {
     Fn& f = fn_of(c, id);
     const double t0 = now_ms();
     if (f.live > 0) fail(SAGE_EBUSY, "function has %d live setups", f.live);
-    for (size_t i = 0; i < c.flights.size(); i++) finish_flight(c, (int)i);
-    // copies from f's sources or host-cache copies may still be in flight;
-    // the caller may free the sources on return
-    HIPX(hipEventSynchronize(f.ready));
-    settle_reloads(c, true);
-    Pool& P = c.pool;
-    for (uint32_t cl : f.cls) P.cls[cl].members--;
-    for (uint32_t cl : f.distinct)
-      if (P.cls[cl].members == 0) P.drop_class(cl);
-    c.logical -= f.ro_bytes;
-    if (f.d_table) c.cache.put(f.d_table);
-    (void)hipEventDestroy(f.ready);
-    for (hipEvent_t e : f.seg) (void)hipEventDestroy(e);
-    c.fns.erase(id);
+    unregister_fn(c, id);
     c.t_unregister += now_ms() - t0;
   });
 }

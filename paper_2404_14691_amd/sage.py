@@ -109,6 +109,8 @@ _sigs = {
     "sage_host_free": (None, [_P, _P]),
     "fn_register": (C.c_int, [_P, C.POINTER(sage_fn_desc), C.POINTER(sage_blob), C.c_size_t,
                               C.POINTER(C.c_uint64)]),
+    "fn_register_batch": (C.c_int, [_P, C.c_size_t, C.POINTER(sage_fn_desc), C.POINTER(C.POINTER(sage_blob)),
+                                    C.POINTER(C.c_size_t), C.POINTER(C.c_uint64), C.POINTER(C.c_double)]),
     "fn_unregister": (C.c_int, [_P, C.c_uint64]),
     "fn_setup": (C.c_int, [_P, C.c_uint64, C.c_uint32, C.POINTER(C.c_uint64)]),
     "fn_invoke": (C.c_int, [_P, C.c_uint64, _P, C.c_size_t, _P, C.c_size_t, C.c_uint32]),
@@ -231,6 +233,22 @@ def fn_register(ctx: int, desc: sage_fn_desc, blobs) -> int:
     out = C.c_uint64()
     _check(_lib.fn_register(ctx, C.byref(desc), arr, len(blobs), C.byref(out)), "fn_register")
     return out.value
+
+
+def fn_register_batch(ctx: int, descs, blob_lists):
+    """Register len(descs) functions in one pipelined call; returns (handles,
+    per-function registration ms)."""
+    n = len(descs)
+    if n != len(blob_lists):
+        raise ValueError("one blob list per descriptor")
+    darr = (sage_fn_desc * n)(*descs)
+    barrs = [(sage_blob * len(b))(*b) for b in blob_lists]
+    ptrs = (C.POINTER(sage_blob) * n)(*[C.cast(a, C.POINTER(sage_blob)) for a in barrs])
+    counts = (C.c_size_t * n)(*[len(b) for b in blob_lists])
+    out = (C.c_uint64 * n)()
+    ms = (C.c_double * n)()
+    _check(_lib.fn_register_batch(ctx, n, darr, ptrs, counts, out, ms), "fn_register_batch")
+    return list(out), list(ms)
 
 
 def fn_unregister(ctx: int, fn: int) -> None:

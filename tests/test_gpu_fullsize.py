@@ -55,7 +55,9 @@ def test_sharing_workload_full_size(sage_ctx_factory, torch_cuda):
     dev = [torch.from_numpy(b.view(np.uint8)).cuda() for b in w.blobs]
     torch.cuda.synchronize()
     desc = S.mlp_desc(S.SAGE_MLP_BF16, 8, 4096)
-    fns = [S.fn_register(ctx, desc, [S.make_blob(d.data_ptr(), d.numel(), where=S.SAGE_SRC_DEVICE)]) for d in dev]
+    # one batch call, as the benchmark registers them
+    fns, _ = S.fn_register_batch(ctx, [desc] * 4, [[S.make_blob(d.data_ptr(), d.numel(), where=S.SAGE_SRC_DEVICE)]
+                                                   for d in dev])
     for f, b in zip(fns, w.blobs):
         assert np.array_equal(S.sage_fn_fingerprints(ctx, f), OF.fp64k_blob(b))
     canon = OD.partition_dict(w.blobs, 65536)

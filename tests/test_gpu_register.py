@@ -202,3 +202,121 @@ def test_device_source_across_chunks(sage_ctx_factory, torch_cuda, monkeypatch, 
     for f in fns:
         S.fn_unregister(ctx, f)
 
+
+
+def _source(S, ctx, b, where, torch, keep):
+    if where == "host":
+        return S.make_blob(b)
+    if where == "pinned":
+        arr = S.pinned_array(ctx, b.shape, b.dtype)
+        arr[:] = b
+        keep.append(arr)
+        return S.make_blob(arr)
+    d = torch.from_numpy(b.view(np.uint8)).cuda()
+    torch.cuda.synchronize()
+    keep.append(d)
+    return S.make_blob(d.data_ptr(), b.nbytes, where=S.SAGE_SRC_DEVICE)
+
+
+@pytest.mark.parametrize("mix,dev_chunk", [("device", None), ("device", "524288"), ("mixed", None)])
+def test_register_batch_matches_oracle_and_one_by_one(sage_ctx_factory, torch_cuda, monkeypatch, mix, dev_chunk):
+    """fn_register_batch: fingerprints, the dedup partition, the pool bytes and
+    the accounting bit-exact against the oracle, and every function's outputs
+    the same bits as after one-by-one registration.  Device sources are
+    fingerprinted ahead of the previous function's classification (with
+    512 KiB device chunks the later functions find too few free ring slots
+    and go one by one); a mix of device, pinned and pageable sources."""
+    from paper_2404_14691_amd import sage as S
+    from oracle import mlp as OM
+    torch = torch_cuda
+    if dev_chunk:
+        monkeypatch.setenv("SAGE_DEV_CHUNK_BYTES", dev_chunk)
+    blobs = _blobs()
+    wheres = ["device"] * 3 if mix == "device" else ["device", "pinned", "host"]
+    desc = S.mlp_desc(S.SAGE_MLP_BF16, LAYERS, WIDTH)
+    outs = []
+    for batch in (True, False):
+        ctx = sage_ctx_factory(chunk_bytes=256 << 10, ring_slots=8 if dev_chunk else 3, streams=2)
+        keep = []
+        srcs = [[_source(S, ctx, b, w, torch, keep)] for b, w in zip(blobs, wheres)]
+        if batch:
+            fns, ms = S.fn_register_batch(ctx, [desc] * 3, srcs)
+            assert len(set(fns)) == 3 and all(m > 0 for m in ms)
+            _check_against_oracle(S, ctx, fns, blobs)
+        else:
+            fns = [S.fn_register(ctx, desc, s) for s in srcs]
+        ys = []
+        for i, f in enumerate(fns):
+            x = synth.bf16_inputs(5, WIDTH, 6, i)
+            inv = S.fn_setup(ctx, f, 5)
+            y = np.zeros((5, WIDTH), dtype=np.float32)
+            S.fn_invoke(ctx, inv, x, y)
+            S.fn_release(ctx, inv)
+            W = OM.bf16_to_f64(blobs[i]).reshape(LAYERS, WIDTH, WIDTH)
+            assert OM.normwise_error(y, OM.mlp_forward(OM.bf16_to_f64(x), W)) <= 2e-2
+            ys.append(y)
+        outs.append(ys)
+        for f in fns:
+            S.fn_unregister(ctx, f)
+        st = S.sage_get_stats(ctx)
+        assert st["classes"] == 0 and st["logical_bytes"] == 0
+        for a in keep:
+            if isinstance(a, np.ndarray):
+                S.sage_host_free(ctx, a.ctypes.data)
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+def _status(fn, *args):
+    from paper_2404_14691_amd import sage as S
+    try:
+        fn(*args)
+    except S.SageError as e:
+        return e.status
+    return S.SAGE_OK
+
+
+def test_register_batch_all_or_nothing(sage_ctx_factory, torch_cuda):
+    """A batch whose second function cannot be placed (the pool is held by a
+    live setup of another function) fails with ENOMEM and leaves no function
+    of the batch behind: the first one, already registered, is taken out
+    again.  The held function is untouched and still computes; a batch that
+    fits registers afterwards (the ring slots held for fingerprints taken
+    ahead were given back)."""
+    from paper_2404_14691_amd import sage as S
+    from oracle import mlp as OM
+    torch = torch_cuda
+    ctx = sage_ctx_factory(pool_budget_bytes=48 * 65536)
+    mk = lambda width, seed: synth.shared_mlp_bf16_functions(n_fns=1, layers=2, width=width, share_frac=0.0,
+                                                             seed=seed).blobs[0]
+    wa, wb, wc, wd = mk(512, 41), mk(256, 42), mk(1024, 43), mk(256, 44)  # 16, 4, 64 and 4 blocks
+    fa = S.fn_register(ctx, S.mlp_desc(S.SAGE_MLP_BF16, 2, 512), [S.make_blob(wa)])
+    inv = S.fn_setup(ctx, fa, 2)  # holds its 16 blocks: 32 of the 48 slots are left
+    st0 = S.sage_get_stats(ctx)
+    keep = []
+    src = lambda w: [_source(S, ctx, w, "device", torch, keep)]
+    descs = [S.mlp_desc(S.SAGE_MLP_BF16, 2, 256), S.mlp_desc(S.SAGE_MLP_BF16, 2, 1024)]
+    assert _status(S.fn_register_batch, ctx, descs, [src(wb), src(wc)]) == S.SAGE_ENOMEM
+    st1 = S.sage_get_stats(ctx)
+    for k in ("logical_bytes", "unique_bytes", "classes", "resident_bytes", "refcount_sum", "live_setups"):
+        assert st1[k] == st0[k], k
+    x = synth.bf16_inputs(2, 512, 41, 0)
+    y = np.zeros((2, 512), dtype=np.float32)
+    S.fn_invoke(ctx, inv, x, y)
+    W = OM.bf16_to_f64(wa).reshape(2, 512, 512)
+    assert OM.normwise_error(y, OM.mlp_forward(OM.bf16_to_f64(x), W)) <= 2e-2
+    fns, _ = S.fn_register_batch(ctx, [descs[0]] * 2, [src(wb), src(wd)])
+    for f, w in zip(fns, (wb, wd)):
+        assert np.array_equal(S.sage_fn_fingerprints(ctx, f), OF.fp64k_blob(w))
+        S.fn_unregister(ctx, f)
+    S.fn_release(ctx, inv)
+    S.fn_unregister(ctx, fa)
+
+
+def test_register_batch_empty_and_null(sage_ctx_factory, torch_cuda):
+    import ctypes as C
+    from paper_2404_14691_amd import sage as S
+    ctx = sage_ctx_factory()
+    assert S.fn_register_batch(ctx, [], []) == ([], [])
+    out = (C.c_uint64 * 1)()
+    assert S._lib.fn_register_batch(ctx, 1, None, None, None, out, None) == S.SAGE_EINVAL
