@@ -841,10 +841,26 @@ sage_status sage_mfma_ceiling(sage_ctx* p, uint32_t k, uint32_t reps, double* us
     if (k == 0 || k % 32 || k > 65536 || reps == 0 || reps > 1000) fail(SAGE_EINVAL, "k %u or reps %u out of range", k, reps);
     std::lock_guard<std::recursive_mutex> lk(c.mu);
     const uint32_t grid = (uint32_t)c.cus;
-    float* out = static_cast<float*>(c.cache.get((size_t)grid * 512 * sizeof(float)));
-    auto* clk = static_cast<unsigned long long*>(c.cache.get((size_t)grid * 2 * sizeof(unsigned long long)));
     hipStream_t s = c.ctl;
+    float* out = nullptr;
+    unsigned long long* clk = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
+    struct Release {  // on every way out, after the stream has drained
+      Ctx& c;
+      hipStream_t s;
+      float*& out;
+      unsigned long long*& clk;
+      hipEvent_t &e0, &e1;
+      ~Release() {
+        (void)hipStreamSynchronize(s);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (out) c.cache.put(out);
+        if (clk) c.cache.put(clk);
+      }
+    } release{c, s, out, clk, e0, e1};
+    out = static_cast<float*>(c.cache.get((size_t)grid * 512 * sizeof(float)));
+    clk = static_cast<unsigned long long*>(c.cache.get((size_t)grid * 2 * sizeof(unsigned long long)));
     HIPX(hipEventCreate(&e0));
     HIPX(hipEventCreate(&e1));
     HIPX(launch_mfma_ceiling(grid, k / 32, out, clk, s));  // warm-up
@@ -857,10 +873,6 @@ sage_status sage_mfma_ceiling(sage_ctx* p, uint32_t k, uint32_t reps, double* us
     std::vector<unsigned long long> h((size_t)grid * 2);
     HIPX(hipMemcpyAsync(h.data(), clk, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     HIPX(hipStreamSynchronize(s));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    c.cache.put(out);
-    c.cache.put(clk);
     std::vector<double> ghz;
     for (uint32_t g = 0; g < grid; g++)
       if (h[2 * g + 1]) ghz.push_back((double)h[2 * g] / (double)h[2 * g + 1] * 0.1);  // reference clock 100 MHz
