@@ -85,6 +85,53 @@ def test_blkcopy_copy_and_verify(sage_ctx_factory, torch_cuda):
     assert res.cpu().tolist() == [0, 0, 1, 1]
 
 
+def test_blkcopy_launch_larger_than_one_wave(sage_ctx_factory, torch_cuda):
+    """More operations than one wave of workgroups (32 per CU): the launch
+    takes blocks two at a time, full-block COPY pairs on the fast path and
+    partial COPYs and VERIFYs mixed in; every destination block is checked."""
+    from paper_2404_14691_amd import sage as S
+    torch = torch_cuda
+    ctx = sage_ctx_factory()
+    n = torch.cuda.get_device_properties(0).multi_processor_count * 32 + 37
+    rng = np.random.default_rng(11)
+    nsrc = 64
+    src = rng.integers(0, 256, nsrc * 65536, dtype=np.uint8)
+    dsrc = _dev(torch, src)
+    dst = torch.full((n * 65536,), 0xA5, dtype=torch.uint8, device="cuda")
+    ops = np.zeros(n, dtype=[("src", "<u8"), ("dst", "<u8"), ("len", "<u4"), ("op", "<u4")])
+    kind = np.zeros(n, dtype=np.int64)  # 0 full COPY, 1 partial COPY, 2 VERIFY equal, 3 VERIFY different
+    for i in range(n):
+        j = i % nsrc
+        if i % 97 == 5:
+            kind[i] = 2
+            ops[i] = (dsrc.data_ptr() + j * 65536, dsrc.data_ptr() + j * 65536, 65536, S.SAGE_OP_VERIFY)
+        elif i % 97 == 6:
+            kind[i] = 3
+            ops[i] = (dsrc.data_ptr() + j * 65536, dsrc.data_ptr() + ((j + 1) % nsrc) * 65536, 65536,
+                      S.SAGE_OP_VERIFY)
+        elif i % 89 == 7:
+            kind[i] = 1
+            ops[i] = (dsrc.data_ptr() + j * 65536, dst.data_ptr() + i * 65536, 1000, S.SAGE_OP_COPY)
+        else:
+            ops[i] = (dsrc.data_ptr() + j * 65536, dst.data_ptr() + i * 65536, 65536, S.SAGE_OP_COPY)
+    dops = _dev(torch, ops.view(np.uint8))
+    res = torch.full((n,), 7, dtype=torch.int32, device="cuda")
+    S.sage_blkcopy(ctx, dops.data_ptr(), n, res.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    out = dst.cpu().numpy().reshape(n, 65536)
+    blocks = src.reshape(nsrc, 65536)
+    r = res.cpu().numpy()
+    for i in range(n):
+        j = i % nsrc
+        if kind[i] == 0:
+            assert np.array_equal(out[i], blocks[j]), i
+        elif kind[i] == 1:
+            assert np.array_equal(out[i, :1000], blocks[j, :1000]) and np.all(out[i, 1000:] == 0xA5), i
+        else:
+            assert np.all(out[i] == 0xA5), i
+            assert r[i] == (0 if kind[i] == 2 else 1), i
+
+
 def test_mfma_ceiling_measurement(sage_ctx_factory, torch_cuda):
     """The compute-side ceiling measurement of the main GEMM tile runs,
     reports a positive time and a plausible shader clock, and scales with K;
