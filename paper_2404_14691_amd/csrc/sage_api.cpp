@@ -405,13 +405,17 @@ static void drop_fn_shell(Ctx& c, Fn& F) {
 // code branch's time.
 static double register_fn(Ctx& c, Fn& F) {
   double t_code = 0;
+  bool data_in = false;  // register_shared returned: the blocks are counted into their classes
   auto code = [&] {
     const double t0 = now_ms();
     F.mod = load_module(c, F.d.kind);
     t_code = now_ms() - t0;
   };
   auto data = [&] {
-    if (c.cfg.share) register_shared(c, F);
+    if (c.cfg.share) {
+      register_shared(c, F);
+      data_in = true;
+    }
   };
   try {
     run_two_branches(code, data, c.cfg.serial_setup != 0, &c.worker);
@@ -419,6 +423,12 @@ static double register_fn(Ctx& c, Fn& F) {
     HIPX(hipEventRecord(F.ready, c.ctl));
   } catch (...) {
     (void)hipStreamSynchronize(c.ctl);
+    if (data_in) {  // the other branch failed after the data was in: take the blocks out again
+      Pool& P = c.pool;
+      for (uint32_t cl : F.cls) P.cls[cl].members--;
+      for (uint32_t cl : F.distinct)
+        if (P.cls[cl].members == 0) P.drop_class(cl);
+    }
     drop_fn_shell(c, F);
     throw;
   }
