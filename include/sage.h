@@ -127,7 +127,8 @@ typedef struct {
   size_t ring_slots;         /* pinned staging slots for host->device (default 8; 1 = no pipelining) */
   size_t chunk_bytes;        /* bytes per staging slot, multiple of 64 KiB (default 8 MiB) */
   uint32_t streams;          /* copy/fingerprint streams (default 4) */
-  uint32_t fill_threads;     /* host threads copying pageable sources into staging (default 4) */
+  uint32_t fill_threads;     /* host threads copying pageable sources into staging, and host inputs /
+                                outputs of MLP launches over 1 MiB through theirs (default 4) */
   uint32_t inflight_groups;  /* grouped launches that may run concurrently (default 4) */
   uint32_t share;            /* 1 (default): shared block pool; 0: private copy per invocation */
   uint32_t batch;            /* 1 (default): grouped launches replayed from hipGraphs; 0: eager */

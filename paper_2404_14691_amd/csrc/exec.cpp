@@ -145,7 +145,10 @@ void finish_flight(Ctx& c, int f) {
   Flight& F = c.flights[f];
   if (!F.busy) return;
   HIPX(hipEventSynchronize(F.done));
-  for (auto& d : F.deliver) std::memcpy(d.first, F.h_out + d.second.first, d.second.second);
+  std::vector<HostCopy> out;
+  out.reserve(F.deliver.size());
+  for (auto& d : F.deliver) out.push_back({(uint8_t*)d.first, F.h_out + d.second.first, d.second.second});
+  copy_parallel(c, out);
   F.deliver.clear();
   F.busy = false;
   c.timer.collect();
@@ -257,6 +260,7 @@ int launch_mlp_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, int fl
   uint64_t* out_tab = in_tab + rows_cap;
   uint32_t row = 0, tiles = 0, ttiles = 0, ng = 0, nt = 0;
   F.deliver.clear();
+  std::vector<HostCopy> in_copies;  // host inputs into the pinned staging, copied after the loop
   for (size_t g = 0; g < tabs.size(); g++) {
     const uint32_t row0 = row;
     for (size_t i : members[g]) {
@@ -269,7 +273,7 @@ int launch_mlp_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, int fl
         out_tab[R] = host_out ? (uint64_t)(F.d_out + (size_t)R * W * 4)
                               : (uint64_t)((uint8_t*)cl.out + (size_t)r * W * 4);
       }
-      if (host_in) std::memcpy(F.h_in + (size_t)row * W * es_in, cl.in, (size_t)b * W * es_in);
+      if (host_in) in_copies.push_back({F.h_in + (size_t)row * W * es_in, (const uint8_t*)cl.in, (size_t)b * W * es_in});
       if (host_out) F.deliver.push_back({cl.out, {(size_t)row * W * 4, (size_t)b * W * 4}});
       row += b;
     }
@@ -289,6 +293,7 @@ int launch_mlp_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, int fl
       ttiles += ((part + plan.tail->bm - 1) / plan.tail->bm) * (W / plan.tail->bn);
     }
   }
+  copy_parallel(c, in_copies);
   *hdr = GemmHdr{ng, tiles, M, 0};
   *thdr = GemmHdr{nt, ttiles, M, 0};
   const bool split = nt > 0;

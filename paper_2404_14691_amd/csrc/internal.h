@@ -483,6 +483,12 @@ struct Ctx {
 void ring_init(Ctx& c);
 void ring_destroy(Ctx& c);
 void fill_parallel(Ctx& c, uint8_t* dst, const uint8_t* src, size_t n);
+struct HostCopy {
+  uint8_t* dst;
+  const uint8_t* src;
+  size_t n;
+};
+void copy_parallel(Ctx& c, const std::vector<HostCopy>& items);
 
 // Two setup branches: the code branch on `w` (or a new thread when w is
 // null), the data branch on the caller; serial runs code then data.

@@ -231,3 +231,33 @@ def test_allocation_failure_gives_enomem_without_side_effects(sage_ctx_factory, 
     S.fn_invoke(ok, inv, synth.bf16_inputs(3, 256, 34, 0), y)
     assert np.isfinite(y).all() and np.abs(y).sum() > 0
     S.fn_release(ok, inv)
+
+
+def test_host_io_batch_above_a_megabyte_same_bits_as_device_io(sage_ctx_factory, torch_cuda):
+    """A batched launch whose host inputs and outputs exceed 1 MiB is staged
+    by several host threads: every output equals the same launch's with
+    device inputs and outputs bit for bit, and sampled ones the oracle."""
+    from paper_2404_14691_amd import sage as S
+    from oracle import mlp as OM
+    torch = torch_cuda
+    W, L = 1024, 2
+    ctx = sage_ctx_factory()
+    w = synth.shared_mlp_bf16_functions(n_fns=2, layers=L, width=W, share_frac=0.2, seed=61).blobs
+    fns = [S.fn_register(ctx, S.mlp_desc(S.SAGE_MLP_BF16, L, W), [S.make_blob(b)]) for b in w]
+    batches = [int(b) for b in synth.uniform_batches(48, 1, 32, seed=61)]
+    xs = [synth.bf16_inputs(b, W, 61, i) for i, b in enumerate(batches)]
+    assert sum(x.nbytes for x in xs) > (1 << 20)
+    invs = [S.fn_setup(ctx, fns[i % 2], b) for i, b in enumerate(batches)]
+    ys = [np.zeros((b, W), dtype=np.float32) for b in batches]
+    S.fn_invoke_batch(ctx, invs, xs, ys)
+    dx = [torch.from_numpy(x).cuda() for x in xs]
+    dy = [torch.zeros((b, W), dtype=torch.float32, device="cuda") for b in batches]
+    torch.cuda.synchronize()
+    S.fn_invoke_batch(ctx, invs, [(t.data_ptr(), t.numel() * 2) for t in dx],
+                      [(t.data_ptr(), t.numel() * 4) for t in dy], S.SAGE_IO_DEVICE_IN | S.SAGE_IO_DEVICE_OUT)
+    S.fn_release_batch(ctx, invs)
+    for y, t in zip(ys, dy):
+        assert np.array_equal(y, t.cpu().numpy())
+    for i in (0, 17, 47):
+        Wm = OM.bf16_to_f64(w[i % 2]).reshape(L, W, W)
+        assert OM.normwise_error(ys[i], OM.mlp_forward(OM.bf16_to_f64(xs[i]), Wm)) <= 2e-2
