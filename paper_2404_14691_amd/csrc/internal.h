@@ -376,8 +376,39 @@ struct TuneEntry {
 };
 
 // Long-lived helper thread that runs the code branch of function setup.
+// One host copy (bytes from src to dst).
+struct HostCopy {
+  uint8_t* dst;
+  const uint8_t* src;
+  size_t n;
+};
+
+// Persistent host copy threads: the workers and the calling thread take the
+// pieces of one job round robin, and run() returns when all are copied.  One
+// job at a time (its callers hold the context's mutex).
+class CopyPool {
+ public:
+  ~CopyPool() { stop(); }
+  void start(size_t workers);
+  void stop();
+  void run(const std::vector<HostCopy>& pieces);
+
+ private:
+  void work();
+  std::vector<std::thread> th_;
+  std::mutex mu_;
+  std::condition_variable cv_, done_;
+  const HostCopy* job_ = nullptr;
+  size_t n_ = 0;
+  std::atomic<size_t> next_{0};
+  uint64_t gen_ = 0;
+  size_t busy_ = 0;
+  bool quit_ = false;
+};
+
 class Worker {
  public:
+  ~Worker() { stop(); }
   void start(int device);
   void stop();
   void run(std::function<void()> task);  // queue one task
@@ -463,6 +494,7 @@ struct Ctx {
   // reference under `mu` and keep the state alive while they wait on it
   std::shared_ptr<Serve> serve;
   Worker worker;                             // code branch of fn_register
+  CopyPool copier;                           // fill_threads - 1 host copy threads
   std::string force_tile;                    // SAGE_TILE: fixed GEMM tile shape (tests)
   std::string last_launch;                   // kernels and tiles of the last MLP launch
   bool test_fp_const = false;                // force every fingerprint equal (collision test)
@@ -483,11 +515,6 @@ struct Ctx {
 void ring_init(Ctx& c);
 void ring_destroy(Ctx& c);
 void fill_parallel(Ctx& c, uint8_t* dst, const uint8_t* src, size_t n);
-struct HostCopy {
-  uint8_t* dst;
-  const uint8_t* src;
-  size_t n;
-};
 void copy_parallel(Ctx& c, const std::vector<HostCopy>& items);
 
 // Two setup branches: the code branch on `w` (or a new thread when w is

@@ -109,46 +109,26 @@ static void ring_reserve(Ctx& c, int slot, size_t nblk) {
   R.cap[slot] = nblk;
 }
 
-// Host copy of a pageable source into pinned staging, split over threads.
-void fill_parallel(Ctx& c, uint8_t* dst, const uint8_t* src, size_t n) {
-  const size_t nt = std::max<uint32_t>(1, c.cfg.fill_threads);
-  if (nt == 1 || n < (1u << 20)) {
-    std::memcpy(dst, src, n);
-    return;
-  }
-  const size_t part = (n / nt + 4095) & ~size_t(4095);
-  std::vector<std::thread> th;
-  for (size_t i = 1; i < nt; i++) {
-    const size_t o = i * part;
-    if (o >= n) break;
-    th.emplace_back([=] { std::memcpy(dst + o, src + o, std::min(part, n - o)); });
-  }
-  std::memcpy(dst, src, std::min(part, n));
-  for (auto& t : th) t.join();
-}
+// Host copy of a pageable source into pinned staging, over the copy threads.
+void fill_parallel(Ctx& c, uint8_t* dst, const uint8_t* src, size_t n) { copy_parallel(c, {HostCopy{dst, src, n}}); }
 
-// Many host copies (a batched launch's host inputs into pinned staging, or
-// its outputs out of it), cut into pieces of at most 1 MiB that the fill
-// threads take round robin.  Below 1 MiB in all, one thread copies.
+// Many host copies (a pageable source into staging, a batched launch's host
+// inputs into pinned staging or its outputs out of it), cut into pieces of
+// at most 1 MiB that the context's copy threads and the caller take round
+// robin.  Below 1 MiB in all, the caller copies alone.
 void copy_parallel(Ctx& c, const std::vector<HostCopy>& items) {
   size_t total = 0;
   for (const HostCopy& it : items) total += it.n;
-  const size_t nt = std::max<uint32_t>(1, c.cfg.fill_threads);
-  if (nt == 1 || total < (1u << 20)) {
+  if (total < (1u << 20)) {
     for (const HostCopy& it : items) std::memcpy(it.dst, it.src, it.n);
     return;
   }
   constexpr size_t kPiece = 1u << 20;
   std::vector<HostCopy> pieces;
+  pieces.reserve(total / kPiece + items.size());
   for (const HostCopy& it : items)
     for (size_t o = 0; o < it.n; o += kPiece) pieces.push_back({it.dst + o, it.src + o, std::min(kPiece, it.n - o)});
-  auto run = [&pieces, nt](size_t k) {
-    for (size_t q = k; q < pieces.size(); q += nt) std::memcpy(pieces[q].dst, pieces[q].src, pieces[q].n);
-  };
-  std::vector<std::thread> th;
-  for (size_t k = 1; k < nt && k < pieces.size(); k++) th.emplace_back(run, k);
-  run(0);
-  for (auto& t : th) t.join();
+  c.copier.run(pieces);
 }
 
 // --------------------------------------------------------------- modules

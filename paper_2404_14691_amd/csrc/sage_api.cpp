@@ -224,6 +224,29 @@ sage_status sage_open(int device, const sage_config* cfg, sage_ctx** out) {
     if (c.cfg.ring_slots < 1 || c.cfg.chunk_bytes < kBlock || c.cfg.chunk_bytes % kBlock || c.cfg.streams < 1)
       fail(SAGE_EINVAL, "ring_slots >= 1, streams >= 1, chunk_bytes a multiple of 64 KiB");
     if (!(c.cfg.exit_stage_ms >= 0)) fail(SAGE_EINVAL, "exit_stage_ms must be >= 0");
+    // environment knobs (tests and measurements), checked before anything starts
+    if (const char* e = std::getenv("SAGE_TILE")) c.force_tile = e;
+    if (const char* e = std::getenv("SAGE_FAULT_ALLOC_AFTER")) {
+      const long long v = std::strtoll(e, nullptr, 0);
+      if (v < 0) fail(SAGE_EINVAL, "SAGE_FAULT_ALLOC_AFTER must be >= 0");
+      c.alloc_fault.left = v;
+    }
+    c.pool.fault = &c.alloc_fault;
+    c.cache.fault = &c.alloc_fault;
+    if (const char* e = std::getenv("SAGE_STENCIL_FUSE")) c.stencil_fuse = std::strtol(e, nullptr, 0) != 0;
+    if (const char* e = std::getenv("SAGE_F32_COLS")) {
+      c.f32_cols = (uint32_t)std::strtoul(e, nullptr, 0);
+      if (c.f32_cols != 4 && c.f32_cols != 8) fail(SAGE_EINVAL, "SAGE_F32_COLS must be 4 or 8");
+    }
+    if (const char* e = std::getenv("SAGE_DEV_CHUNK_BYTES")) {
+      const uint64_t v = std::strtoull(e, nullptr, 0);
+      if (v < kBlock || v % kBlock) fail(SAGE_EINVAL, "SAGE_DEV_CHUNK_BYTES must be a positive multiple of 65536");
+      c.dev_chunk = v;
+    }
+    if (const char* e = std::getenv("SAGE_TEST_FP_CONST")) {
+      c.test_fp_const = true;
+      c.test_fp_value = std::strtoull(e, nullptr, 0);
+    }
     int ndev = 0;
     HIPX(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) fail(SAGE_EINVAL, "device %d not present (%d devices)", device, ndev);
@@ -261,28 +284,7 @@ sage_status sage_open(int device, const sage_config* cfg, sage_ctx** out) {
     flights_init(c);
     tune_load(c);
     c.worker.start(device);
-    if (const char* e = std::getenv("SAGE_TILE")) c.force_tile = e;
-    if (const char* e = std::getenv("SAGE_FAULT_ALLOC_AFTER")) {
-      const long long v = std::strtoll(e, nullptr, 0);
-      if (v < 0) fail(SAGE_EINVAL, "SAGE_FAULT_ALLOC_AFTER must be >= 0");
-      c.alloc_fault.left = v;
-    }
-    c.pool.fault = &c.alloc_fault;
-    c.cache.fault = &c.alloc_fault;
-    if (const char* e = std::getenv("SAGE_STENCIL_FUSE")) c.stencil_fuse = std::strtol(e, nullptr, 0) != 0;
-    if (const char* e = std::getenv("SAGE_F32_COLS")) {
-      c.f32_cols = (uint32_t)std::strtoul(e, nullptr, 0);
-      if (c.f32_cols != 4 && c.f32_cols != 8) fail(SAGE_EINVAL, "SAGE_F32_COLS must be 4 or 8");
-    }
-    if (const char* e = std::getenv("SAGE_DEV_CHUNK_BYTES")) {
-      const uint64_t v = std::strtoull(e, nullptr, 0);
-      if (v < kBlock || v % kBlock) fail(SAGE_EINVAL, "SAGE_DEV_CHUNK_BYTES must be a positive multiple of 65536");
-      c.dev_chunk = v;
-    }
-    if (const char* e = std::getenv("SAGE_TEST_FP_CONST")) {
-      c.test_fp_const = true;
-      c.test_fp_value = std::strtoull(e, nullptr, 0);
-    }
+    c.copier.start(std::max<uint32_t>(1, c.cfg.fill_threads) - 1);
     *out = h.release();
   });
 }
@@ -292,6 +294,7 @@ sage_status sage_close(sage_ctx* p) {
     Ctx& c = ctx_of(p);
     serve_destroy(c);
     c.worker.stop();
+    c.copier.stop();
     {
       std::lock_guard<std::recursive_mutex> lk(c.mu);
       (void)hipSetDevice(c.device);

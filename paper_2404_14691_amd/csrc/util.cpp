@@ -240,6 +240,62 @@ void Worker::wait() {
   }
 }
 
+// ------------------------------------------------------ host copy threads
+void CopyPool::start(size_t workers) {
+  quit_ = false;
+  for (size_t i = 0; i < workers; i++)
+    th_.emplace_back([this] {
+      uint64_t seen = 0;
+      for (;;) {
+        {
+          std::unique_lock<std::mutex> lk(mu_);
+          cv_.wait(lk, [&] { return quit_ || gen_ != seen; });
+          if (quit_) return;
+          seen = gen_;
+        }
+        work();
+        std::lock_guard<std::mutex> lk(mu_);
+        if (--busy_ == 0) done_.notify_all();
+      }
+    });
+}
+
+void CopyPool::stop() {
+  {
+    std::lock_guard<std::mutex> lk(mu_);
+    quit_ = true;
+  }
+  cv_.notify_all();
+  for (auto& t : th_)
+    if (t.joinable()) t.join();
+  th_.clear();
+}
+
+void CopyPool::work() {
+  for (size_t q; (q = next_.fetch_add(1)) < n_;) std::memcpy(job_[q].dst, job_[q].src, job_[q].n);
+}
+
+void CopyPool::run(const std::vector<HostCopy>& pieces) {
+  if (th_.empty() || pieces.size() < 2) {
+    for (const HostCopy& p : pieces) std::memcpy(p.dst, p.src, p.n);
+    return;
+  }
+  {
+    std::lock_guard<std::mutex> lk(mu_);
+    job_ = pieces.data();
+    n_ = pieces.size();
+    next_ = 0;
+    busy_ = th_.size();
+    gen_++;
+  }
+  cv_.notify_all();
+  work();
+  std::unique_lock<std::mutex> lk(mu_);
+  done_.wait(lk, [&] { return busy_ == 0; });
+  job_ = nullptr;
+  n_ = 0;
+}
+
 void run_two_branches(const std::function<void()>& code, const std::function<void()>& data, bool serial,
                       Worker* w) {
   if (serial) {

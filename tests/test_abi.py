@@ -61,3 +61,16 @@ def test_selftest_rejects_bad_arguments():
     with pytest.raises(S.SageError) as e:
         S.sage_selftest_setup_overlap(-1, 0, 0, False)
     assert e.value.status == S.SAGE_EINVAL
+
+
+@pytest.mark.parametrize("knob,value", [("SAGE_F32_COLS", "5"), ("SAGE_DEV_CHUNK_BYTES", "1000"),
+                                        ("SAGE_FAULT_ALLOC_AFTER", "-1")])
+def test_bad_environment_knob_is_einval_before_anything_starts(monkeypatch, knob, value):
+    """A bad test knob makes sage_open return EINVAL (checked before any
+    device call or helper thread), not abort the process."""
+    from paper_2404_14691_amd import sage as S
+    monkeypatch.setenv(knob, value)
+    with pytest.raises(S.SageError) as e:
+        S.sage_open(0, S.sage_config_default())
+    assert e.value.status == S.SAGE_EINVAL
+    assert knob in str(e.value)
