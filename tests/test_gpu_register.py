@@ -106,24 +106,32 @@ def test_register_serial_and_unpipelined_agree(sage_ctx_factory, torch_cuda):
         assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("where", ["host", "device"])
+@pytest.mark.parametrize("where", ["host", "device", "device-batch"])
 def test_forced_fingerprint_collisions(sage_ctx_factory, torch_cuda, monkeypatch, where):
     """Every fingerprint forced to one value: only byte verification keeps
     blocks apart, and the partition is still the byte-exact one (staged
     chunks settle their VERIFYs chunk by chunk; device sources at the end of
-    the registration, after counting the blocks in optimistically)."""
+    the registration, after counting the blocks in optimistically; in one
+    fn_register_batch call, while the next function's fingerprints are
+    already out)."""
     from paper_2404_14691_amd import sage as S
     torch = torch_cuda
     monkeypatch.setenv("SAGE_TEST_FP_CONST", "12345")
-    ctx = sage_ctx_factory(chunk_bytes=256 << 10, ring_slots=2)
+    # three slots for the batch: one function's chunk in flight, the next one's fingerprinted ahead, one free
+    ctx = sage_ctx_factory(chunk_bytes=256 << 10, ring_slots=3 if where == "device-batch" else 2)
     monkeypatch.delenv("SAGE_TEST_FP_CONST")
     # BF16 MLP of width 256 and 8 layers: 1 MiB = the first 16 blocks of each blob
     blobs = [np.ascontiguousarray(b[: 8 * 256 * 256]) for b in _blobs()]
-    keep = [torch.from_numpy(b.view(np.uint8)).cuda() for b in blobs] if where == "device" else []
+    dev = where.startswith("device")
+    keep = [torch.from_numpy(b.view(np.uint8)).cuda() for b in blobs] if dev else []
     torch.cuda.synchronize()
-    srcs = [S.make_blob(d.data_ptr(), d.numel(), where=S.SAGE_SRC_DEVICE) for d in keep] if where == "device" \
+    srcs = [S.make_blob(d.data_ptr(), d.numel(), where=S.SAGE_SRC_DEVICE) for d in keep] if dev \
         else [S.make_blob(b) for b in blobs]
-    fns = [S.fn_register(ctx, S.mlp_desc(S.SAGE_MLP_BF16, 8, 256), [s]) for s in srcs]
+    desc = S.mlp_desc(S.SAGE_MLP_BF16, 8, 256)
+    if where == "device-batch":
+        fns, _ = S.fn_register_batch(ctx, [desc] * len(srcs), [[s_] for s_ in srcs])
+    else:
+        fns = [S.fn_register(ctx, desc, [s_]) for s_ in srcs]
     canon = OD.partition_dict(blobs, 65536)
     lib = [[(int(c),) for c in S.sage_fn_block_info(ctx, f)[0]] for f in fns]
     assert OD.same_partition(canon, lib)
