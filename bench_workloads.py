@@ -566,13 +566,17 @@ def rw_only(S, torch, log, reps=3, n_inv=8, nx=512, ny=512, nz=320, sweeps=20, c
 
 
 # ---------------------------------------------------------------- progressive setup
-def progressive(S, torch, log, reps=5, batches=(8, 2048), interval_ms=250.0):
+def progressive(S, torch, log, reps=5, batches=(8, 2048), interval_ms=250.0, rounds=5):
     """Per-kernel readiness: setup + invoke latency of one BF16 MLP
     (8 x 4096^2, 256 MiB) whose blocks must all come back, with the whole
     reload inside fn_setup (off) or with layer l's launch waiting only for
     layer l's copies (on).  Sources: the function's device memory, the pinned
     host cache (second exit stage) and its pageable host memory.  Device-side
-    inputs and outputs; outputs of both modes are compared bit for bit."""
+    inputs and outputs; outputs of both modes are compared bit for bit.
+    Each case runs `rounds` rounds, each a fresh context per mode (the
+    median of `reps` timed setups), the mode order alternating from round to
+    round; reported: the median and IQR over rounds per mode and of the
+    paired difference off - on."""
     from paper_2404_14691_amd import synth
     W, L = 4096, 8
     fn_bytes = L * W * W * 2
@@ -628,23 +632,32 @@ def progressive(S, torch, log, reps=5, batches=(8, 2048), interval_ms=250.0):
             S.sage_close(ctx)
         return float(np.median(ms))
 
+    def q(v):
+        return {"median": round(float(np.median(v)), 3),
+                "iqr": [round(float(np.percentile(v, 25)), 3), round(float(np.percentile(v, 75)), 3)]}
+
     res = {}
     for source in ("device", "host_cache", "pageable"):
         for b in batches:
-            off = case(source, 0, b)
-            on = case(source, 1, b)
+            offs, ons = [], []
+            for k in range(rounds):
+                order = (0, 1) if k % 2 == 0 else (1, 0)
+                for prog in order:
+                    (offs if prog == 0 else ons).append(case(source, prog, b))
             same = bool(torch.equal(outs[(source, 0, b)], outs[(source, 1, b)]))
-            res[f"{source}/b{b}"] = {"off_ms": round(off, 3), "on_ms": round(on, 3), "speedup": round(off / on, 3),
-                                     "outputs_identical": same}
+            off, on = float(np.median(offs)), float(np.median(ons))
+            res[f"{source}/b{b}"] = {"off_ms": q(offs), "on_ms": q(ons),
+                                     "off_minus_on_ms": q([a - c for a, c in zip(offs, ons)]),
+                                     "speedup": round(off / on, 3), "outputs_identical": same}
             log(f"progressive {source} b={b}: {res[f'{source}/b{b}']}")
             if not same:
                 raise RuntimeError(f"progressive outputs differ: {source} b={b}")
     gmean = float(np.exp(np.mean([np.log(v["speedup"]) for v in res.values()])))
     return _line("cold setup+invoke e2e ms, per-layer readiness vs whole-reload setup, 1 MI355X", gmean,
-                 "x geometric-mean speedup", reps, 1, res[f"host_cache/b{maxb}"]["on_ms"],
+                 "x geometric-mean speedup", rounds * reps, 1, res[f"host_cache/b{maxb}"]["on_ms"]["median"],
                  {"workload": f"progressive setup: 1 BF16 MLP 8 x 4096^2 (256 MiB), every block reloaded (from "
                               f"device memory, the pinned host cache, pageable host memory), batch {list(batches)}, "
-                              "device I/O"},
+                              f"device I/O; {rounds} rounds per case, mode order alternating, {reps} setups each"},
                  "bf16", cases=res)
 
 
