@@ -48,10 +48,13 @@ def test_setup_overlap_matches_table4_model(col):
     from paper_2404_14691_amd import sage as S
     s = TABLE["columns"][col]
     k = 0.25
-    got = S.sage_selftest_setup_overlap(s["gpu_ctx"] * k, s["cpu_data"] * k, s["gpu_data"] * k, False)
+    # a sleep only ever overshoots (a busy host delays the wake-up): the least of three runs
+    got = min(S.sage_selftest_setup_overlap(s["gpu_ctx"] * k, s["cpu_data"] * k, s["gpu_data"] * k, False)
+              for _ in range(3))
     want = (SM.parallel_setup(s) - s["cpu_ctx"]) * k
     assert want - 1 <= got <= want + 25
-    serial = S.sage_selftest_setup_overlap(s["gpu_ctx"] * k, s["cpu_data"] * k, s["gpu_data"] * k, True)
+    serial = min(S.sage_selftest_setup_overlap(s["gpu_ctx"] * k, s["cpu_data"] * k, s["gpu_data"] * k, True)
+                 for _ in range(3))
     want_serial = (SM.serial_setup(s) - s["cpu_ctx"]) * k
     assert want_serial - 1 <= serial <= want_serial + 25
 
