@@ -53,6 +53,53 @@ __device__ __forceinline__ uint8_t* c_row(const LayerArgs& la, uint32_t r, uint3
   return la.c_tab ? reinterpret_cast<uint8_t*>(la.c_tab[r]) : la.c_base + (uint64_t)r * la.N * esize;
 }
 
+template <int CTRL>
+__device__ __forceinline__ float quad_swap(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
+}
+
+// Epilogue of every shape.  Lane l holds column l & 15 and rows
+// 4 (l >> 4) + 0..3 of each 16 x 16 fragment; after relu, two DPP swaps
+// (lanes l ^ 1, then l ^ 2) transpose each lane quad's 4 x 4 block, so that
+// a lane holds 4 consecutive columns of one row and stores them at once
+// (8 B of BF16 or 16 B of FP32): a quarter of the store instructions of
+// one value per lane.  Values and rounding are unchanged.  Every lane of
+// the wave runs the swaps; only the stores are bounded by the group's rows.
+template <int FM, int FN>
+__device__ __forceinline__ void store_tile(const f32x4 (&acc)[FM][FN], const LayerArgs& la, const GemmGroup& gr,
+                                           uint32_t row_base, uint32_t col_base, bool relu, bool out_f32,
+                                           uint32_t lane) {
+  typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+  const bool b = lane & 1, hb = (lane >> 1) & 1;
+  const uint32_t rq = row_base + 4 * (lane >> 4) + (lane & 3);  // this lane's row in each 16-row fragment
+  const uint32_t cq = col_base + 4 * ((lane & 15) >> 2);        // its first column in each 16-column fragment
+#pragma unroll
+  for (int i = 0; i < FM; i++) {
+    const uint32_t r = rq + i * 16;
+    uint8_t* crow = r < gr.m ? c_row(la, gr.row0 + r, out_f32 ? 4 : 2) : nullptr;
+#pragma unroll
+    for (int j = 0; j < FN; j++) {
+      f32x4 v = acc[i][j];
+      if (relu) {
+#pragma unroll
+        for (int q = 0; q < 4; q++) v[q] = v[q] > 0.f ? v[q] : 0.f;
+      }
+      // quad lane c holds rows 0..3 of column c; after the swaps lane c holds row c, columns 0..3
+      const float r0 = quad_swap<0xB1>(b ? v[0] : v[1]), r2 = quad_swap<0xB1>(b ? v[2] : v[3]);  // quad_perm [1,0,3,2]
+      const float own0 = b ? v[1] : v[0], own2 = b ? v[3] : v[2];
+      const float w00 = b ? r0 : own0, w01 = b ? own0 : r0, w10 = b ? r2 : own2, w11 = b ? own2 : r2;
+      const float u0 = quad_swap<0x4E>(hb ? w00 : w10), u1 = quad_swap<0x4E>(hb ? w01 : w11);     // quad_perm [2,3,0,1]
+      const float k0 = hb ? w10 : w00, k1 = hb ? w11 : w01;
+      const float c0 = hb ? u0 : k0, c1 = hb ? u1 : k1, c2 = hb ? k0 : u0, c3 = hb ? k1 : u1;
+      if (crow) {
+        const uint32_t col = cq + j * 16;
+        if (out_f32) *reinterpret_cast<f32x4*>(reinterpret_cast<float*>(crow) + col) = f32x4{c0, c1, c2, c3};
+        else *reinterpret_cast<bf16x4*>(reinterpret_cast<__bf16*>(crow) + col) = bf16x4{(__bf16)c0, (__bf16)c1, (__bf16)c2, (__bf16)c3};
+      }
+    }
+  }
+}
+
 // LDS byte offset of 16-byte chunk `c` of row `r` in a [rows][BK] stage:
 // chunks are XOR-swizzled by the row so that 8 lanes reading one chunk
 // column of 8 consecutive rows hit 8 different bank groups.
@@ -165,25 +212,7 @@ __device__ __forceinline__ void ggemm_bf16(const GemmHdr* __restrict__ hdr, cons
       __syncthreads();
     }
 
-    // epilogue: lane holds column (lane & 15), rows 4*(lane >> 4) + 0..3 of each 16x16 fragment
-#pragma unroll
-    for (int i = 0; i < FM; i++) {
-#pragma unroll
-      for (int q = 0; q < 4; q++) {
-        const uint32_t r = m0 + wm * WM + i * 16 + 4 * (lane >> 4) + q;
-        if (r < gr.m) {
-          uint8_t* crow = c_row(la, gr.row0 + r, out_f32 ? 4 : 2);
-#pragma unroll
-          for (int j = 0; j < FN; j++) {
-            const uint32_t col = n0 + wn * WN + j * 16 + (lane & 15);
-            float v = acc[i][j][q];
-            if (relu) v = v > 0.f ? v : 0.f;
-            if (out_f32) reinterpret_cast<float*>(crow)[col] = v;
-            else reinterpret_cast<__bf16*>(crow)[col] = (__bf16)v;
-          }
-        }
-      }
-    }
+    store_tile<FM, FN>(acc, la, gr, m0 + wm * WM, n0 + wn * WN, relu, out_f32, lane);
   }
 }
 
@@ -303,24 +332,7 @@ __device__ __forceinline__ void ggemm2(const GemmHdr* __restrict__ hdr, const Ge
       __syncthreads();
     }
 
-#pragma unroll
-    for (int i = 0; i < FM; i++) {
-#pragma unroll
-      for (int q = 0; q < 4; q++) {
-        const uint32_t r = m0 + wm * WM + i * 16 + 4 * (lane >> 4) + q;
-        if (r < gr.m) {
-          uint8_t* crow = c_row(la, gr.row0 + r, out_f32 ? 4 : 2);
-#pragma unroll
-          for (int jj = 0; jj < FN; jj++) {
-            const uint32_t col = n0 + wn * WN + jj * 16 + (lane & 15);
-            float v = acc[i][jj][q];
-            if (relu) v = v > 0.f ? v : 0.f;
-            if (out_f32) reinterpret_cast<float*>(crow)[col] = v;
-            else reinterpret_cast<__bf16*>(crow)[col] = (__bf16)v;
-          }
-        }
-      }
-    }
+    store_tile<FM, FN>(acc, la, gr, m0 + wm * WM, n0 + wn * WN, relu, out_f32, lane);
   }
 }
 
@@ -466,24 +478,7 @@ __device__ __forceinline__ void ggemm3(const GemmHdr* __restrict__ hdr, const Ge
     }
     __syncthreads();  // the next tile's first loads overwrite stages still being read
 
-#pragma unroll
-    for (int i = 0; i < FM; i++) {
-#pragma unroll
-      for (int q = 0; q < 4; q++) {
-        const uint32_t r = m0 + wm * WM + i * 16 + 4 * (lane >> 4) + q;
-        if (r < gr.m) {
-          uint8_t* crow = c_row(la, gr.row0 + r, out_f32 ? 4 : 2);
-#pragma unroll
-          for (int jj = 0; jj < FN; jj++) {
-            const uint32_t col = n0 + wn * WN + jj * 16 + (lane & 15);
-            float v = acc[i][jj][q];
-            if (relu) v = v > 0.f ? v : 0.f;
-            if (out_f32) reinterpret_cast<float*>(crow)[col] = v;
-            else reinterpret_cast<__bf16*>(crow)[col] = (__bf16)v;
-          }
-        }
-      }
-    }
+    store_tile<FM, FN>(acc, la, gr, m0 + wm * WM, n0 + wn * WN, relu, out_f32, lane);
   }
 }
 
@@ -612,24 +607,7 @@ __device__ __forceinline__ void ggemm6(const GemmHdr* __restrict__ hdr, const Ge
     }
     if (!lag) phase_sync();  // both groups leave the tile after the same number of barriers
 
-#pragma unroll
-    for (int i = 0; i < FM; i++) {
-#pragma unroll
-      for (int q = 0; q < 4; q++) {
-        const uint32_t r = m0 + wm * WM + i * 16 + 4 * (lane >> 4) + q;
-        if (r < gr.m) {
-          uint8_t* crow = c_row(la, gr.row0 + r, out_f32 ? 4 : 2);
-#pragma unroll
-          for (int jj = 0; jj < FN; jj++) {
-            const uint32_t col = n0 + wn * WN + jj * 16 + (lane & 15);
-            float v = acc[i][jj][q];
-            if (relu) v = v > 0.f ? v : 0.f;
-            if (out_f32) reinterpret_cast<float*>(crow)[col] = v;
-            else reinterpret_cast<__bf16*>(crow)[col] = (__bf16)v;
-          }
-        }
-      }
-    }
+    store_tile<FM, FN>(acc, la, gr, m0 + wm * WM, n0 + wn * WN, relu, out_f32, lane);
   }
 }
 
