@@ -263,7 +263,7 @@ def mlp_f32(S, torch, log, reps=5):
                  "f32", detail=res,
                  speedup_vs_plain=round(res["plain"]["ms_16_invocations"] / res["shared"]["ms_16_invocations"], 2),
                  roofline={"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "mlp_f32_layer_c4 (one output column per wave)",
+                           "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "mlp_f32_layer (4 output columns per workgroup, K split over its waves)",
                            "avg_launch_ms": round(avg, 5), "bytes_per_launch": alg, "launches": k_n})
 
 

@@ -15,7 +15,7 @@
 //   ggemm6*_bf16_<BM>x<BN> 8-wave ping-pong over the same ring, the main
 //                          shape of large grouped launches.
 // mlp_f32_layer is the same layer in FP32 on the vector ALUs for small
-// batches (one wave per two output columns, fixed reduction order).
+// batches (K split over a workgroup's waves, fixed reduction order).
 //
 // Every tile shape walks K in the same order with the same MFMA, so an
 // output element's bits do not depend on the tile shape, on its row
@@ -675,150 +675,134 @@ SAGE_GGEMM6(ggemm6p_bf16_256x256, 256, 256, 128, 64, 4, true)
 SAGE_GGEMM6(ggemm6_bf16_256x128, 256, 128, 64, 64, 4, false)
 
 // ---------------------------------------------------------------- FP32 MLP
-// Tiles: (group, block of 8 output columns); wave w of the workgroup owns
-// columns 8*cb + 2w and 8*cb + 2w + 1 and walks the group's rows 8 at a time.
-// Lane l accumulates k = 4l + 256i (i = 0, 1, ...) with fmaf in order, then a
-// fixed xor-butterfly sums the lanes, so the order depends on nothing but K.
-// A few rows are bound by load latency, not bandwidth: per K chunk of 2048,
-// each wave loads its two weight rows into registers with every load issued
-// before the first FMA, and the workgroup stages the 8 input rows in LDS
-// once for its four waves.
+// A few rows are bound by load latency, not bandwidth: every load of a
+// K chunk goes out before the first FMA, straight into registers.
 constexpr uint32_t kF32KC = 2048;                       // K per chunk
 typedef __attribute__((address_space(1))) const f32x4 g_f32x4;
 
-// CPW output columns per wave (4 CPW per workgroup): 2 gives fewer
-// workgroups that each read the 8 input rows once for 8 columns, 1 twice as
-// many workgroups (two per CU at 8 rows of width 2048) with half the weight
-// rows each.  The K order of a column is the same in both.
-// ONE: the launch has a single group, passed by value (its block table
-// `wtab1` and row count `m1`, row0 and first tile 0): the header and group
-// record are not read, which takes two dependent loads off the way to the
-// weights.
-template <int CPW, bool ONE>
-__device__ __forceinline__ void mlp_f32_body(const GemmHdr* __restrict__ hdr, const GemmGroup* __restrict__ groups,
-                                             const LayerArgs& la, float (*xs)[kF32KC], const uint64_t* wtab1,
-                                             uint32_t m1) {
-  static_assert(CPW == 1 || CPW == 2, "one or two columns per wave");
-  constexpr int WPL = kF32KC / 256;                     // float4 per lane per weight row per chunk
-  constexpr int XPR = kF32KC / 4 / 256;                 // float4 per thread per staged row per chunk
+// K split over the waves.  Tiles: (group, block of CW output columns); the
+// four waves of the workgroup share the tile's CW columns and split each
+// 2048-wide K chunk into quarters: wave w takes k in [kc + w kn/4, kc +
+// (w + 1) kn/4), lane l the float4 at 4l and 4l + 256 of that quarter.  Every
+// lane loads its slice of the 8 input rows and of the CW weight rows straight
+// into registers (no staging, no barrier before the FMAs) and accumulates 8 x
+// CW partial sums with fmaf in k order.  The lanes' sums are combined by a
+// halving exchange (lanes l ^ 32, l ^ 16, ...: each step a lane keeps half of
+// its values and adds its partner's copy of that half), the waves' in LDS in
+// wave order.  The order depends only on K, not on the rows of the launch.
+template <int CW, bool ONE>
+__device__ __forceinline__ void mlp_f32_ks_body(const GemmHdr* __restrict__ hdr, const GemmGroup* __restrict__ groups,
+                                                const LayerArgs& la, float (*red)[8 * CW], const uint64_t* wtab1,
+                                                uint32_t m1) {
+  static_assert(CW == 4 || CW == 8, "4 or 8 columns per workgroup");
+  constexpr int V = 8 * CW;  // partial sums per lane: 8 rows x CW columns
   const uint32_t t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const uint32_t K = la.K;
   const bool relu = la.flags & kRelu;
-  const uint32_t total_tiles = ONE ? la.N / (4 * CPW) : hdr->total_tiles;
+  const uint32_t total_tiles = ONE ? la.N / CW : hdr->total_tiles;
   for (uint32_t tile = blockIdx.x; tile < total_tiles; tile += gridDim.x) {
     GemmGroup gr;
     if (ONE) gr = GemmGroup{reinterpret_cast<uint64_t>(wtab1), m1, 0, 0, 0};
     else gr = groups[find_group(groups, hdr->n_groups, tile)];
-    const uint32_t n = (tile - gr.tile_start) * (4 * CPW) + wave * CPW;
+    const uint32_t n = (tile - gr.tile_start) * CW;
     const uint64_t* wtab = reinterpret_cast<const uint64_t*>(gr.wtab);
-    const uint64_t off0 = la.w_off + (uint64_t)n * K * 4, off1 = off0 + (uint64_t)K * 4;
-    const float* w0 = reinterpret_cast<const float*>(wtab[off0 >> kBlockShift] + (off0 & (kBlock - 1)));
-    // (with one column per wave there is no second row: off1 would be past the blob for the last column)
-    const float* w1 = CPW == 2 ? reinterpret_cast<const float*>(wtab[off1 >> kBlockShift] + (off1 & (kBlock - 1))) : w0;
+    const float* wr[CW];
+#pragma unroll
+    for (int c = 0; c < CW; c++) {
+      const uint64_t off = la.w_off + (uint64_t)(n + c) * K * 4;
+      wr[c] = reinterpret_cast<const float*>(wtab[off >> kBlockShift] + (off & (kBlock - 1)));
+    }
     for (uint32_t r0 = 0; r0 < gr.m; r0 += 8) {
       const uint32_t nr = gr.m - r0 < 8 ? gr.m - r0 : 8;
-      // the rows' addresses once per row block; loads are not branched
-      // around but clamped into valid rows and columns (a value loaded for
-      // a missing row or column is not used), so they all go out together
+      // rows past the group's end read its first row of the block (not stored)
       const float* ar[8];
-      if (la.a_tab) {
-#pragma unroll
-        for (int i = 0; i < 8; i++) ar[i] = reinterpret_cast<const float*>(la.a_tab[gr.row0 + r0 + ((uint32_t)i < nr ? i : 0)]);
-      } else {
-#pragma unroll
-        for (int i = 0; i < 8; i++)
-          ar[i] = reinterpret_cast<const float*>(la.a_base + (uint64_t)(gr.row0 + r0 + ((uint32_t)i < nr ? i : 0)) * K * 4);
-      }
-      float acc0[8], acc1[8];
-#pragma unroll
-      for (int i = 0; i < 8; i++) acc0[i] = acc1[i] = 0.f;
-      for (uint32_t kc = 0; kc < K; kc += kF32KC) {
-        const uint32_t kn = K - kc < kF32KC ? K - kc : kF32KC;  // a power of two >= 128
-        f32x4 wa[WPL], wb[WPL], xv[8][XPR];
-#pragma unroll
-        for (int j = 0; j < WPL; j++) {
-          const uint32_t k = 4 * lane + 256 * j < kn ? 4 * lane + 256 * j : kn - 4;
-          wa[j] = *(g_f32x4*)(uintptr_t)(w0 + kc + k);
-          if constexpr (CPW == 2) wb[j] = *(g_f32x4*)(uintptr_t)(w1 + kc + k);
-        }
-        // rows r0 .. r0 + nr - 1, columns kc .. kc + kn - 1: float4 q = t + 256 m of each row
-        const uint32_t q4 = kn / 4;
-#pragma unroll
-        for (int i = 0; i < 8; i++)
-#pragma unroll
-          for (int m = 0; m < XPR; m++) {
-            const uint32_t q = t + 256 * m < q4 ? t + 256 * m : q4 - 1;
-            xv[i][m] = *(g_f32x4*)(uintptr_t)(ar[i] + kc + 4 * q);
-          }
-#pragma unroll
-        for (int i = 0; i < 8; i++)
-#pragma unroll
-          for (int m = 0; m < XPR; m++) {
-            const uint32_t q = t + 256 * m;
-            if ((uint32_t)i < nr && q < q4) *reinterpret_cast<f32x4*>(&xs[i][4 * q]) = xv[i][m];
-          }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < WPL; j++) {
-          const uint32_t k = 4 * lane + 256 * j;
-          if (k < kn) {
-#pragma unroll
-            for (int i = 0; i < 8; i++) {
-              if ((uint32_t)i < nr) {
-                const f32x4 a = *reinterpret_cast<const f32x4*>(&xs[i][k]);
-                acc0[i] = fmaf(a.x, wa[j].x, acc0[i]);
-                acc0[i] = fmaf(a.y, wa[j].y, acc0[i]);
-                acc0[i] = fmaf(a.z, wa[j].z, acc0[i]);
-                acc0[i] = fmaf(a.w, wa[j].w, acc0[i]);
-                if constexpr (CPW == 2) {
-                  acc1[i] = fmaf(a.x, wb[j].x, acc1[i]);
-                  acc1[i] = fmaf(a.y, wb[j].y, acc1[i]);
-                  acc1[i] = fmaf(a.z, wb[j].z, acc1[i]);
-                  acc1[i] = fmaf(a.w, wb[j].w, acc1[i]);
-                }
-              }
-            }
-          }
-        }
-        __syncthreads();  // the next chunk or row block restages xs
-      }
 #pragma unroll
       for (int i = 0; i < 8; i++) {
+        const uint32_t r = gr.row0 + r0 + ((uint32_t)i < nr ? i : 0);
+        ar[i] = la.a_tab ? reinterpret_cast<const float*>(la.a_tab[r])
+                         : reinterpret_cast<const float*>(la.a_base + (uint64_t)r * K * 4);
+      }
+      float acc[8][CW];
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-          acc0[i] += __shfl_xor(acc0[i], o, 64);
-          if constexpr (CPW == 2) acc1[i] += __shfl_xor(acc1[i], o, 64);
+      for (int i = 0; i < 8; i++)
+#pragma unroll
+        for (int c = 0; c < CW; c++) acc[i][c] = 0.f;
+      for (uint32_t kc = 0; kc < K; kc += kF32KC) {
+        const uint32_t kn = K - kc < kF32KC ? K - kc : kF32KC;  // a power of two >= 128
+        const uint32_t kw = kn / 4, base = kc + wave * kw;
+        f32x4 xv[8][2], wv[CW][2];
+#pragma unroll
+        for (int j = 0; j < 2; j++) {
+          const uint32_t k4 = 4 * (lane + 64 * j);
+          const uint32_t k = base + (k4 < kw ? k4 : 0);  // idle lanes of a narrow chunk load in bounds
+#pragma unroll
+          for (int c = 0; c < CW; c++) wv[c][j] = *(g_f32x4*)(uintptr_t)(wr[c] + k);
+#pragma unroll
+          for (int i = 0; i < 8; i++) xv[i][j] = *(g_f32x4*)(uintptr_t)(ar[i] + k);
         }
-      }
-      if (lane == 0) {
-        for (uint32_t i = 0; i < nr; i++) {
-          float* crow = reinterpret_cast<float*>(c_row(la, gr.row0 + r0 + i, 4));
-          float v0 = acc0[i], v1 = acc1[i];
-          if (relu) {
-            v0 = v0 > 0.f ? v0 : 0.f;
-            v1 = v1 > 0.f ? v1 : 0.f;
+#pragma unroll
+        for (int j = 0; j < 2; j++) {
+          if (4 * (lane + 64 * j) < kw) {
+#pragma unroll
+            for (int i = 0; i < 8; i++)
+#pragma unroll
+              for (int c = 0; c < CW; c++) {
+                acc[i][c] = fmaf(xv[i][j].x, wv[c][j].x, acc[i][c]);
+                acc[i][c] = fmaf(xv[i][j].y, wv[c][j].y, acc[i][c]);
+                acc[i][c] = fmaf(xv[i][j].z, wv[c][j].z, acc[i][c]);
+                acc[i][c] = fmaf(xv[i][j].w, wv[c][j].w, acc[i][c]);
+              }
           }
-          crow[n] = v0;
-          if constexpr (CPW == 2) crow[n + 1] = v1;
         }
       }
+      // halving exchange: after the step with mask m a lane holds half as many
+      // values, each the sum over twice as many lanes; a lane with bit m set
+      // keeps the upper half.  V = 64 ends with value l in lane l; V = 32 with
+      // value l >> 1 in lanes l and l ^ 1 after a last plain exchange.
+      float v[V];
+#pragma unroll
+      for (int i = 0; i < 8; i++)
+#pragma unroll
+        for (int c = 0; c < CW; c++) v[i * CW + c] = acc[i][c];
+#pragma unroll
+      for (int h = V / 2, m = 32; h >= 1; h >>= 1, m >>= 1) {
+        const bool up = lane & m;
+#pragma unroll
+        for (int s = 0; s < h; s++) {
+          const float keep = up ? v[s + h] : v[s], send = up ? v[s] : v[s + h];
+          v[s] = keep + __shfl_xor(send, m, 64);
+        }
+      }
+      if constexpr (V == 32) v[0] += __shfl_xor(v[0], 1, 64);
+      const uint32_t idx = V == 64 ? lane : lane >> 1;
+      if (V == 64 || (lane & 1) == 0) red[wave][idx] = v[0];
+      __syncthreads();
+      if (t < (uint32_t)V) {
+        const uint32_t i = t / CW, c = t % CW;
+        if (i < nr) {
+          float s = red[0][t] + red[1][t];
+          s += red[2][t];
+          s += red[3][t];
+          if (relu) s = s > 0.f ? s : 0.f;
+          reinterpret_cast<float*>(c_row(la, gr.row0 + r0 + i, 4))[n + c] = s;
+        }
+      }
+      __syncthreads();  // the next row block reuses red
     }
   }
 }
 
-// wtab1 non-null: the launch's only group, by value (see ONE above)
-extern "C" __global__ __launch_bounds__(256) void mlp_f32_layer(const GemmHdr* __restrict__ hdr,
-                                                                const GemmGroup* __restrict__ groups,
-                                                                LayerArgs la, const uint64_t* wtab1, uint32_t m1) {
-  __shared__ __attribute__((aligned(16))) float xs[8][kF32KC];
-  if (wtab1) mlp_f32_body<2, true>(hdr, groups, la, xs, wtab1, m1);
-  else mlp_f32_body<2, false>(hdr, groups, la, xs, wtab1, m1);
-}
-
-extern "C" __global__ __launch_bounds__(256) void mlp_f32_layer_c4(const GemmHdr* __restrict__ hdr,
-                                                                   const GemmGroup* __restrict__ groups,
-                                                                   LayerArgs la, const uint64_t* wtab1, uint32_t m1) {
-  __shared__ __attribute__((aligned(16))) float xs[8][kF32KC];
-  if (wtab1) mlp_f32_body<1, true>(hdr, groups, la, xs, wtab1, m1);
-  else mlp_f32_body<1, false>(hdr, groups, la, xs, wtab1, m1);
-}
+#define SAGE_F32KS(NAME, CW)                                                                            \
+  extern "C" __global__ __launch_bounds__(256) void NAME(const GemmHdr* __restrict__ hdr,                \
+                                                         const GemmGroup* __restrict__ groups,           \
+                                                         LayerArgs la, const uint64_t* wtab1, uint32_t m1) { \
+    __shared__ float red[4][8 * CW];                                                                     \
+    if (wtab1) mlp_f32_ks_body<CW, true>(hdr, groups, la, red, wtab1, m1);                               \
+    else mlp_f32_ks_body<CW, false>(hdr, groups, la, red, wtab1, m1);                                    \
+  }
+// ONE: the launch has a single group, passed by value (its block table
+// `wtab1` and row count `m1`, row0 and first tile 0): the header and group
+// record are not read, which takes two dependent loads off the way to the
+// weights.
+SAGE_F32KS(mlp_f32_layer, 4)
+SAGE_F32KS(mlp_f32_layer_c8, 8)

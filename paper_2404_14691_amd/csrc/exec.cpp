@@ -298,7 +298,7 @@ int launch_mlp_group(Ctx& c, const std::vector<Call>& calls, uint32_t io, int fl
   *thdr = GemmHdr{nt, ttiles, M, 0};
   const bool split = nt > 0;
   const TileShape* ms = bf16 ? plan.main : nullptr;
-  const std::string kname = bf16 ? ms->name : c.f32_cols == 4 ? "mlp_f32_layer_c4" : "mlp_f32_layer";
+  const std::string kname = bf16 ? ms->name : c.f32_cols == 4 ? "mlp_f32_layer" : "mlp_f32_layer_c8";
   c.last_launch = kname + ":" + std::to_string(tiles);
   if (split) c.last_launch += std::string("+") + plan.tail->name + ":" + std::to_string(ttiles);
 

@@ -219,6 +219,26 @@ def test_f32_scattered_block_table_same_bits(sage_ctx_factory, torch_cuda):
         assert OM.normwise_error(y, OM.mlp_forward(x, w.astype(np.float64))) <= F32_TOL
 
 
+def test_f32_mlp_two_k_chunks(sage_ctx_factory, torch_cuda):
+    """Width 4096: each column's K is walked as two 2048-wide chunks whose
+    partial sums accumulate before the lanes and waves are combined; 3 and 9
+    rows alone (ragged row blocks) and together (8 + 4), against the float64
+    oracle and each other."""
+    from paper_2404_14691_amd import sage as S
+    ctx = sage_ctx_factory(pool_budget_bytes=512 << 20)
+    W, L = 4096, 2
+    rng = np.random.default_rng(12)
+    w = (rng.standard_normal((L, W, W)) / np.sqrt(W)).astype(np.float32)
+    fn = S.fn_register(ctx, S.mlp_desc(S.SAGE_MLP_F32, L, W), [S.make_blob(w.reshape(-1))])
+    xs = [rng.standard_normal((b, W)).astype(np.float32) for b in (3, 9)]
+    ys = _run(S, ctx, fn, xs, W)
+    for x, y in zip(xs, ys):
+        assert OM.normwise_error(y, OM.mlp_forward(x, w.astype(np.float64))) <= F32_TOL
+    solo = _run(S, ctx, fn, xs, W, batch_call=False)
+    for a, b in zip(ys, solo):
+        assert np.array_equal(a, b)
+
+
 def test_f32_mlp_full_size_sixteen_invocations(sage_ctx_factory, torch_cuda):
     """2-layer FP32 MLP of width 2048, 16 sequential invocations of 8 rows,
     each with its own input: every output element vs the float64 oracle."""
@@ -346,9 +366,10 @@ def test_relax_rejects_read_only_blobs(sage_ctx_factory, torch_cuda):
 
 
 def test_f32_four_and_eight_columns_per_workgroup_same_bits(sage_ctx_factory, torch_cuda, monkeypatch):
-    """The FP32 layer with one column per wave (SAGE_F32_COLS=4) walks each
-    column's K in the same order as with two: the same bits, one group and
-    two groups (the last column of the last layer included).  A one-group
+    """The FP32 layer with four output columns per workgroup (SAGE_F32_COLS=4)
+    splits each column's K over the lanes and waves as with eight and sums
+    the partial sums along the same exchange tree: the same bits, one group
+    and two groups (the last column of the last layer included).  A one-group
     launch passes its group by value, a two-group one reads the groups from
     the launch header: the solo run against the batch compares the two."""
     from paper_2404_14691_amd import sage as S
