@@ -680,6 +680,27 @@ SAGE_GGEMM6(ggemm6_bf16_256x128, 256, 128, 64, 64, 4, false)
 constexpr uint32_t kF32KC = 2048;                       // K per chunk
 typedef __attribute__((address_space(1))) const f32x4 g_f32x4;
 
+// The value of lane l ^ m (m a power of two below 64) for every lane of the
+// wave.  Within a row of 16 lanes through DPP: m = 1, 2 by quad permutation,
+// 8 by a rotation of the row by 8, 4 by rotations by 4 and 12 (a lane with
+// bit 2 set takes the one that reads 4 lanes down, i.e. lane l - 4); 16 and
+// 32 through the LDS crossbar.  Every lane of the wave must execute it.
+__device__ __forceinline__ float lane_xor(float x, int m, uint32_t lane) {
+  const int xi = __builtin_bit_cast(int, x);
+  int r;
+  if (m == 1) r = __builtin_amdgcn_mov_dpp(xi, 0xB1, 0xF, 0xF, false);        // quad_perm [1,0,3,2]
+  else if (m == 2) r = __builtin_amdgcn_mov_dpp(xi, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+  else if (m == 8) r = __builtin_amdgcn_mov_dpp(xi, 0x128, 0xF, 0xF, false);  // row_ror:8
+  else if (m == 4) {
+    const int down = __builtin_amdgcn_mov_dpp(xi, 0x124, 0xF, 0xF, false);  // row_ror:4: lane l reads l - 4
+    const int up = __builtin_amdgcn_mov_dpp(xi, 0x12C, 0xF, 0xF, false);    // row_ror:12: lane l reads l + 4
+    r = (lane & 4) ? down : up;
+  } else {
+    return __shfl_xor(x, m, 64);
+  }
+  return __builtin_bit_cast(float, r);
+}
+
 // K split over the waves.  Tiles: (group, block of CW output columns); the
 // four waves of the workgroup share the tile's CW columns and split each
 // 2048-wide K chunk into quarters: wave w takes k in [kc + w kn/4, kc +
@@ -687,9 +708,9 @@ typedef __attribute__((address_space(1))) const f32x4 g_f32x4;
 // lane loads its slice of the 8 input rows and of the CW weight rows straight
 // into registers (no staging, no barrier before the FMAs) and accumulates 8 x
 // CW partial sums with fmaf in k order.  The lanes' sums are combined by a
-// halving exchange (lanes l ^ 32, l ^ 16, ...: each step a lane keeps half of
-// its values and adds its partner's copy of that half), the waves' in LDS in
-// wave order.  The order depends only on K, not on the rows of the launch.
+// halving exchange (partners l ^ 1, l ^ 2, l ^ 8, l ^ 4, l ^ 16, l ^ 32: each
+// step a lane keeps half of its values and adds its partner's copy of that
+// half), the waves' in LDS in wave order.  The order depends only on K, not on the rows of the launch.
 template <int CW, bool ONE>
 __device__ __forceinline__ void mlp_f32_ks_body(const GemmHdr* __restrict__ hdr, const GemmGroup* __restrict__ groups,
                                                 const LayerArgs& la, float (*red)[8 * CW], const uint64_t* wtab1,
@@ -755,27 +776,33 @@ __device__ __forceinline__ void mlp_f32_ks_body(const GemmHdr* __restrict__ hdr,
           }
         }
       }
-      // halving exchange: after the step with mask m a lane holds half as many
-      // values, each the sum over twice as many lanes; a lane with bit m set
-      // keeps the upper half.  V = 64 ends with value l in lane l; V = 32 with
-      // value l >> 1 in lanes l and l ^ 1 after a last plain exchange.
+      // halving exchange: at the step with lane mask m a lane keeps half of its
+      // values (the upper half if its bit m is set) and adds its partner's
+      // (lane l ^ m) copy of that half, so each kept value becomes the sum over
+      // twice as many lanes.  Masks 1, 2, 8, 4 (DPP within a row of 16), then
+      // 16 and 32 (through LDS) on the few values left; V = 32 ends with a
+      // plain exchange over mask 32.  The value a lane ends with is read off
+      // its bits: the bit of each step's mask picks the half it kept.
       float v[V];
 #pragma unroll
       for (int i = 0; i < 8; i++)
 #pragma unroll
         for (int c = 0; c < CW; c++) v[i * CW + c] = acc[i][c];
+      constexpr int kMask[6] = {1, 2, 8, 4, 16, 32};
+      uint32_t idx = 0;
 #pragma unroll
-      for (int h = V / 2, m = 32; h >= 1; h >>= 1, m >>= 1) {
+      for (int st = 0, h = V / 2; h >= 1; st++, h >>= 1) {
+        const int m = kMask[st];
         const bool up = lane & m;
+        if (up) idx += h;
 #pragma unroll
-        for (int s = 0; s < h; s++) {
-          const float keep = up ? v[s + h] : v[s], send = up ? v[s] : v[s + h];
-          v[s] = keep + __shfl_xor(send, m, 64);
+        for (int q = 0; q < h; q++) {
+          const float keep = up ? v[q + h] : v[q], send = up ? v[q] : v[q + h];
+          v[q] = keep + lane_xor(send, m, lane);
         }
       }
-      if constexpr (V == 32) v[0] += __shfl_xor(v[0], 1, 64);
-      const uint32_t idx = V == 64 ? lane : lane >> 1;
-      if (V == 64 || (lane & 1) == 0) red[wave][idx] = v[0];
+      if constexpr (V == 32) v[0] += lane_xor(v[0], 32, lane);
+      if (V == 64 || (lane & 32) == 0) red[wave][idx] = v[0];
       __syncthreads();
       if (t < (uint32_t)V) {
         const uint32_t i = t / CW, c = t % CW;
