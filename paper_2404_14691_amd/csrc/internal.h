@@ -171,11 +171,17 @@ class FpIndex {
  public:
   uint32_t find(uint64_t fp) const;
   void set(uint64_t fp, uint32_t head);  // insert or overwrite
+  // insert unless present (one probe sequence): the value already there, or kNone
+  uint32_t insert_if_absent(uint64_t fp, uint32_t head);
+  // the value at fp (kNone if absent); if it is `head`, it becomes `next`,
+  // or the entry goes when next is kNone (one probe sequence)
+  uint32_t pop_head(uint64_t fp, uint32_t head, uint32_t next);
   void erase(uint64_t fp);
   void clear();
 
  private:
   void grow();
+  void erase_at(size_t i);
   std::vector<uint64_t> key_;
   std::vector<uint32_t> val_;  // kNone = empty
   size_t mask_ = 0, n_ = 0;

@@ -45,14 +45,29 @@ void FpIndex::set(uint64_t fp, uint32_t head) {
   }
 }
 
+uint32_t FpIndex::insert_if_absent(uint64_t fp, uint32_t head) {
+  if ((n_ + 1) * 2 > key_.size()) grow();
+  for (size_t i = fp_hash(fp) & mask_;; i = (i + 1) & mask_) {
+    if (val_[i] == kNone) {
+      key_[i] = fp;
+      val_[i] = head;
+      n_++;
+      return kNone;
+    }
+    if (key_[i] == fp) return val_[i];
+  }
+}
+
 // Linear probing with backward-shift deletion (no tombstones).
 void FpIndex::erase(uint64_t fp) {
   if (!n_) return;
-  size_t i = fp_hash(fp) & mask_;
-  for (;; i = (i + 1) & mask_) {
+  for (size_t i = fp_hash(fp) & mask_;; i = (i + 1) & mask_) {
     if (val_[i] == kNone) return;
-    if (key_[i] == fp) break;
+    if (key_[i] == fp) return erase_at(i);
   }
+}
+
+void FpIndex::erase_at(size_t i) {
   for (size_t j = (i + 1) & mask_;; j = (j + 1) & mask_) {
     if (val_[j] == kNone) break;
     const size_t home = fp_hash(key_[j]) & mask_;
@@ -66,6 +81,20 @@ void FpIndex::erase(uint64_t fp) {
   }
   val_[i] = kNone;
   n_--;
+}
+
+uint32_t FpIndex::pop_head(uint64_t fp, uint32_t head, uint32_t next) {
+  if (!n_) return kNone;
+  for (size_t i = fp_hash(fp) & mask_;; i = (i + 1) & mask_) {
+    if (val_[i] == kNone) return kNone;
+    if (key_[i] != fp) continue;
+    const uint32_t h = val_[i];
+    if (h == head) {
+      if (next != kNone) val_[i] = next;
+      else erase_at(i);
+    }
+    return h;
+  }
 }
 
 void FpIndex::clear() {
@@ -146,10 +175,8 @@ uint32_t Pool::new_class(uint64_t fp, uint32_t len) {
 
 void Pool::index_add(uint32_t c) {
   cls[c].next = kNone;
-  const uint32_t h = index_.find(cls[c].fp);
-  if (h == kNone) {
-    index_.set(cls[c].fp, c);
-  } else {
+  const uint32_t h = index_.insert_if_absent(cls[c].fp, c);
+  if (h != kNone) {
     uint32_t t = h;
     while (cls[t].next != kNone) t = cls[t].next;
     cls[t].next = c;
@@ -159,11 +186,8 @@ void Pool::index_add(uint32_t c) {
 
 void Pool::index_remove(uint32_t c) {
   if (!cls[c].indexed) return;
-  const uint32_t h = index_.find(cls[c].fp);
-  if (h == c) {
-    if (cls[c].next == kNone) index_.erase(cls[c].fp);
-    else index_.set(cls[c].fp, cls[c].next);
-  } else if (h != kNone) {
+  const uint32_t h = index_.pop_head(cls[c].fp, c, cls[c].next);
+  if (h != c && h != kNone) {
     uint32_t t = h;
     while (t != kNone && cls[t].next != c) t = cls[t].next;
     if (t != kNone) cls[t].next = cls[c].next;
@@ -273,12 +297,29 @@ void Pool::host_release(uint32_t c) {
 }
 
 void Pool::sort_by_seq(std::vector<uint32_t>& ids) const {
-  std::vector<std::pair<uint64_t, uint32_t>> a(ids.size()), b(ids.size());
-  uint64_t mx = 0;
+  if (ids.size() < 2) return;
+  // sequence numbers are unique: already ascending, or spread over few
+  // values (a registration's classes were mostly created recently), a
+  // direct placement by seq - min is one pass
+  uint64_t mn = ~0ull, mx = 0;
+  bool sorted = true;
   for (size_t i = 0; i < ids.size(); i++) {
-    a[i] = {cls[ids[i]].seq, ids[i]};
-    mx = std::max(mx, a[i].first);
+    const uint64_t q = cls[ids[i]].seq;
+    if (i && q < cls[ids[i - 1]].seq) sorted = false;
+    mn = std::min(mn, q);
+    mx = std::max(mx, q);
   }
+  if (sorted) return;
+  if (mx - mn < 8 * (uint64_t)ids.size() + 4096) {
+    std::vector<uint32_t> at(mx - mn + 1, kNone);
+    for (uint32_t id : ids) at[cls[id].seq - mn] = id;
+    size_t k = 0;
+    for (uint32_t id : at)
+      if (id != kNone) ids[k++] = id;
+    return;
+  }
+  std::vector<std::pair<uint64_t, uint32_t>> a(ids.size()), b(ids.size());
+  for (size_t i = 0; i < ids.size(); i++) a[i] = {cls[ids[i]].seq, ids[i]};
   for (unsigned shift = 0; shift < 64 && (mx >> shift) != 0; shift += 8) {
     size_t cnt[257] = {0};
     for (const auto& e : a) cnt[((e.first >> shift) & 255) + 1]++;

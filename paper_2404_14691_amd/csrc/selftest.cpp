@@ -161,13 +161,43 @@ uint32_t pool_stress(uint64_t seed, uint32_t n_ops, uint32_t budget, std::string
     }
     if (!check()) return op;
   }
-  // creation order sort of every live class
+  // creation order sort of every live class, of the same classes shuffled,
+  // of an already ascending list and of a sparse subset (every path of the
+  // sort: ascending, direct placement, radix); each against std::sort
   std::vector<uint32_t> ids;
   for (auto& kv : model) ids.push_back(kv.first);
-  P.sort_by_seq(ids);
-  for (size_t i = 1; i < ids.size(); i++)
-    if (P.cls[ids[i - 1]].seq >= P.cls[ids[i]].seq) return why = "sort_by_seq out of order", n_ops - 1;
+  auto by_seq = [&](std::vector<uint32_t> v) {
+    std::sort(v.begin(), v.end(), [&](uint32_t a, uint32_t b) { return P.cls[a].seq < P.cls[b].seq; });
+    return v;
+  };
+  std::vector<std::vector<uint32_t>> cases{ids};
+  std::shuffle(cases[0].begin(), cases[0].end(), rng);
+  cases.push_back(by_seq(ids));
+  std::vector<uint32_t> sparse;
+  for (size_t i = 0; i < cases[1].size(); i += 97) sparse.push_back(cases[1][i]);
+  std::reverse(sparse.begin(), sparse.end());
+  cases.push_back(sparse);
+  cases.push_back(ids);
+  for (auto& v : cases) {
+    const std::vector<uint32_t> want = by_seq(v);
+    P.sort_by_seq(v);
+    if (v != want) return why = "sort_by_seq: not the creation order of its input", n_ops - 1;
+  }
   P.destroy();
+  // classes spread over a wide range of sequence numbers (the radix path)
+  Pool Q;
+  Q.init(1, 1, /*host_standin=*/true);
+  std::vector<uint32_t> wide;
+  for (uint32_t i = 0; i < 40000; i++) {
+    const uint32_t c = Q.new_class(rng(), 1);
+    if (rng() % 64 == 0) wide.push_back(c);
+  }
+  std::shuffle(wide.begin(), wide.end(), rng);
+  std::vector<uint32_t> want = wide;
+  std::sort(want.begin(), want.end(), [&](uint32_t a, uint32_t b) { return Q.cls[a].seq < Q.cls[b].seq; });
+  Q.sort_by_seq(wide);
+  Q.destroy();
+  if (wide != want) return why = "sort_by_seq: not the creation order of a sparse input", n_ops - 1;
   return n_ops;
 }
 
@@ -180,10 +210,27 @@ uint32_t index_stress(uint64_t seed, uint32_t n_ops, std::string& why) {
   const uint64_t keys = 1 + n_ops / 3;
   for (uint32_t op = 0; op < n_ops; op++) {
     const uint64_t k = (rng() % keys) * 0x9E3779B97F4A7C15ull;  // clustered home buckets after hashing
-    if (rng() % 3) {
+    const uint32_t r = (uint32_t)(rng() % 6);
+    if (r < 3) {
       const uint32_t v = (uint32_t)(rng() % 1000000);
       ix.set(k, v);
       m[k] = v;
+    } else if (r == 3) {  // insert only if absent: returns what was there
+      const uint32_t v = (uint32_t)(rng() % 1000000);
+      auto it = m.find(k);
+      const uint32_t had = it == m.end() ? kNone : it->second;
+      if (ix.insert_if_absent(k, v) != had) return why = "fingerprint index insert_if_absent differs", op;
+      if (had == kNone) m[k] = v;
+    } else if (r == 4) {  // replace or drop the value if it is the expected one
+      auto it = m.find(k);
+      const uint32_t had = it == m.end() ? kNone : it->second;
+      const uint32_t expect = rng() % 2 && had != kNone ? had : (uint32_t)(rng() % 1000000);
+      const uint32_t next = rng() % 2 ? kNone : (uint32_t)(rng() % 1000000);
+      if (ix.pop_head(k, expect, next) != had) return why = "fingerprint index pop_head differs", op;
+      if (had != kNone && had == expect) {
+        if (next == kNone) m.erase(k);
+        else m[k] = next;
+      }
     } else {
       ix.erase(k);
       m.erase(k);
