@@ -239,6 +239,27 @@ def test_f32_mlp_two_k_chunks(sage_ctx_factory, torch_cuda):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("W,L", [(128, 3), (16384, 1)])
+def test_f32_mlp_width_limits(sage_ctx_factory, torch_cuda, W, L):
+    """The narrowest FP32 layer (width 128: a 32-wide quarter of K per wave,
+    8 of its 64 lanes loading) and the widest (16384: rows of 64 KiB, eight
+    K chunks), 5 and 11 rows, batched and alone, against the float64 oracle
+    and each other."""
+    from paper_2404_14691_amd import sage as S
+    ctx = sage_ctx_factory(pool_budget_bytes=(2 << 30))
+    rng = np.random.default_rng(W + L)
+    w = (rng.standard_normal((L, W, W), dtype=np.float32) / np.float32(np.sqrt(W)))
+    fn = S.fn_register(ctx, S.mlp_desc(S.SAGE_MLP_F32, L, W), [S.make_blob(w.reshape(-1))])
+    xs = [rng.standard_normal((b, W), dtype=np.float32) for b in (5, 11)]
+    ys = _run(S, ctx, fn, xs, W)
+    for x, y in zip(xs, ys):
+        assert OM.normwise_error(y, OM.mlp_forward(x, w.astype(np.float64))) <= F32_TOL
+    solo = _run(S, ctx, fn, xs, W, batch_call=False)
+    for a, b in zip(ys, solo):
+        assert np.array_equal(a, b)
+    S.fn_unregister(ctx, fn)
+
+
 def test_f32_mlp_full_size_sixteen_invocations(sage_ctx_factory, torch_cuda):
     """2-layer FP32 MLP of width 2048, 16 sequential invocations of 8 rows,
     each with its own input: every output element vs the float64 oracle."""
