@@ -131,6 +131,29 @@ def test_bf16_every_tile_shape_same_bits(sage_ctx_factory, torch_cuda, monkeypat
                 assert np.array_equal(a, b), tile
 
 
+@pytest.mark.parametrize("width,layers", [(128, 3), (8192, 1)])
+def test_bf16_mlp_width_limits(sage_ctx_factory, torch_cuda, width, layers):
+    """The narrowest BF16 layer (width 128: only the shapes at most 128 wide
+    fit; 3 layers are 96 KiB, so the blob ends in a partial block) and a wide
+    one (8192: a K walk of 256 slices, 128 MiB per layer), 5 and 11 rows
+    batched and alone, against the float64 oracle and each other."""
+    from paper_2404_14691_amd import sage as S
+    ctx = sage_ctx_factory(pool_budget_bytes=(1 << 30))
+    rng = np.random.default_rng(width)
+    blob = synth.f32_to_bf16_bits(rng.standard_normal((layers, width, width), dtype=np.float32)
+                                  / np.float32(np.sqrt(width))).reshape(-1)
+    fn = S.fn_register(ctx, S.mlp_desc(S.SAGE_MLP_BF16, layers, width), [S.make_blob(blob)])
+    xs = [synth.bf16_inputs(b, width, width, i) for i, b in enumerate((5, 11))]
+    ys = _run(S, ctx, fn, xs, width)
+    W = OM.bf16_to_f64(blob).reshape(layers, width, width)
+    for x, y in zip(xs, ys):
+        assert OM.normwise_error(y, OM.mlp_forward(OM.bf16_to_f64(x), W)) <= BF16_TOL
+    solo = _run(S, ctx, fn, xs, width, batch_call=False)
+    for a, b in zip(ys, solo):
+        assert np.array_equal(a, b)
+    S.fn_unregister(ctx, fn)
+
+
 def test_bf16_permutation_weights_exact(sage_ctx_factory, torch_cuda):
     """Permutation-matrix weights: every output is one input value, passed
     through ReLU: the block-table indexing and the MFMA fragment layout must
