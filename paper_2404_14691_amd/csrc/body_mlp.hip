@@ -710,7 +710,8 @@ __device__ __forceinline__ float lane_xor(float x, int m, uint32_t lane) {
 // CW partial sums with fmaf in k order.  The lanes' sums are combined by a
 // halving exchange (partners l ^ 1, l ^ 2, l ^ 8, l ^ 4, l ^ 16, l ^ 32: each
 // step a lane keeps half of its values and adds its partner's copy of that
-// half), the waves' in LDS in wave order.  The order depends only on K, not on the rows of the launch.
+// half), the waves' in LDS in wave order.  The order depends only on K,
+// not on the rows of the launch.
 template <int CW, bool ONE>
 __device__ __forceinline__ void mlp_f32_ks_body(const GemmHdr* __restrict__ hdr, const GemmGroup* __restrict__ groups,
                                                 const LayerArgs& la, float (*red)[8 * CW], const uint64_t* wtab1,
