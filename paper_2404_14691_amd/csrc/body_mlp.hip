@@ -728,21 +728,32 @@ __device__ __forceinline__ void mlp_f32_ks_body(const GemmHdr* __restrict__ hdr,
     else gr = groups[find_group(groups, hdr->n_groups, tile)];
     const uint32_t n = (tile - gr.tile_start) * CW;
     const uint64_t* wtab = reinterpret_cast<const uint64_t*>(gr.wtab);
+    // the block-table entries of the CW weight rows: every load issued
+    // before the first is used (one round trip, not CW)
+    uint64_t went[CW];
+#pragma unroll
+    for (int c = 0; c < CW; c++) went[c] = wtab[(la.w_off + (uint64_t)(n + c) * K * 4) >> kBlockShift];
     const float* wr[CW];
 #pragma unroll
-    for (int c = 0; c < CW; c++) {
-      const uint64_t off = la.w_off + (uint64_t)(n + c) * K * 4;
-      wr[c] = reinterpret_cast<const float*>(wtab[off >> kBlockShift] + (off & (kBlock - 1)));
-    }
+    for (int c = 0; c < CW; c++)
+      wr[c] = reinterpret_cast<const float*>(went[c] + ((la.w_off + (uint64_t)(n + c) * K * 4) & (kBlock - 1)));
     for (uint32_t r0 = 0; r0 < gr.m; r0 += 8) {
       const uint32_t nr = gr.m - r0 < 8 ? gr.m - r0 : 8;
-      // rows past the group's end read its first row of the block (not stored)
+      // rows past the group's end read its first row of the block (not
+      // stored); row-table entries, like the block-table ones, all go out
+      // before the first is used
       const float* ar[8];
+      if (la.a_tab) {
+        uint64_t rent[8];
 #pragma unroll
-      for (int i = 0; i < 8; i++) {
-        const uint32_t r = gr.row0 + r0 + ((uint32_t)i < nr ? i : 0);
-        ar[i] = la.a_tab ? reinterpret_cast<const float*>(la.a_tab[r])
-                         : reinterpret_cast<const float*>(la.a_base + (uint64_t)r * K * 4);
+        for (int i = 0; i < 8; i++) rent[i] = la.a_tab[gr.row0 + r0 + ((uint32_t)i < nr ? i : 0)];
+#pragma unroll
+        for (int i = 0; i < 8; i++) ar[i] = reinterpret_cast<const float*>(rent[i]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; i++)
+          ar[i] = reinterpret_cast<const float*>(la.a_base +
+                                                 (uint64_t)(gr.row0 + r0 + ((uint32_t)i < nr ? i : 0)) * K * 4);
       }
       float acc[8][CW];
 #pragma unroll
