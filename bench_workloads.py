@@ -102,6 +102,7 @@ def batching(S, torch, log, steps=10, warmup=2):
         el = time.perf_counter() - t0
         S.sage_timing_enable(ctx, False)
         g_ms, g_n = S.sage_timing_get(ctx, "ggemm_bf16")
+        plan = S.sage_last_launch(ctx)
         t0 = time.perf_counter()
         pres = [plain(pctx)]
         torch.cuda.synchronize()
@@ -124,8 +125,8 @@ def batching(S, torch, log, steps=10, warmup=2):
                  plain={"value": round(256 / pel, 2), "ms_per_step": round(pel * 1e3, 2)},
                  speedup_vs_plain=round(value / (256 / pel), 2),
                  roofline={"bound": "mfma", "achieved": round(ach, 2), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
-                           "frac": round(ach / BF16_PEAK_TFLOPS, 4), "traffic": None, "kernel": "ggemm_bf16",
-                           "avg_launch_ms": round(avg, 5)})
+                           "frac": round(ach / BF16_PEAK_TFLOPS, 4), "traffic": None,
+                           "kernel": "grouped BF16 GEMM layer: " + plan, "avg_launch_ms": round(avg, 5)})
 
 
 # ---------------------------------------------------------------- stencil
